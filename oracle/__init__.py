@@ -1,0 +1,105 @@
+"""CPU oracle (test infrastructure only).
+
+Plain C11 + pthreads in ``wn_oracle.c``; this module compiles it with gcc
+and exposes it through ctypes.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import it.  It shares no code with the HIP
+library and does not import the ``paper_2510_25159_amd`` package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["wn_oracle.c", "wn_oracle_core.inc", "wn_oracle_periodic.inc"]
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no HIP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp,
+               os.path.join(_HERE, "wn_oracle.c"), "-lpthread", "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.wno_query.restype = ctypes.c_int
+        lib.wno_query.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P, P, P,
+                                  ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P]
+        lib.wno_segment_winding.restype = ctypes.c_double
+        lib.wno_segment_winding.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int32, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def query(faces, point_face, u, v, near_tol: float = 1e-9, nthreads: int | None = None,
+          long_double: bool = False):
+    """Winding number and certified near flag for each point.
+
+    ``faces`` is any object with the CSR attributes of
+    ``paper_2510_25159_amd.workloads.Faces``; ``point_face[i]`` names the face
+    of point i.  Returns (omega float64 [N], near int8 [N])."""
+    lib = _load()
+    flo = np.ascontiguousarray(faces.face_loop_offsets, dtype=np.int32)
+    lso = np.ascontiguousarray(faces.loop_seg_offsets, dtype=np.int32)
+    sco = np.ascontiguousarray(faces.seg_cp_offsets, dtype=np.int64)
+    cu = np.ascontiguousarray(faces.cp_u, dtype=np.float64)
+    cv = np.ascontiguousarray(faces.cp_v, dtype=np.float64)
+    cw = None if faces.cp_w is None else np.ascontiguousarray(faces.cp_w, dtype=np.float64)
+    dom = np.ascontiguousarray(faces.face_domain, dtype=np.int32)
+    per = np.ascontiguousarray(faces.face_period, dtype=np.float64)
+    pf = np.ascontiguousarray(point_face, dtype=np.int32)
+    pu = np.ascontiguousarray(u, dtype=np.float64)
+    pv = np.ascontiguousarray(v, dtype=np.float64)
+    n = len(pu)
+    out_w = np.empty(n, dtype=np.float64)
+    out_n = np.empty(n, dtype=np.int8)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    st = lib.wno_query(len(flo) - 1, _ptr(flo), len(lso) - 1, _ptr(lso), len(sco) - 1, _ptr(sco), _ptr(cu),
+                       _ptr(cv), _ptr(cw), _ptr(dom), _ptr(per), n, _ptr(pf), _ptr(pu), _ptr(pv),
+                       float(near_tol), int(nthreads), 1 if long_double else 0, _ptr(out_w), _ptr(out_n))
+    if st != 0:
+        raise OracleError(f"oracle returned status {st}")
+    return out_w, out_n
+
+
+def query_faces(faces, queries, **kw):
+    """All points of a ``Queries`` container (grouped by face)."""
+    return query(faces, queries.face_ids(), queries.u, queries.v, **kw)
+
+
+def segment_winding(cp, w, x, y, long_double: bool = False):
+    """Winding number (turns) of one Bezier segment seen from (x, y) and its near flag."""
+    lib = _load()
+    cp = np.asarray(cp, dtype=np.float64)
+    cu = np.ascontiguousarray(cp[:, 0])
+    cv = np.ascontiguousarray(cp[:, 1])
+    cw = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    near = ctypes.c_int32(0)
+    r = lib.wno_segment_winding(_ptr(cu), _ptr(cv), _ptr(cw), len(cp) - 1, float(x), float(y),
+                                1 if long_double else 0, ctypes.byref(near))
+    return r, near.value

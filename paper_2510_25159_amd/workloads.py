@@ -1,0 +1,415 @@
+"""Seeded synthetic inputs: trimmed faces and query points.
+
+This module only *constructs* inputs.  It holds none of the winding-number
+arithmetic (no bounds, no angle sums, no recursion, no lifting): the CPU
+oracle under ``oracle/`` and the HIP library both consume what it returns,
+and neither imports the other.
+
+Shapes follow the workloads of the paper's experiments (Sec. 5): star-shaped
+closed C0 Bezier loops standing in for the Bezier-Guarding closed-loop sets,
+256x256-style uniform query grids, rational weights (App. A.1 treats the
+rational case), and periodic faces whose loops wrap the period cell
+(Sec. 4.3-4.5).  Every array is produced from numpy ``PCG64`` streams keyed
+by ``(seed, face index)`` so a subset of faces can be rebuilt on its own.
+
+Layout (CSR, host numpy arrays):
+
+* ``face_loop_offsets``  int32  [F+1]   faces -> loops
+* ``loop_seg_offsets``   int32  [L+1]   loops -> ordered segments
+* ``seg_cp_offsets``     int64  [S+1]   segments -> control points; degree = count-1
+* ``cp_u, cp_v``         float64 [C]    control points
+* ``cp_w``               float64 [C] or None (non-rational)
+* ``face_domain``        int32  [F]     0 plane, 1 cylinder (periodic in u), 2 torus
+* ``face_period``        float64 [2F]   (T_u, T_v) per face
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from math import comb
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+DOMAIN_PLANE = 0
+DOMAIN_CYLINDER_U = 1
+DOMAIN_TORUS = 2
+
+SEED_C1 = 1
+SEED_C2 = 2
+SEED_C3 = 3
+SEED_C4_TRAIN = 40
+SEED_C4_EVAL = 41
+SEED_C5 = 5
+
+
+@dataclass
+class Faces:
+    face_loop_offsets: np.ndarray
+    loop_seg_offsets: np.ndarray
+    seg_cp_offsets: np.ndarray
+    cp_u: np.ndarray
+    cp_v: np.ndarray
+    cp_w: Optional[np.ndarray]
+    face_domain: np.ndarray
+    face_period: np.ndarray
+
+    @property
+    def num_faces(self) -> int:
+        return len(self.face_loop_offsets) - 1
+
+    @property
+    def num_loops(self) -> int:
+        return len(self.loop_seg_offsets) - 1
+
+    @property
+    def num_segments(self) -> int:
+        return len(self.seg_cp_offsets) - 1
+
+    @property
+    def num_cps(self) -> int:
+        return len(self.cp_u)
+
+    def face_segment_counts(self) -> np.ndarray:
+        lo = self.loop_seg_offsets[self.face_loop_offsets[:-1]]
+        hi = self.loop_seg_offsets[self.face_loop_offsets[1:]]
+        return (hi - lo).astype(np.int64)
+
+
+@dataclass
+class Queries:
+    u: np.ndarray
+    v: np.ndarray
+    face_point_offsets: np.ndarray  # int64 [F+1]
+    near_mask: Optional[np.ndarray] = None  # True where the point was placed near a curve
+
+    @property
+    def num_points(self) -> int:
+        return len(self.u)
+
+    def face_ids(self) -> np.ndarray:
+        counts = np.diff(self.face_point_offsets)
+        return np.repeat(np.arange(len(counts), dtype=np.int32), counts)
+
+
+# --------------------------------------------------------------------------
+# loop containers used while building a face
+# --------------------------------------------------------------------------
+@dataclass
+class _Loop:
+    # list of per-segment control point arrays, each [(n+1), 2], and weights [(n+1)] or None
+    cps: List[np.ndarray] = field(default_factory=list)
+    ws: List[Optional[np.ndarray]] = field(default_factory=list)
+
+
+def _assemble(face_loops: Sequence[Sequence[_Loop]], domains, periods, rational: bool) -> Faces:
+    flo = [0]
+    lso = [0]
+    sco = [0]
+    us, vs, wsl = [], [], []
+    for loops in face_loops:
+        for lp in loops:
+            for cp, w in zip(lp.cps, lp.ws):
+                us.append(cp[:, 0])
+                vs.append(cp[:, 1])
+                if rational:
+                    wsl.append(w if w is not None else np.ones(len(cp)))
+                sco.append(sco[-1] + len(cp))
+            lso.append(lso[-1] + len(lp.cps))
+        flo.append(flo[-1] + len(loops))
+    return Faces(
+        face_loop_offsets=np.asarray(flo, dtype=np.int32),
+        loop_seg_offsets=np.asarray(lso, dtype=np.int32),
+        seg_cp_offsets=np.asarray(sco, dtype=np.int64),
+        cp_u=np.ascontiguousarray(np.concatenate(us)).astype(np.float64),
+        cp_v=np.ascontiguousarray(np.concatenate(vs)).astype(np.float64),
+        cp_w=(np.ascontiguousarray(np.concatenate(wsl)).astype(np.float64) if rational else None),
+        face_domain=np.asarray(domains, dtype=np.int32),
+        face_period=np.asarray(periods, dtype=np.float64).reshape(-1),
+    )
+
+
+def _face_rng(seed: int, face: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, face])))
+
+
+# --------------------------------------------------------------------------
+# star curves r(theta) = rho * (1 + 0.3 * s(theta)/max|s|), s = 8 Fourier modes
+# --------------------------------------------------------------------------
+class StarCurve:
+    """Closed star-shaped curve around ``center`` (counter-clockwise in theta)."""
+
+    def __init__(self, rng: np.random.Generator, rho: float = 1.0, center=(0.0, 0.0), modes: int = 8,
+                 amp: float = 0.3):
+        k = np.arange(1, modes + 1, dtype=np.float64)
+        self.k = k
+        self.a = rng.uniform(-1.0, 1.0, modes) / k
+        self.b = rng.uniform(-1.0, 1.0, modes) / k
+        grid = np.linspace(0.0, 2.0 * np.pi, 4096, endpoint=False)
+        m = np.max(np.abs(self._s(grid)))
+        self.scale = amp / m if m > 0 else 0.0
+        self.rho = float(rho)
+        self.center = np.asarray(center, dtype=np.float64)
+
+    def _s(self, th):
+        th = np.asarray(th, dtype=np.float64)[..., None]
+        return np.sum(self.a * np.cos(self.k * th) + self.b * np.sin(self.k * th), axis=-1)
+
+    def _ds(self, th):
+        th = np.asarray(th, dtype=np.float64)[..., None]
+        return np.sum(self.k * (-self.a * np.sin(self.k * th) + self.b * np.cos(self.k * th)), axis=-1)
+
+    def r(self, th):
+        return self.rho * (1.0 + self.scale * self._s(th))
+
+    def point(self, th):
+        th = np.asarray(th, dtype=np.float64)
+        r = self.r(th)
+        return np.stack([self.center[0] + r * np.cos(th), self.center[1] + r * np.sin(th)], axis=-1)
+
+    def tangent(self, th):
+        th = np.asarray(th, dtype=np.float64)
+        r = self.r(th)
+        dr = self.rho * self.scale * self._ds(th)
+        c, s = np.cos(th), np.sin(th)
+        return np.stack([dr * c - r * s, dr * s + r * c], axis=-1)
+
+    def r_max(self) -> float:
+        return self.rho * (1.0 + self.scale * np.max(np.abs(self._s(np.linspace(0, 2 * np.pi, 4096)))) * 1.001)
+
+
+def hermite_star_loop(curve: StarCurve, nseg: int) -> _Loop:
+    """Closed CCW loop of ``nseg`` cubic Hermite pieces; consecutive pieces share
+    their joint bit-for-bit and the last piece ends exactly at the first point."""
+    th = 2.0 * np.pi * np.arange(nseg + 1) / nseg
+    V = curve.point(th[:-1])
+    T = curve.tangent(th[:-1])
+    dth = 2.0 * np.pi / nseg
+    lp = _Loop()
+    for i in range(nseg):
+        j = (i + 1) % nseg
+        P0, P3 = V[i], V[j]
+        P1 = P0 + (dth / 3.0) * T[i]
+        P2 = P3 - (dth / 3.0) * T[j]
+        lp.cps.append(np.stack([P0, P1, P2, P3]))
+        lp.ws.append(None)
+    return lp
+
+
+def sampled_star_loop(curve: StarCurve, nseg: int, degrees: np.ndarray, weights_rng=None,
+                      wlo: float = 0.5, whi: float = 2.0) -> _Loop:
+    """Closed CCW loop whose segment i has degree ``degrees[i]`` and control points
+    sampled on the star at equally spaced angles inside the segment's wedge."""
+    th = 2.0 * np.pi * np.arange(nseg + 1) / nseg
+    V = curve.point(th[:-1])
+    lp = _Loop()
+    for i in range(nseg):
+        n = int(degrees[i])
+        j = (i + 1) % nseg
+        if n > 1:
+            tt = th[i] + (th[i + 1] - th[i]) * np.arange(1, n) / n
+            inner = curve.point(tt)
+            cp = np.vstack([V[i][None], inner, V[j][None]])
+        else:
+            cp = np.stack([V[i], V[j]])
+        lp.cps.append(cp)
+        lp.ws.append(weights_rng.uniform(wlo, whi, n + 1) if weights_rng is not None else None)
+    return lp
+
+
+def reverse_loop(lp: _Loop) -> _Loop:
+    out = _Loop()
+    for cp, w in zip(reversed(lp.cps), reversed(lp.ws)):
+        out.cps.append(cp[::-1].copy())
+        out.ws.append(None if w is None else w[::-1].copy())
+    return out
+
+
+def eval_rational_bezier(cp: np.ndarray, w: Optional[np.ndarray], t: np.ndarray) -> np.ndarray:
+    """Bernstein-sum evaluation (input placement only)."""
+    n = len(cp) - 1
+    t = np.asarray(t, dtype=np.float64)[..., None]
+    j = np.arange(n + 1)
+    binom = np.array([comb(n, int(i)) for i in j], dtype=np.float64)
+    basis = binom * t ** j * (1.0 - t) ** (n - j)
+    if w is not None:
+        basis = basis * w
+    den = basis.sum(axis=-1, keepdims=True)
+    return (basis @ cp) / den
+
+
+_BINOM = np.array([[comb(n, j) if j <= n else 0 for j in range(6)] for n in range(6)], dtype=np.float64)
+
+
+def _eval_many(loops: Sequence[_Loop], li: np.ndarray, si: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Vectorised Bernstein-sum evaluation of segment ``si`` of loop ``li`` at ``t``."""
+    segs = [(cp, w) for lp in loops for cp, w in zip(lp.cps, lp.ws)]
+    base = np.cumsum([0] + [len(lp.cps) for lp in loops])
+    S = len(segs)
+    P = np.zeros((S, 6, 2))
+    W = np.zeros((S, 6))
+    deg = np.zeros(S, dtype=np.int64)
+    for k, (cp, w) in enumerate(segs):
+        n = len(cp) - 1
+        P[k, : n + 1] = cp
+        W[k, : n + 1] = 1.0 if w is None else w
+        deg[k] = n
+    g = base[li] + si
+    n = deg[g]
+    j = np.arange(6)[None, :]
+    tt = t[:, None]
+    basis = _BINOM[n] * tt ** j * (1.0 - tt) ** np.maximum(n[:, None] - j, 0) * (j <= n[:, None])
+    basis = basis * W[g]
+    den = basis.sum(axis=1, keepdims=True)
+    return np.einsum("nj,njc->nc", basis, P[g]) / den
+
+
+# --------------------------------------------------------------------------
+# Config 1: one planar face, one closed CCW loop of 64 cubic segments
+# --------------------------------------------------------------------------
+def config1_faces(seed: int = SEED_C1, nseg: int = 64) -> Faces:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    curve = StarCurve(rng)
+    lp = hermite_star_loop(curve, nseg)
+    return _assemble([[lp]], [DOMAIN_PLANE], [[0.0, 0.0]], rational=False)
+
+
+def config1_queries(seed: int = SEED_C1, n: int = 65536, half: float = 1.5) -> Queries:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1_000_003])))
+    pts = rng.uniform(-half, half, size=(n, 2))
+    return Queries(u=np.ascontiguousarray(pts[:, 0]), v=np.ascontiguousarray(pts[:, 1]),
+                   face_point_offsets=np.asarray([0, n], dtype=np.int64),
+                   near_mask=np.zeros(n, dtype=bool))
+
+
+def config1(seed: int = SEED_C1):
+    return config1_faces(seed), config1_queries(seed)
+
+
+# --------------------------------------------------------------------------
+# Config 2: batched B-Rep-like planar faces
+# --------------------------------------------------------------------------
+def _loguniform_int(rng, lo, hi):
+    return int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+
+
+def _min_hull_radius(lp: _Loop) -> float:
+    """Smallest distance from the origin to any segment of any control-point pair
+    (a lower bound of the distance from the origin to every control-point hull)."""
+    best = np.inf
+    for cp in lp.cps:
+        m = len(cp)
+        for i in range(m):
+            for j in range(i + 1, m):
+                a, b = cp[i], cp[j]
+                d = b - a
+                L2 = float(d @ d)
+                t = 0.0 if L2 == 0.0 else float(np.clip(-(a @ d) / L2, 0.0, 1.0))
+                p = a + t * d
+                best = min(best, float(np.hypot(p[0], p[1])))
+    return best
+
+
+def config2_face(seed: int, f: int, q_lo: int = 1024, q_hi: int = 65536, near_frac: float = 0.3,
+                 seg_lo: int = 4, seg_hi: int = 256, max_holes: int = 7, near_offset: float = 1e-3):
+    """One face of the batched set: loops (outer first) and its queries."""
+    rng = _face_rng(seed, f)
+    outer_curve = StarCurve(rng, rho=1.0)
+    nseg = _loguniform_int(rng, seg_lo, seg_hi)
+    outer = sampled_star_loop(outer_curve, nseg, rng.integers(1, 6, nseg), weights_rng=rng)
+    loops = [outer]
+    r_safe = min(0.6, 0.95 * _min_hull_radius(outer))
+    K = int(rng.integers(0, max_holes + 1))
+    discs = []
+    for _ in range(K):
+        for _try in range(200):
+            rho = rng.uniform(0.05, 0.15)
+            hc = StarCurve(rng, rho=rho)
+            rmax = hc.r_max()
+            c = rng.uniform(-r_safe, r_safe, 2)
+            if np.hypot(*c) + rmax > r_safe:
+                continue
+            if any(np.hypot(*(c - c2)) <= rmax + r2 for c2, r2 in discs):
+                continue
+            hc.center = c
+            discs.append((c, rmax))
+            ns = _loguniform_int(rng, seg_lo, seg_hi)
+            hole = sampled_star_loop(hc, ns, rng.integers(1, 6, ns), weights_rng=rng)
+            loops.append(reverse_loop(hole))
+            break
+    nq = _loguniform_int(rng, q_lo, q_hi)
+    n_near = int(round(near_frac * nq))
+    pts = rng.uniform(-1.5, 1.5, size=(nq, 2))
+    near = np.zeros(nq, dtype=bool)
+    if n_near > 0:
+        li = rng.integers(0, len(loops), n_near)
+        seg_counts = np.array([len(lp.cps) for lp in loops])
+        si = (rng.uniform(0, 1, n_near) * seg_counts[li]).astype(np.int64)
+        si = np.minimum(si, seg_counts[li] - 1)
+        t = rng.uniform(0, 1, n_near)
+        rad = near_offset * np.sqrt(rng.uniform(0, 1, n_near))
+        phi = rng.uniform(0, 2 * np.pi, n_near)
+        base = _eval_many(loops, li, si, t)
+        pts[:n_near] = base + np.stack([rad * np.cos(phi), rad * np.sin(phi)], axis=-1)
+        near[:n_near] = True
+        perm = rng.permutation(nq)
+        pts = pts[perm]
+        near = near[perm]
+    return loops, pts, near
+
+
+def config2(seed: int = SEED_C2, num_faces: int = 2000, face_ids: Optional[Sequence[int]] = None, **kw):
+    ids = list(range(num_faces)) if face_ids is None else list(face_ids)
+    face_loops, pts_all, near_all, offs = [], [], [], [0]
+    for f in ids:
+        loops, pts, near = config2_face(seed, f, **kw)
+        face_loops.append(loops)
+        pts_all.append(pts)
+        near_all.append(near)
+        offs.append(offs[-1] + len(pts))
+    faces = _assemble(face_loops, [DOMAIN_PLANE] * len(ids), [[0.0, 0.0]] * len(ids), rational=True)
+    P = np.concatenate(pts_all)
+    q = Queries(u=np.ascontiguousarray(P[:, 0]), v=np.ascontiguousarray(P[:, 1]),
+                face_point_offsets=np.asarray(offs, dtype=np.int64), near_mask=np.concatenate(near_all))
+    return faces, q
+
+
+# --------------------------------------------------------------------------
+# helpers for tests
+# --------------------------------------------------------------------------
+def faces_from_loops(face_loops, domains=None, periods=None, rational=None) -> Faces:
+    """Build a Faces container from explicit python loops.
+
+    ``face_loops``: list (faces) of list (loops) of list (segments) of
+    (cps [(n+1),2], weights or None)."""
+    fl = []
+    any_rat = False
+    for loops in face_loops:
+        lps = []
+        for segs in loops:
+            lp = _Loop()
+            for cp, w in segs:
+                lp.cps.append(np.asarray(cp, dtype=np.float64))
+                lp.ws.append(None if w is None else np.asarray(w, dtype=np.float64))
+                any_rat |= w is not None
+            lps.append(lp)
+        fl.append(lps)
+    F = len(fl)
+    domains = [DOMAIN_PLANE] * F if domains is None else domains
+    periods = [[0.0, 0.0]] * F if periods is None else periods
+    return _assemble(fl, domains, periods, rational=any_rat if rational is None else rational)
+
+
+def queries_for_faces(per_face_points: Sequence[np.ndarray]) -> Queries:
+    offs = [0]
+    for p in per_face_points:
+        offs.append(offs[-1] + len(p))
+    P = np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1, 2) for p in per_face_points]) \
+        if per_face_points else np.zeros((0, 2))
+    return Queries(u=np.ascontiguousarray(P[:, 0]), v=np.ascontiguousarray(P[:, 1]),
+                   face_point_offsets=np.asarray(offs, dtype=np.int64))
+
+
+def subset_queries(q: Queries, idx: np.ndarray):
+    """Pick queries ``idx`` (global indices).  Returns (face id per point, u, v)."""
+    fid = q.face_ids()[idx]
+    return fid, q.u[idx].copy(), q.v[idx].copy()
