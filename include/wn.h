@@ -1,0 +1,192 @@
+/* wn.h - batched generalized-winding-number containment queries on trimmed
+ * surfaces, MI355X (gfx950).
+ *
+ * The problem (Sec. 4.1): given a query point x = (u, v) in the parameter
+ * domain of a trimmed surface and the surface's trimming loops (p-curves,
+ * Sec. 3.1) made of (rational) Bezier segments, decide whether x lies in the
+ * trimmed region.  The library computes the generalized winding number
+ * omega(x) = (1/2pi) * integral of d(theta) along the loops (Sec. 3.2) with the
+ * recursive ellipse-bound algorithm (Alg. 1, Sec. 4.1-4.2), lifts loops of
+ * periodic domains to the universal covering space (Sec. 4.3-4.5) and rounds
+ * omega to inside/outside.
+ *
+ * Conventions
+ *  - Every call returns a wn_status; WN_OK is 0.  No C++ exception crosses
+ *    this interface.  Host-side validation errors are reported synchronously
+ *    and leave outputs untouched.
+ *  - "host" pointers are read during the call only; the caller keeps
+ *    ownership.  "device" pointers are HIP device memory owned by the caller
+ *    (for instance torch tensors); the library never frees them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Query work is enqueued on it and is asynchronous: outputs are valid once
+ *    the stream reaches that point.  Only wn_create_faces synchronizes (it
+ *    reads back the covering-space lift of periodic faces).
+ *  - A wn_faces handle is immutable after creation: concurrent wn_query calls
+ *    on different streams with the same handle are safe.  Each call allocates
+ *    its own stream-ordered scratch memory.
+ */
+#ifndef WN_H
+#define WN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WN_OK = 0,
+    WN_E_INVALID = 1,     /* malformed descriptor or argument                  */
+    WN_E_NOMEM = 2,       /* device or host allocation failed                  */
+    WN_E_DEVICE = 3,      /* a HIP call failed                                 */
+    WN_E_TOPOLOGY = 4,    /* periodic loops violate the Proposition of Sec. 4.5 */
+    WN_E_DEPTH = 5,       /* recursion depth bound exceeds the stack cap       */
+    WN_E_UNSUPPORTED = 6  /* option combination not provided                   */
+} wn_status;
+
+/* Parameter domain of a face (Sec. 3.1, Sec. 4.3). */
+typedef enum {
+    WN_DOMAIN_PLANE = 0,      /* simply connected rectangle                  */
+    WN_DOMAIN_CYLINDER_U = 1, /* periodic in u with period T_u (uni-periodic)  */
+    WN_DOMAIN_TORUS = 2       /* periodic in u and v (bi-periodic)             */
+} wn_domain;
+
+/* Arithmetic of the far-field pair test (the recursion is always FP64). */
+typedef enum {
+    WN_PREC_FP64 = 0,  /* every step in FP64                                    */
+    WN_PREC_MIXED = 1  /* FP32 filtered far-field predicates, FP64 where the
+                          filter cannot certify the decision                     */
+} wn_precision;
+
+/* Rounding of omega to a label (Sec. 4.1: "classify based on this value"). */
+typedef enum {
+    WN_RULE_NONZERO = 0,  /* inside iff |omega| > 1/2 */
+    WN_RULE_POSITIVE = 1  /* inside iff omega > 1/2   */
+} wn_rule;
+
+/* How query work is scheduled on the GPU. */
+typedef enum {
+    WN_SCHED_PLAIN = 0,   /* one launch per face, near pairs recursed in line      */
+    WN_SCHED_BATCHED = 1, /* one persistent work-queue launch over all faces;
+                             near pairs compacted into a queue, recursed after    */
+    WN_SCHED_BINNED = 2   /* BATCHED, near queue ordered by predicted depth        */
+} wn_schedule;
+
+/* Output labels written to out_inside. */
+enum {
+    WN_OUTSIDE = 0,
+    WN_INSIDE = 1,
+    WN_ON_BOUNDARY = 2, /* Alg. 1 met an evaluated curve point within eps     */
+    WN_INVALID_POINT = 3 /* non-finite query coordinates                       */
+};
+
+/* Face descriptor: CSR faces -> loops -> segments -> control points.
+ * All pointers are HOST pointers, copied during wn_create_faces. */
+typedef struct {
+    int32_t num_faces, num_loops, num_segments;
+    int64_t num_cps;
+    const int32_t* face_loop_offsets; /* [num_faces+1], loops of face f are [o[f], o[f+1])       */
+    const int32_t* loop_seg_offsets;  /* [num_loops+1], segments of a loop, in path order         */
+    const int64_t* seg_cp_offsets;    /* [num_segments+1], degree = count - 1, 1..5                */
+    const double* cp_u;               /* [num_cps] control point u                                */
+    const double* cp_v;               /* [num_cps] control point v                                */
+    const double* cp_w;               /* [num_cps] weights > 0, or NULL for non-rational curves    */
+    const int32_t* face_domain;       /* [num_faces] wn_domain, or NULL = all planar               */
+    const double* face_period;        /* [2*num_faces] (T_u, T_v); read for periodic faces only    */
+} wn_faces_desc;
+
+typedef struct {
+    double eps;        /* on-boundary tolerance of Alg. 1 (default 1e-10), in [1e-15, 1e-2] */
+    int32_t precision; /* wn_precision (default WN_PREC_FP64)                              */
+    int32_t rule;      /* wn_rule (default WN_RULE_NONZERO)                                 */
+    int32_t schedule;  /* wn_schedule (default WN_SCHED_BATCHED)                            */
+    int32_t stack_cap; /* largest accepted depth bound ceil(log2(B/eps))+3 (default 52, max 52) */
+    int32_t flags;     /* reserved, 0                                                       */
+} wn_options;
+
+/* Query points, grouped by face: the points of face f are
+ * [face_point_offsets[f], face_point_offsets[f+1]). */
+typedef struct {
+    int64_t num_points;
+    const double* u;                       /* device, element i at u[i*stride]                 */
+    const double* v;                       /* device, element i at v[i*stride]                 */
+    int64_t stride;                        /* >= 1; 1 = separate arrays, 2 = interleaved (u,v) */
+    const int64_t* face_point_offsets;     /* device [num_faces+1], non-decreasing, last = num_points */
+    const int64_t* face_point_offsets_host;/* host copy of the same, or NULL (then the plain
+                                              schedule reads the device copy back, synchronously) */
+} wn_points;
+
+typedef struct wn_faces wn_faces; /* opaque; owns all device copies */
+
+/* Per-call overrides and diagnostics (all fields optional: 0/NULL = default). */
+typedef struct {
+    int32_t schedule;        /* -1 = the handle's default, else wn_schedule               */
+    int32_t precision;       /* -1 = the handle's default, else wn_precision              */
+    int32_t rule;            /* -1 = the handle's default, else wn_rule                   */
+    int32_t queries_per_wg;  /* 0 = tuned; else 64, 128 or 256 queries per workgroup       */
+    int32_t queue_policy;    /* 0 = tuned, 1 = persistent workgroups popping an atomic work
+                                queue, 2 = one workgroup per work item (batched schedules)  */
+    int64_t near_capacity;   /* 0 = default (2 * num_points + 65536) near-queue entries    */
+    uint8_t* depth_log;      /* device [num_points * max_segments_per_face] or NULL.  Entry
+                                i * max_segments_per_face + j receives the deepest level Alg. 1
+                                reached for point i against segment j of its face (0 = decided
+                                at the whole segment).  Written by WN_SCHED_PLAIN only.     */
+} wn_query_opts;
+
+/* Fill `opt` with the defaults listed above.  Never fails. */
+void wn_default_options(wn_options* opt);
+void wn_default_query_opts(wn_query_opts* q);
+
+/* Validate `desc` (CSR monotone, degrees 1..5, finite coordinates with
+ * |coordinate| < 1e30, weights > 0, periods > 0 for periodic faces), compute
+ * each segment's derivative bound B (Lemma 1 and App. A.1; the minimum of the
+ * two rational bounds), check the depth bound ceil(log2(B/eps))+3 against
+ * opt->stack_cap (WN_E_DEPTH), pack structure-of-arrays device copies and, for
+ * periodic faces, lift the loops to the covering space and pair them
+ * (Sec. 4.3-4.5; WN_E_TOPOLOGY when the loops of a torus face cannot be split
+ * into A, B, C with |A| = |B|).  `opt` may be NULL (defaults).  On success
+ * *out owns the device data; release it with wn_destroy_faces.  Synchronizes
+ * `stream`. */
+wn_status wn_create_faces(const wn_faces_desc* desc, const wn_options* opt, void* stream, wn_faces** out);
+
+/* omega and label for every query point.  out_winding: device double
+ * [num_points] (NaN for on-boundary and invalid points); out_inside: device
+ * uint8 [num_points], one of WN_OUTSIDE/INSIDE/ON_BOUNDARY/INVALID_POINT.
+ * Either output may be NULL.  Asynchronous on `stream`. */
+wn_status wn_query(const wn_faces* faces, const wn_points* points, double* out_winding, uint8_t* out_inside,
+                   void* stream);
+
+/* wn_query with per-call overrides (`q` may be NULL). */
+wn_status wn_query_ex(const wn_faces* faces, const wn_points* points, double* out_winding, uint8_t* out_inside,
+                      const wn_query_opts* q, void* stream);
+
+/* Release a handle (waits for nothing: the caller must not destroy a handle
+ * that queued work still uses).  NULL is ignored. */
+void wn_destroy_faces(wn_faces* faces);
+
+/* Static text for a status code. */
+const char* wn_status_string(wn_status s);
+
+/* Host-only helpers (no device access; usable without a GPU). */
+
+/* Derivative bound B of one segment (Lemma 1, App. A.1): non-rational
+ * n * max_i |P_i - P_{i-1}|; rational min(n (W/w) max_{i,j} |P_i - P_j|,
+ * n (W/w)^2 max_i |P_i - P_{i-1}|).  cp_w may be NULL.  Returns WN_E_INVALID
+ * for degree outside 1..5 or non-positive weights. */
+wn_status wn_segment_bound(const double* cp_u, const double* cp_v, const double* cp_w, int32_t degree,
+                           double* out_B);
+
+/* Summary of a created handle (host copy of sizes). */
+typedef struct {
+    int32_t num_faces, num_loops, num_segments;
+    int32_t max_segments_per_face;
+    int32_t max_depth_bound;   /* largest ceil(log2(B/eps))+3 over segments */
+    int64_t device_bytes;      /* device memory held by the handle */
+} wn_faces_info;
+wn_status wn_get_faces_info(const wn_faces* faces, wn_faces_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WN_H */

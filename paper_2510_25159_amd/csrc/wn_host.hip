@@ -1,0 +1,410 @@
+// Host side of the winding-number library: validation, per-segment bounds,
+// device packing and query scheduling behind the C ABI of include/wn.h.
+#include "../../include/wn.h"
+#include "wn_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+using namespace wn;
+
+struct wn_faces {
+    int device = 0;
+    void* dmem = nullptr;
+    int64_t dbytes = 0;
+    Segs sg{};
+    FaceTab ft{};
+    int32_t num_faces = 0, num_loops = 0, num_segments = 0;
+    int32_t max_spf = 0, max_depth = 0;
+    double eps = 1e-10, eps2 = 1e-20;
+    int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
+    int cu_count = 0;
+    std::vector<int32_t> h_seg_begin;
+};
+
+namespace {
+
+constexpr int kBinom[kCoef][kCoef] = {{1, 0, 0, 0, 0, 0}, {1, 1, 0, 0, 0, 0},  {1, 2, 1, 0, 0, 0},
+                                      {1, 3, 3, 1, 0, 0}, {1, 4, 6, 4, 1, 0}, {1, 5, 10, 10, 5, 1}};
+
+bool finite_small(double x) { return isfinite(x) && fabs(x) < kCoordLimit; }
+
+wn_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return WN_OK;
+    if (e == hipErrorOutOfMemory) return WN_E_NOMEM;
+    return WN_E_DEVICE;
+}
+
+// Lemma 1 / App. A.1 bound for one segment (no validation).
+double segment_bound(const double* u, const double* v, const double* w, int n) {
+    double maxd = 0.0;  // max_i |P_i - P_{i-1}|
+    for (int i = 1; i <= n; ++i) maxd = std::max(maxd, hypot(u[i] - u[i - 1], v[i] - v[i - 1]));
+    if (!w) return n * maxd;
+    double wmin = w[0], wmax = w[0];
+    for (int i = 1; i <= n; ++i) {
+        wmin = std::min(wmin, w[i]);
+        wmax = std::max(wmax, w[i]);
+    }
+    bool unit = true;
+    for (int i = 0; i <= n; ++i) unit = unit && (w[i] == 1.0);
+    if (unit) return n * maxd;
+    double diam = 0.0;  // max_{i,j} |P_i - P_j|
+    for (int i = 0; i <= n; ++i)
+        for (int j = i + 1; j <= n; ++j) diam = std::max(diam, hypot(u[i] - u[j], v[i] - v[j]));
+    const double r = wmax / wmin;
+    const double b1 = n * r * diam;
+    const double b2 = n * r * r * maxd;
+    // a few ulps of slack for the rounding of the products above
+    return std::min(b1, b2) * (1.0 + 8.0 * 2.220446049250313e-16);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wn_status_string(wn_status s) {
+    switch (s) {
+        case WN_OK: return "ok";
+        case WN_E_INVALID: return "invalid argument or descriptor";
+        case WN_E_NOMEM: return "out of memory";
+        case WN_E_DEVICE: return "HIP device error";
+        case WN_E_TOPOLOGY: return "periodic loops violate the pairing proposition";
+        case WN_E_DEPTH: return "recursion depth bound exceeds the stack cap";
+        case WN_E_UNSUPPORTED: return "unsupported option combination";
+    }
+    return "unknown status";
+}
+
+void wn_default_options(wn_options* opt) {
+    if (!opt) return;
+    opt->eps = 1e-10;
+    opt->precision = WN_PREC_FP64;
+    opt->rule = WN_RULE_NONZERO;
+    opt->schedule = WN_SCHED_BATCHED;
+    opt->stack_cap = kDepthCap;
+    opt->flags = 0;
+}
+
+void wn_default_query_opts(wn_query_opts* q) {
+    if (!q) return;
+    memset(q, 0, sizeof(*q));
+    q->schedule = -1;
+    q->precision = -1;
+    q->rule = -1;
+}
+
+wn_status wn_segment_bound(const double* cp_u, const double* cp_v, const double* cp_w, int32_t degree,
+                           double* out_B) {
+    if (!cp_u || !cp_v || !out_B || degree < 1 || degree > kMaxDeg) return WN_E_INVALID;
+    for (int i = 0; i <= degree; ++i) {
+        if (!finite_small(cp_u[i]) || !finite_small(cp_v[i])) return WN_E_INVALID;
+        if (cp_w && !(cp_w[i] > 0.0 && isfinite(cp_w[i]))) return WN_E_INVALID;
+    }
+    *out_B = segment_bound(cp_u, cp_v, cp_w, degree);
+    return WN_OK;
+}
+
+wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void* stream, wn_faces** out) {
+    if (!d || !out) return WN_E_INVALID;
+    *out = nullptr;
+    wn_options opt;
+    wn_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (!(opt.eps >= 1e-15 && opt.eps <= 1e-2)) return WN_E_INVALID;
+    if (opt.stack_cap < 1 || opt.stack_cap > kDepthCap) return WN_E_INVALID;
+    if (opt.precision < 0 || opt.precision > WN_PREC_MIXED) return WN_E_INVALID;
+    if (opt.rule < 0 || opt.rule > WN_RULE_POSITIVE) return WN_E_INVALID;
+    if (opt.schedule < 0 || opt.schedule > WN_SCHED_BINNED) return WN_E_INVALID;
+    const int32_t F = d->num_faces, L = d->num_loops, S = d->num_segments;
+    if (F < 0 || L < 0 || S < 0) return WN_E_INVALID;
+    if (!d->face_loop_offsets || !d->loop_seg_offsets || !d->seg_cp_offsets) return WN_E_INVALID;
+    if (S > 0 && (!d->cp_u || !d->cp_v)) return WN_E_INVALID;
+    // CSR structure
+    if (d->face_loop_offsets[0] != 0 || d->face_loop_offsets[F] != L) return WN_E_INVALID;
+    for (int32_t f = 0; f < F; ++f)
+        if (d->face_loop_offsets[f + 1] < d->face_loop_offsets[f]) return WN_E_INVALID;
+    if (d->loop_seg_offsets[0] != 0 || d->loop_seg_offsets[L] != S) return WN_E_INVALID;
+    for (int32_t l = 0; l < L; ++l)
+        if (d->loop_seg_offsets[l + 1] < d->loop_seg_offsets[l]) return WN_E_INVALID;
+    if (d->seg_cp_offsets[0] != 0 || d->seg_cp_offsets[S] != d->num_cps) return WN_E_INVALID;
+    for (int32_t s = 0; s < S; ++s) {
+        const int64_t n = d->seg_cp_offsets[s + 1] - d->seg_cp_offsets[s] - 1;
+        if (n < 1 || n > kMaxDeg) return WN_E_INVALID;
+    }
+    for (int64_t i = 0; i < d->num_cps; ++i) {
+        if (!finite_small(d->cp_u[i]) || !finite_small(d->cp_v[i])) return WN_E_INVALID;
+        if (d->cp_w && !(d->cp_w[i] > 0.0 && isfinite(d->cp_w[i]) && d->cp_w[i] < 1e100)) return WN_E_INVALID;
+    }
+    for (int32_t f = 0; f < F; ++f) {
+        const int dom = d->face_domain ? d->face_domain[f] : WN_DOMAIN_PLANE;
+        if (dom != WN_DOMAIN_PLANE) return WN_E_UNSUPPORTED;
+    }
+
+    wn_faces* h = new (std::nothrow) wn_faces();
+    if (!h) return WN_E_NOMEM;
+    h->num_faces = F;
+    h->num_loops = L;
+    h->num_segments = S;
+    h->eps = opt.eps;
+    h->eps2 = opt.eps * opt.eps;
+    h->precision = opt.precision;
+    h->rule = opt.rule;
+    h->schedule = opt.schedule;
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+        delete h;
+        return WN_E_DEVICE;
+    }
+
+    // per face: segment range, scale of the rounding margin
+    h->h_seg_begin.resize((size_t)F + 1);
+    std::vector<double> face_scale((size_t)F, 0.0);
+    for (int32_t f = 0; f <= F; ++f) h->h_seg_begin[f] = d->loop_seg_offsets[d->face_loop_offsets[f]];
+    for (int32_t f = 0; f < F; ++f) {
+        const int32_t a = h->h_seg_begin[f], b = h->h_seg_begin[f + 1];
+        h->max_spf = std::max(h->max_spf, b - a);
+        double m = 0.0;
+        for (int64_t i = d->seg_cp_offsets[a]; i < d->seg_cp_offsets[b]; ++i)
+            m = std::max(m, std::max(fabs(d->cp_u[i]), fabs(d->cp_v[i])));
+        face_scale[f] = m;
+    }
+
+    // per segment host arrays
+    std::vector<double> p0x(S), p0y(S), pnx(S), pny(S), hb2(S), Bv(S), eta(S);
+    std::vector<double> coef((size_t)S * kCoef * 4, 0.0);
+    std::vector<uint8_t> deg(S), rat(S);
+    int32_t maxd = 0;
+    for (int32_t f = 0; f < F; ++f) {
+        const double e = 8.0 * 1.1102230246251565e-16 * (1.0 + face_scale[f]);
+        for (int32_t s = h->h_seg_begin[f]; s < h->h_seg_begin[f + 1]; ++s) {
+            const int64_t c0 = d->seg_cp_offsets[s];
+            const int n = (int)(d->seg_cp_offsets[s + 1] - c0 - 1);
+            const double* u = d->cp_u + c0;
+            const double* v = d->cp_v + c0;
+            const double* w = d->cp_w ? d->cp_w + c0 : nullptr;
+            bool is_rat = false;
+            if (w)
+                for (int i = 0; i <= n; ++i) is_rat = is_rat || (w[i] != 1.0);
+            const double B = segment_bound(u, v, is_rat ? w : nullptr, n);
+            // Termination lemma: depth <= ceil(log2(B/eps)) + 2 (+1 for the rounding margins)
+            const int D = B > 0.0 ? (int)ceil(log2(B / opt.eps)) + 3 : 1;
+            maxd = std::max(maxd, D);
+            p0x[s] = u[0];
+            p0y[s] = v[0];
+            pnx[s] = u[n];
+            pny[s] = v[n];
+            Bv[s] = B;
+            eta[s] = e;
+            const double Be = B * (1.0 + kAxisInflate) + e;
+            hb2[s] = 0.5 * Be * Be;
+            deg[s] = (uint8_t)n;
+            rat[s] = is_rat ? 1 : 0;
+            for (int j = 0; j <= n; ++j) {
+                const int i = n - j;
+                const double wi = is_rat ? w[i] : 1.0;
+                const double c = (double)kBinom[n][i] * wi;
+                double* slot = &coef[((size_t)s * kCoef + j) * 4];
+                slot[0] = c * u[i];
+                slot[1] = c * v[i];
+                slot[2] = c;
+                slot[3] = 0.0;
+            }
+        }
+    }
+    h->max_depth = maxd;
+    if (maxd > opt.stack_cap) {
+        delete h;
+        return WN_E_DEPTH;
+    }
+
+    // faces ordered by segment count (largest first) for the work queue
+    std::vector<int32_t> order((size_t)F);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return (h->h_seg_begin[a + 1] - h->h_seg_begin[a]) > (h->h_seg_begin[b + 1] - h->h_seg_begin[b]);
+    });
+
+    // one device allocation, 256-byte aligned sub-buffers
+    struct Part {
+        const void* src;
+        size_t bytes;
+        size_t off;
+    };
+    std::vector<Part> parts;
+    size_t total = 0;
+    auto add = [&](const void* src, size_t bytes) -> size_t {
+        const size_t off = total;
+        parts.push_back({src, bytes, off});
+        total += (bytes + 255) & ~(size_t)255;
+        return off;
+    };
+    const size_t o_p0x = add(p0x.data(), S * 8), o_p0y = add(p0y.data(), S * 8);
+    const size_t o_pnx = add(pnx.data(), S * 8), o_pny = add(pny.data(), S * 8);
+    const size_t o_hb2 = add(hb2.data(), S * 8), o_B = add(Bv.data(), S * 8), o_eta = add(eta.data(), S * 8);
+    const size_t o_coef = add(coef.data(), coef.size() * 8);
+    const size_t o_deg = add(deg.data(), S), o_rat = add(rat.data(), S);
+    const size_t o_sb = add(h->h_seg_begin.data(), ((size_t)F + 1) * 4);
+    const size_t o_ord = add(order.data(), (size_t)F * 4);
+    if (total == 0) total = 256;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&h->dmem, total);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_status(e);
+    }
+    h->dbytes = (int64_t)total;
+    char* base = (char*)h->dmem;
+    for (const Part& p : parts) {
+        if (p.bytes == 0) continue;
+        e = hipMemcpyAsync(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(h->dmem);
+        delete h;
+        return hip_status(e);
+    }
+    h->sg.p0x = (const double*)(base + o_p0x);
+    h->sg.p0y = (const double*)(base + o_p0y);
+    h->sg.pnx = (const double*)(base + o_pnx);
+    h->sg.pny = (const double*)(base + o_pny);
+    h->sg.hb2 = (const double*)(base + o_hb2);
+    h->sg.B = (const double*)(base + o_B);
+    h->sg.eta = (const double*)(base + o_eta);
+    h->sg.coef = (const double*)(base + o_coef);
+    h->sg.deg = (const uint8_t*)(base + o_deg);
+    h->sg.rat = (const uint8_t*)(base + o_rat);
+    h->ft.seg_begin = (const int32_t*)(base + o_sb);
+    h->ft.order = (const int32_t*)(base + o_ord);
+    h->ft.num_faces = F;
+    *out = h;
+    return WN_OK;
+}
+
+void wn_destroy_faces(wn_faces* h) {
+    if (!h) return;
+    if (h->dmem) (void)hipFree(h->dmem);
+    delete h;
+}
+
+wn_status wn_get_faces_info(const wn_faces* h, wn_faces_info* info) {
+    if (!h || !info) return WN_E_INVALID;
+    info->num_faces = h->num_faces;
+    info->num_loops = h->num_loops;
+    info->num_segments = h->num_segments;
+    info->max_segments_per_face = h->max_spf;
+    info->max_depth_bound = h->max_depth;
+    info->device_bytes = h->dbytes;
+    return WN_OK;
+}
+
+static int pick_qpw(int64_t n, int cu) {
+    // enough workgroups to cover every CU a few times before using 4 query
+    // groups per workgroup (segment split over waves otherwise)
+    if (n >= (int64_t)cu * 256 * 4) return 256;
+    if (n >= (int64_t)cu * 128 * 4) return 128;
+    return 64;
+}
+
+wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint8_t* out_lab,
+                      const wn_query_opts* qo, void* stream) {
+    if (!h || !p) return WN_E_INVALID;
+    wn_query_opts q;
+    wn_default_query_opts(&q);
+    if (qo) q = *qo;
+    const int sched = q.schedule >= 0 ? q.schedule : h->schedule;
+    const int prec = q.precision >= 0 ? q.precision : h->precision;
+    const int rule = q.rule >= 0 ? q.rule : h->rule;
+    if (sched > WN_SCHED_BINNED || prec > WN_PREC_MIXED || rule > WN_RULE_POSITIVE) return WN_E_INVALID;
+    if (q.queries_per_wg != 0 && q.queries_per_wg != 64 && q.queries_per_wg != 128 && q.queries_per_wg != 256)
+        return WN_E_INVALID;
+    if (q.queue_policy < 0 || q.queue_policy > 2 || q.near_capacity < 0) return WN_E_INVALID;
+    if (prec == WN_PREC_MIXED || sched == WN_SCHED_BINNED) return WN_E_UNSUPPORTED;
+    if (q.depth_log && sched != WN_SCHED_PLAIN) return WN_E_UNSUPPORTED;
+    const int64_t N = p->num_points;
+    const int32_t F = h->num_faces;
+    if (N < 0 || N >= 0x7fffffffll) return WN_E_INVALID;
+    if (N == 0) return WN_OK;
+    if (!p->u || !p->v || p->stride < 1 || !p->face_point_offsets) return WN_E_INVALID;
+    if (F == 0) return WN_E_INVALID;
+    if (p->face_point_offsets_host) {
+        const int64_t* o = p->face_point_offsets_host;
+        if (o[0] != 0 || o[F] != N) return WN_E_INVALID;
+        for (int32_t f = 0; f < F; ++f)
+            if (o[f + 1] < o[f]) return WN_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const Points pts{p->u, p->v, p->stride, p->face_point_offsets, N};
+    const int qpw = q.queries_per_wg ? q.queries_per_wg : pick_qpw(N, h->cu_count);
+    hipError_t e = hipSuccess;
+
+    if (sched == WN_SCHED_PLAIN) {
+        std::vector<int64_t> offs;
+        const int64_t* ho = p->face_point_offsets_host;
+        if (!ho) {
+            offs.resize((size_t)F + 1);
+            e = hipMemcpyAsync(offs.data(), p->face_point_offsets, offs.size() * 8, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_status(e);
+            if (offs[0] != 0 || offs[F] != N) return WN_E_INVALID;
+            for (int32_t f = 0; f < F; ++f)
+                if (offs[f + 1] < offs[f]) return WN_E_INVALID;
+            ho = offs.data();
+        }
+        const Out out{out_w, out_lab, q.depth_log, h->max_spf, rule};
+        for (int32_t f = 0; f < F && e == hipSuccess; ++f) {
+            const int64_t nf = ho[f + 1] - ho[f];
+            if (nf == 0) continue;
+            e = launch_far(true, qpw, h->sg, h->ft, pts, nullptr, nullptr, nullptr, f, (nf + qpw - 1) / qpw,
+                           NearQueue{}, out, h->eps2, st);
+        }
+        return hip_status(e);
+    }
+
+    // batched: one persistent far launch over all faces, near queue, finalize
+    const int64_t max_items = N / qpw + F + 1;
+    int64_t cap = q.near_capacity > 0 ? q.near_capacity : 2 * N + 65536;
+    cap = std::min<int64_t>(cap, 0xfffffff0ll);
+    size_t total = 0;
+    auto take = [&](size_t bytes) {
+        const size_t off = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return off;
+    };
+    const size_t o_io = take(((size_t)F + 1) * 4), o_im = take((size_t)max_items * 8), o_ct = take(16);
+    const size_t o_nq = take((size_t)cap * 4), o_ns = take((size_t)cap * 4);
+    const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
+    void* scratch = nullptr;
+    e = hipMallocAsync(&scratch, total, st);
+    if (e != hipSuccess) return hip_status(e);
+    char* b = (char*)scratch;
+    int32_t* item_offs = (int32_t*)(b + o_io);
+    int2* item_map = (int2*)(b + o_im);
+    uint32_t* counters = (uint32_t*)(b + o_ct);
+    NearQueue nq{(uint32_t*)(b + o_nq), (uint32_t*)(b + o_ns), counters + 1, (uint32_t)cap};
+    Out out{out_w ? out_w : (double*)(b + o_w), out_lab ? out_lab : (uint8_t*)(b + o_l), nullptr, 0, rule};
+    e = launch_build_items(h->ft, pts, qpw, item_offs, item_map, max_items, counters, st);
+    if (e == hipSuccess) {
+        const bool persistent = q.queue_policy != 2;
+        const int64_t grid = persistent ? (int64_t)h->cu_count * far_blocks_per_cu(false, qpw) : max_items;
+        e = launch_far(false, qpw, h->sg, h->ft, pts, item_offs, item_map, persistent ? counters : nullptr, -1, grid,
+                       nq, out, h->eps2, st);
+    }
+    if (e == hipSuccess) e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * 8, st);
+    if (e == hipSuccess) e = launch_finalize(pts, out, st);
+    const hipError_t e2 = hipFreeAsync(scratch, st);
+    if (e == hipSuccess) e = e2;
+    return hip_status(e);
+}
+
+wn_status wn_query(const wn_faces* h, const wn_points* p, double* out_w, uint8_t* out_lab, void* stream) {
+    return wn_query_ex(h, p, out_w, out_lab, nullptr, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Internal layout shared by the host side (wn_host.hip) and the kernels
+// (wn_kernels.hip) of the winding-number library.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wn {
+
+constexpr int kMaxDeg = 5;
+constexpr int kCoef = kMaxDeg + 1;  // coefficient slots per segment
+constexpr int kWave = 64;
+constexpr int kWG = 256;            // threads per workgroup of the pair kernels
+constexpr int kWavesPerWG = kWG / kWave;
+constexpr int kStackSlots = 8;      // LDS ring slots per lane for pending right end points
+constexpr int kDepthCap = 52;       // dyadic parameters a + 2^-k stay exact in FP64
+constexpr int kSegChunk = kWG;      // segments staged in LDS per chunk
+// Relative inflation of the ellipse axis: the far decision is taken only when
+// it survives rounding (Lemma 1 boundary "<=" counts as inside, so inflating
+// the bound only sends borderline pairs to the recursion).
+constexpr double kAxisInflate = 9.094947017729282e-13;  // 2^-40
+// Coordinates (control points at creation, queries at run time) must stay
+// below this magnitude so that a few chord factors multiplied between two
+// rescalings of the angle accumulator can neither overflow nor underflow.
+constexpr double kCoordLimit = 1e15;
+
+// Per-segment data.  Far-field arrays are structure-of-arrays (coalesced
+// staging into LDS); the recursion coefficients of one segment are contiguous
+// (each near-pair lane gathers a different segment).
+struct Segs {
+    const double* p0x;  // [S] curve start gamma(0)
+    const double* p0y;
+    const double* pnx;  // [S] curve end gamma(1)
+    const double* pny;
+    const double* hb2;  // [S] 0.5 * (B (1 + kAxisInflate) + eta)^2 : root ellipse test
+    const double* B;    // [S] derivative bound (Lemma 1 / App. A.1)
+    const double* eta;  // [S] absolute rounding margin of the ellipse axis
+    const double* coef; // [S][kCoef][4]: slot j = (x, y, w, 0) of C(n, n-j) w_{n-j} P_{n-j}
+    const uint8_t* deg; // [S] degree 1..5
+    const uint8_t* rat; // [S] 1 if any weight != 1
+};
+
+struct FaceTab {
+    const int32_t* seg_begin;  // [F+1] segments of face f are [seg_begin[f], seg_begin[f+1])
+    const int32_t* order;      // [F] faces sorted by segment count, descending
+    int32_t num_faces;
+};
+
+struct Points {
+    const double* u;
+    const double* v;
+    int64_t stride;
+    const int64_t* offs;  // [F+1] device
+    int64_t n;
+};
+
+struct NearQueue {
+    uint32_t* q;       // [cap] query index
+    uint32_t* s;       // [cap] segment index
+    uint32_t* count;   // device counter (may exceed cap: overflow pairs are done in line)
+    uint32_t cap;
+};
+
+struct Out {
+    double* w;      // [N] omega (or angle accumulator in the batched path)
+    uint8_t* lab;   // [N] label (or on-boundary flag in the batched path)
+    uint8_t* depth; // optional depth log
+    int32_t depth_stride;
+    int32_t rule;
+};
+
+}  // namespace wn
+
+// Kernel launchers (wn_kernels.hip).
+namespace wn {
+hipError_t launch_build_items(const FaceTab& ft, const Points& pts, int qpw, int32_t* item_offs, int2* item_map,
+                              int64_t map_cap, uint32_t* counters, hipStream_t st);
+hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
+                      const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
+                      int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
+hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
+                       hipStream_t st);
+hipError_t launch_finalize(const Points& pts, Out out, hipStream_t st);
+int far_blocks_per_cu(bool inline_near, int qpw);
+}  // namespace wn

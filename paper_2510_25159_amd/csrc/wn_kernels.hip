@@ -1,0 +1,524 @@
+// HIP kernels (gfx950) of the winding-number containment library.
+//
+// Method (Alg. 1, Sec. 4.1-4.2): for every (query x, segment gamma) pair,
+//   - if an evaluated curve point is within eps of x: on-boundary;
+//   - else if x is outside the ellipse d(x, gamma(a)) + d(x, gamma(b)) <= B (b - a)
+//     (Lemma 1, Eq. of the sub-segment bound): the sub-segment sweeps the
+//     angle of its chord (Sec. 3.2 eqs. 2-3);
+//   - else split at the midpoint and recurse.
+// omega(x) = (sum of angles) / 2pi over all segments of the face (additivity,
+// Sec. 3.2 eq. 1), rounded to a label (Sec. 4.1).
+//
+// gfx950 realisation.
+//  * Far field: one lane per query, segments streamed through an LDS tile
+//    (uniform-address LDS reads broadcast to the wave).  The ellipse test is
+//    evaluated without square roots:  d1 + d2 > Bk  <=>  R < 0 or r1 r2 > R^2
+//    with R = Bk^2/2 - (r1 + r2)/2, ri = di^2.
+//  * Angle sums: instead of one atan2 per pair, each lane keeps the product
+//    z = prod (dot + i cross) of its chords and an integer K of completed
+//    turns; a chord with angle theta multiplies z and K changes by the sign
+//    rule below, so that sum(theta) = arg(z) + 2 pi K.  One atan2 per query.
+//    Sign rule (s = sign bit of the imaginary part): both factors in the same
+//    closed half plane and the product in the other one => the angle crossed
+//    +-pi: K += s(product) - s(z).  Mixed half planes never cross +-pi.  The
+//    decision uses the stored rounded values, so arg(z) + 2 pi K stays
+//    consistent through rounding (only |sum| error ~ 1 ulp per factor).
+//  * Near pairs: Alg. 1 on an explicit stack.  Nodes are dyadic [a, a + 2^-k];
+//    pending right end points are kept in an LDS ring of kStackSlots slots
+//    per lane; a pending point whose slot was reused is re-evaluated (same
+//    parameter, same code => the same value).
+//  * Curve points: O(n) Bernstein evaluation (Horner in t with powers of
+//    1 - t over pre-scaled coefficients C(n,i) w_i P_i; one reciprocal for
+//    rational segments).
+#include "wn_internal.h"
+
+#include <math.h>
+
+namespace wn {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------------------
+// angle accumulator
+// ---------------------------------------------------------------------------
+struct Turn {
+    double zr, zi;
+    int K;
+};
+
+__device__ __forceinline__ int sign_bit(double x) { return (int)((unsigned)__double2hiint(x) >> 31); }
+
+__device__ __forceinline__ void turn_mul(Turn& t, double wr, double wi) {
+    const double nr = fma(t.zr, wr, -(t.zi * wi));
+    const double ni = fma(t.zr, wi, t.zi * wr);
+    const int sz = sign_bit(t.zi), sw = sign_bit(wi), sn = sign_bit(ni);
+    t.K += (sz == sw) ? (sn - sz) : 0;
+    t.zr = nr;
+    t.zi = ni;
+}
+
+// Rescale z by a power of two (exact) so that products of a few factors can
+// neither overflow nor underflow.
+__device__ __forceinline__ void turn_norm(Turn& t) {
+    int e;
+    (void)frexp(fmax(fabs(t.zr), fabs(t.zi)), &e);
+    t.zr = ldexp(t.zr, -e);
+    t.zi = ldexp(t.zi, -e);
+}
+
+__device__ __forceinline__ double turn_angle(const Turn& t) { return atan2(t.zi, t.zr) + kTwoPi * (double)t.K; }
+
+// ---------------------------------------------------------------------------
+// ellipse test (Lemma 1 / sub-segment bound), square-root free
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool outside_ellipse(double ra, double rb, double hb2) {
+    const double R = fma(-0.5, ra + rb, hb2);
+    return (R < 0.0) || (ra * rb > R * R);
+}
+
+__device__ __forceinline__ double half_axis2(double B, double eta, int k) {
+    const double Bk = fma(ldexp(B, -k), 1.0 + kAxisInflate, eta);
+    return 0.5 * Bk * Bk;
+}
+
+// ---------------------------------------------------------------------------
+// curve evaluation
+// ---------------------------------------------------------------------------
+struct Coef {
+    double x[kCoef], y[kCoef], w[kCoef];
+    int n;
+    bool rat;
+};
+
+__device__ __forceinline__ void load_coef(const Segs& sg, int s, Coef& c) {
+    const double4* cf = reinterpret_cast<const double4*>(sg.coef) + (size_t)s * kCoef;
+#pragma unroll
+    for (int j = 0; j < kCoef; ++j) {
+        const double4 v = cf[j];
+        c.x[j] = v.x;
+        c.y[j] = v.y;
+        c.w[j] = v.z;
+    }
+    c.n = sg.deg[s];
+    c.rat = sg.rat[s] != 0;
+}
+
+// gamma(t) = sum_i C(n,i) w_i P_i t^i (1-t)^(n-i) / sum_i C(n,i) w_i t^i (1-t)^(n-i).
+// Slot j holds index i = n - j, so Horner in t runs j = 0..n with (1-t)^j.
+__device__ __forceinline__ void bez_eval(const Coef& c, double t, double& X, double& Y) {
+    const double s = 1.0 - t;
+    double ax = c.x[0], ay = c.y[0], aw = c.w[0], sp = 1.0;
+#pragma unroll
+    for (int j = 1; j < kCoef; ++j) {
+        if (j <= c.n) {
+            sp *= s;
+            ax = fma(ax, t, c.x[j] * sp);
+            ay = fma(ay, t, c.y[j] * sp);
+            aw = fma(aw, t, c.w[j] * sp);
+        }
+    }
+    if (c.rat) {
+        const double r = 1.0 / aw;
+        X = ax * r;
+        Y = ay * r;
+    } else {
+        X = ax;
+        Y = ay;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// near pair: Alg. 1 on an explicit stack.  The root [0,1] is known to be
+// inside its ellipse and not on the boundary.  Points are kept relative to
+// the query.  `stk` is this lane's slot 0 in LDS (slot stride kWave).
+// Returns the deepest level reached; sets onb on an eps hit.
+// ---------------------------------------------------------------------------
+__device__ int near_pair(Turn& T, const Coef& c, double B, double eta, double pnx, double pny, double qx, double qy,
+                         double ax, double ay, double ra, double bx, double by, double rb, double eps2,
+                         double2* stk, bool& onb) {
+    double a = 0.0;  // left end of the current node, exact dyadic
+    int k = 0;       // level: node = [a, a + 2^-k]
+    uint64_t pend = 0, stored = 0;
+    int maxk = 0;
+    bool inside = true;
+    for (;;) {
+        if (inside) {
+            if (k >= kDepthCap) {
+                onb = true;  // cannot happen for a validated eps (depth bound <= cap)
+                return maxk;
+            }
+            const int k1 = k + 1;
+            const int slot = k1 & (kStackSlots - 1);
+            stk[slot * kWave] = make_double2(bx, by);
+            if (k1 >= kStackSlots) stored &= ~(1ull << (k1 - kStackSlots));
+            stored |= 1ull << k1;
+            pend |= 1ull << k1;
+            double mx, my;
+            bez_eval(c, a + ldexp(1.0, -k1), mx, my);
+            mx -= qx;
+            my -= qy;
+            const double rm = mx * mx + my * my;
+            if (rm < eps2) {
+                onb = true;
+                return k1;
+            }
+            bx = mx;
+            by = my;
+            rb = rm;
+            k = k1;
+            maxk = k1 > maxk ? k1 : maxk;
+        } else {
+            turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
+            if (pend == 0) return maxk;
+            turn_norm(T);
+            const int kk = 63 - __clzll(pend);
+            pend &= ~(1ull << kk);
+            a += ldexp(1.0, -k);
+            ax = bx;
+            ay = by;
+            ra = rb;
+            if (stored & (1ull << kk)) {
+                const double2 p = stk[(kk & (kStackSlots - 1)) * kWave];
+                bx = p.x;
+                by = p.y;
+            } else {
+                const double t = a + ldexp(1.0, -kk);
+                if (t == 1.0) {
+                    bx = pnx;
+                    by = pny;
+                } else {
+                    bez_eval(c, t, bx, by);
+                }
+                bx -= qx;
+                by -= qy;
+            }
+            stored &= ~(1ull << kk);
+            rb = bx * bx + by * by;
+            k = kk;
+        }
+        inside = !outside_ellipse(ra, rb, half_axis2(B, eta, k));
+    }
+}
+
+__device__ __forceinline__ uint8_t classify(double omega, int rule) {
+    if (rule == 1) return omega > 0.5 ? 1 : 0;
+    return fabs(omega) > 0.5 ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// work items: (face, tile of QPW queries), faces in descending segment count
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, int qpw, int32_t* item_offs,
+                                                      int2* item_map, int64_t map_cap, uint32_t* counters) {
+    __shared__ int64_t s_sum[1024];
+    const int tid = threadIdx.x;
+    const int F = ft.num_faces;
+    const int chunk = (F + 1023) / 1024;
+    const int r0 = min(F, tid * chunk), r1 = min(F, r0 + chunk);
+    if (tid < 4) counters[tid] = 0;
+    auto tiles_of = [&](int r) -> int64_t {
+        const int f = ft.order[r];
+        int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+        qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
+        qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+        return (qe - qb + qpw - 1) / qpw;
+    };
+    int64_t local = 0;
+    for (int r = r0; r < r1; ++r) local += tiles_of(r);
+    s_sum[tid] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = tid >= off ? s_sum[tid - off] : 0;
+        __syncthreads();
+        s_sum[tid] += v;
+        __syncthreads();
+    }
+    int64_t base = s_sum[tid] - local;
+    for (int r = r0; r < r1; ++r) {
+        const int64_t t = tiles_of(r);
+        const int64_t b = base < map_cap ? base : map_cap;
+        item_offs[r] = (int32_t)b;
+        const int f = ft.order[r];
+        for (int64_t i = 0; i < t && base + i < map_cap; ++i) item_map[base + i] = make_int2(f, (int)i);
+        base += t;
+    }
+    if (tid == 1023) item_offs[F] = (int32_t)(s_sum[1023] < map_cap ? s_sum[1023] : map_cap);
+}
+
+// ---------------------------------------------------------------------------
+// far-field kernel.  GQ query groups of 64 per workgroup, GS = 4 / GQ waves
+// share one query group and split its segments.
+//   INLINE: near pairs recursed in place; writes final omega and labels.
+//   !INLINE: near pairs appended to the near queue (in place on overflow);
+//            writes the angle sum and on-boundary flags for k_near/k_finalize.
+// Item source: item_counter != nullptr -> persistent loop popping items;
+// else item = blockIdx.x.  single_face >= 0 -> items are the tiles of that face.
+// ---------------------------------------------------------------------------
+template <bool INLINE, int GQ>
+__global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
+                                             const int2* item_map, uint32_t* item_counter, int32_t single_face,
+                                             NearQueue nq, Out out, double eps2) {
+    constexpr int GS = kWavesPerWG / GQ;
+    constexpr int QPW = kWave * GQ;
+    __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
+    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    __shared__ double s_ang[kWavesPerWG][kWave];
+    __shared__ int s_flag[kWavesPerWG][kWave];
+    __shared__ int s_item;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    const int gq = wave / GS, gs = wave % GS;
+    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    const int total = single_face >= 0 ? (int)gridDim.x : item_offs[ft.num_faces];
+
+    for (int iter = 0;; ++iter) {
+        int item;
+        if (item_counter) {
+            __syncthreads();
+            if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
+            __syncthreads();
+            item = s_item;
+        } else {
+            if (iter > 0) break;
+            item = blockIdx.x;
+        }
+        if (item >= total) break;
+        int f, tile;
+        if (single_face >= 0) {
+            f = single_face;
+            tile = item;
+        } else {
+            const int2 m = item_map[item];
+            f = m.x;
+            tile = m.y;
+        }
+        int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+        qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
+        qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+        const int64_t qi = qb + (int64_t)tile * QPW + gq * kWave + lane;
+        const bool active = qi < qe;
+        double qx = 0.0, qy = 0.0;
+        if (active) {
+            qx = pts.u[qi * pts.stride];
+            qy = pts.v[qi * pts.stride];
+        }
+        const bool valid = active && fabs(qx) < kCoordLimit && fabs(qy) < kCoordLimit;
+        if (!valid) qx = qy = 0.0;
+        Turn T{1.0, 0.0, 0};
+        bool onb = false;
+        const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
+        int cnt = 0;
+        for (int c0 = s0; c0 < s1; c0 += kSegChunk) {
+            __syncthreads();
+            const int sj = c0 + tid;
+            if (sj < s1) {
+                s_p0x[tid] = sg.p0x[sj];
+                s_p0y[tid] = sg.p0y[sj];
+                s_pnx[tid] = sg.pnx[sj];
+                s_pny[tid] = sg.pny[sj];
+                s_hb2[tid] = sg.hb2[sj];
+            }
+            __syncthreads();
+            const int cn = min(kSegChunk, s1 - c0);
+            for (int j = gs; j < cn; j += GS) {
+                const double ax = s_p0x[j] - qx, ay = s_p0y[j] - qy;
+                const double bx = s_pnx[j] - qx, by = s_pny[j] - qy;
+                const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
+                const bool work = valid && !onb;
+                if (work && (ra < eps2 || rb < eps2)) onb = true;
+                const bool far = outside_ellipse(ra, rb, s_hb2[j]);
+                if (far) turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
+                bool need = work && !onb && !far;
+                int depth = 0;
+                if constexpr (!INLINE) {
+                    const uint64_t m = __ballot(need);
+                    if (m) {
+                        const int leader = __ffsll((unsigned long long)m) - 1;
+                        uint32_t base = 0;
+                        if (lane == leader) base = atomicAdd(nq.count, (uint32_t)__popcll(m));
+                        base = __shfl(base, leader);
+                        const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                        if (need && base + rank < nq.cap) {
+                            nq.q[base + rank] = (uint32_t)qi;
+                            nq.s[base + rank] = (uint32_t)(c0 + j);
+                            need = false;
+                        }
+                    }
+                }
+                if (need) {  // INLINE, or queue overflow
+                    const int s = c0 + j;
+                    Coef c;
+                    load_coef(sg, s, c);
+                    depth = near_pair(T, c, sg.B[s], sg.eta[s], s_pnx[j], s_pny[j], qx, qy, ax, ay, ra, bx, by, rb,
+                                      eps2, stk, onb);
+                }
+                if (INLINE && out.depth && active)
+                    out.depth[qi * (int64_t)out.depth_stride + (c0 + j - s0)] = (uint8_t)depth;
+                if ((++cnt & 3) == 0) turn_norm(T);
+            }
+        }
+        // combine the GS partial sums of each query group
+        double ang = turn_angle(T);
+        if constexpr (GS > 1) {
+            s_ang[wave][lane] = ang;
+            s_flag[wave][lane] = onb ? 1 : 0;
+            __syncthreads();
+            if (gs == 0) {
+#pragma unroll
+                for (int g = 1; g < GS; ++g) {
+                    ang += s_ang[wave + g][lane];
+                    onb = onb || s_flag[wave + g][lane];
+                }
+            }
+        }
+        if (gs == 0 && active) {
+            if constexpr (INLINE) {
+                double w;
+                uint8_t lab;
+                if (!valid) {
+                    w = __builtin_nan("");
+                    lab = 3;
+                } else if (onb) {
+                    w = __builtin_nan("");
+                    lab = 2;
+                } else {
+                    w = ang / kTwoPi;
+                    lab = classify(w, out.rule);
+                }
+                if (out.w) out.w[qi] = w;
+                if (out.lab) out.lab[qi] = lab;
+            } else {
+                out.w[qi] = ang;
+                out.lab[qi] = !valid ? 3 : (onb ? 2 : 0);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// near pass: one lane per queued (query, segment) pair
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2) {
+    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    uint32_t n = *nq.count;
+    n = n < nq.cap ? n : nq.cap;
+    for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+        const uint32_t q = nq.q[i];
+        const uint32_t s = nq.s[i];
+        if ((int64_t)q >= pts.n) continue;
+        const double qx = pts.u[(int64_t)q * pts.stride], qy = pts.v[(int64_t)q * pts.stride];
+        const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
+        const double pnx = sg.pnx[s], pny = sg.pny[s];
+        const double bx = pnx - qx, by = pny - qy;
+        Coef c;
+        load_coef(sg, s, c);
+        Turn T{1.0, 0.0, 0};
+        bool onb = false;
+        near_pair(T, c, sg.B[s], sg.eta[s], pnx, pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
+                  eps2, stk, onb);
+        if (onb) {
+            out.lab[q] = 2;
+        } else {
+            unsafeAtomicAdd(&out.w[q], turn_angle(T));
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= pts.n) return;
+    const uint8_t f = out.lab[i];
+    double w = out.w[i];
+    uint8_t lab;
+    if (f == 3) {
+        w = __builtin_nan("");
+        lab = 3;
+    } else if (f == 2) {
+        w = __builtin_nan("");
+        lab = 2;
+    } else {
+        w = w / kTwoPi;
+        lab = classify(w, out.rule);
+    }
+    out.w[i] = w;
+    out.lab[i] = lab;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_build_items(const FaceTab& ft, const Points& pts, int qpw, int32_t* item_offs, int2* item_map,
+                              int64_t map_cap, uint32_t* counters, hipStream_t st) {
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, ft, pts, qpw, item_offs, item_map, map_cap,
+                       counters);
+    return hipGetLastError();
+}
+
+template <bool INLINE>
+static hipError_t launch_far_q(int qpw, dim3 grid, hipStream_t st, const Segs& sg, const FaceTab& ft,
+                               const Points& pts, const int32_t* item_offs, const int2* item_map,
+                               uint32_t* item_counter, int32_t single_face, NearQueue nq, Out out, double eps2) {
+    switch (qpw) {
+        case 64:
+            hipLaunchKernelGGL((k_far<INLINE, 1>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+                               item_counter, single_face, nq, out, eps2);
+            break;
+        case 128:
+            hipLaunchKernelGGL((k_far<INLINE, 2>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+                               item_counter, single_face, nq, out, eps2);
+            break;
+        default:
+            hipLaunchKernelGGL((k_far<INLINE, 4>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+                               item_counter, single_face, nq, out, eps2);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
+                      const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
+                      int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    const dim3 g((unsigned)grid);
+    if (inline_near)
+        return launch_far_q<true>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter, single_face, nq, out,
+                                  eps2);
+    return launch_far_q<false>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter, single_face, nq, out,
+                               eps2);
+}
+
+hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
+                       hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_near, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Points& pts, Out out, hipStream_t st) {
+    if (pts.n <= 0) return hipSuccess;
+    const int64_t g = (pts.n + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWG), 0, st, pts, out);
+    return hipGetLastError();
+}
+
+int far_blocks_per_cu(bool inline_near, int qpw) {
+    int nb = 0;
+    hipError_t e;
+    if (inline_near) {
+        e = qpw == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<true, 1>, kWG, 0)
+            : qpw == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<true, 2>, kWG, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<true, 4>, kWG, 0);
+    } else {
+        e = qpw == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<false, 1>, kWG, 0)
+            : qpw == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<false, 2>, kWG, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<false, 4>, kWG, 0);
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+}  // namespace wn

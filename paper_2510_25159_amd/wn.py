@@ -1,0 +1,216 @@
+"""Python binding of the C ABI in include/wn.h (argument marshalling only).
+
+Every step of the computation runs in the HIP library ``libwn.so``; this
+module only converts numpy / torch buffers into pointers.  It fails loudly
+when the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from .build import LIB
+
+WN_OK, WN_E_INVALID, WN_E_NOMEM, WN_E_DEVICE, WN_E_TOPOLOGY, WN_E_DEPTH, WN_E_UNSUPPORTED = range(7)
+PLANE, CYLINDER_U, TORUS = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+RULE_NONZERO, RULE_POSITIVE = 0, 1
+SCHED_PLAIN, SCHED_BATCHED, SCHED_BINNED = 0, 1, 2
+OUTSIDE, INSIDE, ON_BOUNDARY, INVALID_POINT = 0, 1, 2, 3
+
+EXPORTS = [
+    "wn_default_options", "wn_default_query_opts", "wn_create_faces", "wn_query", "wn_query_ex",
+    "wn_destroy_faces", "wn_status_string", "wn_segment_bound", "wn_get_faces_info",
+]
+
+_P = ctypes.c_void_p
+
+
+class wn_faces_desc(ctypes.Structure):
+    _fields_ = [("num_faces", ctypes.c_int32), ("num_loops", ctypes.c_int32), ("num_segments", ctypes.c_int32),
+                ("num_cps", ctypes.c_int64), ("face_loop_offsets", _P), ("loop_seg_offsets", _P),
+                ("seg_cp_offsets", _P), ("cp_u", _P), ("cp_v", _P), ("cp_w", _P), ("face_domain", _P),
+                ("face_period", _P)]
+
+
+class wn_options(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("stack_cap", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class wn_points(ctypes.Structure):
+    _fields_ = [("num_points", ctypes.c_int64), ("u", _P), ("v", _P), ("stride", ctypes.c_int64),
+                ("face_point_offsets", _P), ("face_point_offsets_host", _P)]
+
+
+class wn_query_opts(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("queries_per_wg", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
+                ("near_capacity", ctypes.c_int64), ("depth_log", _P)]
+
+
+class wn_faces_info(ctypes.Structure):
+    _fields_ = [("num_faces", ctypes.c_int32), ("num_loops", ctypes.c_int32), ("num_segments", ctypes.c_int32),
+                ("max_segments_per_face", ctypes.c_int32), ("max_depth_bound", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class WnError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: status {status} ({status_string(status)})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libwn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"{LIB} is missing: build it with paper_2510_25159_amd.build.build()")
+        L = ctypes.CDLL(LIB)
+        L.wn_status_string.restype = ctypes.c_char_p
+        L.wn_status_string.argtypes = [ctypes.c_int]
+        L.wn_default_options.argtypes = [ctypes.POINTER(wn_options)]
+        L.wn_default_query_opts.argtypes = [ctypes.POINTER(wn_query_opts)]
+        L.wn_create_faces.restype = ctypes.c_int
+        L.wn_create_faces.argtypes = [ctypes.POINTER(wn_faces_desc), ctypes.POINTER(wn_options), _P,
+                                      ctypes.POINTER(_P)]
+        L.wn_query.restype = ctypes.c_int
+        L.wn_query.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, _P]
+        L.wn_query_ex.restype = ctypes.c_int
+        L.wn_query_ex.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.POINTER(wn_query_opts), _P]
+        L.wn_destroy_faces.argtypes = [_P]
+        L.wn_segment_bound.restype = ctypes.c_int
+        L.wn_segment_bound.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.wn_get_faces_info.restype = ctypes.c_int
+        L.wn_get_faces_info.argtypes = [_P, ctypes.POINTER(wn_faces_info)]
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().wn_status_string(int(s)).decode()
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def segment_bound(cp, w=None) -> float:
+    """Derivative bound B of one segment (host computation, no GPU)."""
+    cp = np.asarray(cp, dtype=np.float64)
+    u = np.ascontiguousarray(cp[:, 0])
+    v = np.ascontiguousarray(cp[:, 1])
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    out = ctypes.c_double(0.0)
+    st = lib().wn_segment_bound(_np_ptr(u), _np_ptr(v), _np_ptr(ww), len(cp) - 1, ctypes.byref(out))
+    if st != WN_OK:
+        raise WnError(st, "wn_segment_bound")
+    return out.value
+
+
+def default_options(**kw) -> wn_options:
+    o = wn_options()
+    lib().wn_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class FaceSet:
+    """Owns a ``wn_faces`` handle built from host CSR arrays (see workloads.Faces)."""
+
+    def __init__(self, faces, stream=None, **opts):
+        self._h = None
+        arrs = dict(
+            flo=np.ascontiguousarray(faces.face_loop_offsets, dtype=np.int32),
+            lso=np.ascontiguousarray(faces.loop_seg_offsets, dtype=np.int32),
+            sco=np.ascontiguousarray(faces.seg_cp_offsets, dtype=np.int64),
+            cu=np.ascontiguousarray(faces.cp_u, dtype=np.float64),
+            cv=np.ascontiguousarray(faces.cp_v, dtype=np.float64),
+            cw=None if faces.cp_w is None else np.ascontiguousarray(faces.cp_w, dtype=np.float64),
+            dom=np.ascontiguousarray(faces.face_domain, dtype=np.int32),
+            per=np.ascontiguousarray(faces.face_period, dtype=np.float64),
+        )
+        d = wn_faces_desc(len(arrs["flo"]) - 1, len(arrs["lso"]) - 1, len(arrs["sco"]) - 1, len(arrs["cu"]),
+                          _np_ptr(arrs["flo"]), _np_ptr(arrs["lso"]), _np_ptr(arrs["sco"]), _np_ptr(arrs["cu"]),
+                          _np_ptr(arrs["cv"]), _np_ptr(arrs["cw"]), _np_ptr(arrs["dom"]), _np_ptr(arrs["per"]))
+        o = default_options(**opts)
+        h = _P()
+        st = lib().wn_create_faces(ctypes.byref(d), ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h))
+        if st != WN_OK:
+            raise WnError(st, "wn_create_faces")
+        self._h = h
+        self.num_faces = d.num_faces
+
+    def info(self) -> wn_faces_info:
+        i = wn_faces_info()
+        st = lib().wn_get_faces_info(self._h, ctypes.byref(i))
+        if st != WN_OK:
+            raise WnError(st, "wn_get_faces_info")
+        return i
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().wn_destroy_faces(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, u, v, offsets, offsets_host=None, out_w=None, out_lab=None, *, stride: int = 1,
+              schedule: Optional[int] = None, precision: Optional[int] = None, rule: Optional[int] = None,
+              queries_per_wg: int = 0, queue_policy: int = 0, near_capacity: int = 0, depth_log=None,
+              stream=None):
+        """Run the query on torch CUDA tensors (float64 u, v; int64 offsets).
+
+        Returns (out_w, out_lab) torch tensors (allocated when not given)."""
+        import torch
+
+        n = u.numel() if stride == 1 else u.numel() // stride + (1 if u.numel() % stride else 0)
+        assert u.is_cuda and v.is_cuda and offsets.is_cuda
+        assert u.dtype == torch.float64 and v.dtype == torch.float64 and offsets.dtype == torch.int64
+        if out_w is None:
+            out_w = torch.empty(n, dtype=torch.float64, device=u.device)
+        if out_lab is None:
+            out_lab = torch.empty(n, dtype=torch.uint8, device=u.device)
+        hoffs = None
+        if offsets_host is not None:
+            hoffs = np.ascontiguousarray(offsets_host, dtype=np.int64)
+        p = wn_points(n, u.data_ptr(), v.data_ptr(), stride, offsets.data_ptr(), _np_ptr(hoffs))
+        q = wn_query_opts()
+        lib().wn_default_query_opts(ctypes.byref(q))
+        if schedule is not None:
+            q.schedule = schedule
+        if precision is not None:
+            q.precision = precision
+        if rule is not None:
+            q.rule = rule
+        q.queries_per_wg = queries_per_wg
+        q.queue_policy = queue_policy
+        q.near_capacity = near_capacity
+        q.depth_log = None if depth_log is None else depth_log.data_ptr()
+        st = lib().wn_query_ex(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
+                               _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_query_ex")
+        return out_w, out_lab

@@ -135,8 +135,16 @@ def _face_rng(seed: int, face: int) -> np.random.Generator:
 # --------------------------------------------------------------------------
 # star curves r(theta) = rho * (1 + 0.3 * s(theta)/max|s|), s = 8 Fourier modes
 # --------------------------------------------------------------------------
+_GRID = np.linspace(0.0, 2.0 * np.pi, 4096, endpoint=False)
+_GRID_K = np.arange(1, 9, dtype=np.float64)
+_GRID_COS = np.cos(_GRID[:, None] * _GRID_K)
+_GRID_SIN = np.sin(_GRID[:, None] * _GRID_K)
+
+
 class StarCurve:
-    """Closed star-shaped curve around ``center`` (counter-clockwise in theta)."""
+    """Closed star-shaped curve around ``center`` (counter-clockwise in theta):
+    r(theta) = rho (1 + amp s(theta) / max|s|), s = sum_k a_k cos k theta + b_k sin k theta,
+    a_k, b_k ~ U[-1, 1] / k, the maximum taken over a 4096-point grid."""
 
     def __init__(self, rng: np.random.Generator, rho: float = 1.0, center=(0.0, 0.0), modes: int = 8,
                  amp: float = 0.3):
@@ -144,9 +152,12 @@ class StarCurve:
         self.k = k
         self.a = rng.uniform(-1.0, 1.0, modes) / k
         self.b = rng.uniform(-1.0, 1.0, modes) / k
-        grid = np.linspace(0.0, 2.0 * np.pi, 4096, endpoint=False)
-        m = np.max(np.abs(self._s(grid)))
+        if modes == 8:
+            m = np.max(np.abs(_GRID_COS @ self.a + _GRID_SIN @ self.b))
+        else:
+            m = np.max(np.abs(self._s(_GRID)))
         self.scale = amp / m if m > 0 else 0.0
+        self.amp = amp
         self.rho = float(rho)
         self.center = np.asarray(center, dtype=np.float64)
 
@@ -173,8 +184,10 @@ class StarCurve:
         c, s = np.cos(th), np.sin(th)
         return np.stack([dr * c - r * s, dr * s + r * c], axis=-1)
 
-    def r_max(self) -> float:
-        return self.rho * (1.0 + self.scale * np.max(np.abs(self._s(np.linspace(0, 2 * np.pi, 4096)))) * 1.001)
+    @staticmethod
+    def radius_bound(rho: float, amp: float = 0.3) -> float:
+        """Upper bound of r(theta) (the grid maximum may miss the true one by a little)."""
+        return rho * (1.0 + 1.02 * amp)
 
 
 def hermite_star_loop(curve: StarCurve, nseg: int) -> _Loop:
@@ -198,21 +211,36 @@ def hermite_star_loop(curve: StarCurve, nseg: int) -> _Loop:
 def sampled_star_loop(curve: StarCurve, nseg: int, degrees: np.ndarray, weights_rng=None,
                       wlo: float = 0.5, whi: float = 2.0) -> _Loop:
     """Closed CCW loop whose segment i has degree ``degrees[i]`` and control points
-    sampled on the star at equally spaced angles inside the segment's wedge."""
+    sampled on the star at equally spaced angles inside the segment's wedge; the
+    joint of consecutive segments is shared bit-for-bit."""
     th = 2.0 * np.pi * np.arange(nseg + 1) / nseg
+    degrees = np.asarray(degrees, dtype=np.int64)
+    # all interior parameters at once
+    inner_th = []
+    for i in range(nseg):
+        n = int(degrees[i])
+        inner_th.append(th[i] + (th[i + 1] - th[i]) * np.arange(1, n) / n)
+    inner_all = np.concatenate(inner_th) if nseg else np.zeros(0)
+    P_inner = curve.point(inner_all)
     V = curve.point(th[:-1])
     lp = _Loop()
+    pos = 0
+    wts = weights_rng.uniform(wlo, whi, int(np.sum(degrees + 1))) if weights_rng is not None else None
+    wpos = 0
     for i in range(nseg):
         n = int(degrees[i])
         j = (i + 1) % nseg
-        if n > 1:
-            tt = th[i] + (th[i + 1] - th[i]) * np.arange(1, n) / n
-            inner = curve.point(tt)
-            cp = np.vstack([V[i][None], inner, V[j][None]])
-        else:
-            cp = np.stack([V[i], V[j]])
+        cp = np.empty((n + 1, 2))
+        cp[0] = V[i]
+        cp[1:n] = P_inner[pos:pos + n - 1]
+        cp[n] = V[j]
+        pos += n - 1
         lp.cps.append(cp)
-        lp.ws.append(weights_rng.uniform(wlo, whi, n + 1) if weights_rng is not None else None)
+        if wts is not None:
+            lp.ws.append(wts[wpos:wpos + n + 1])
+            wpos += n + 1
+        else:
+            lp.ws.append(None)
     return lp
 
 
@@ -293,20 +321,22 @@ def _loguniform_int(rng, lo, hi):
 
 
 def _min_hull_radius(lp: _Loop) -> float:
-    """Smallest distance from the origin to any segment of any control-point pair
-    (a lower bound of the distance from the origin to every control-point hull)."""
-    best = np.inf
+    """Smallest distance from the origin to any segment joining two control
+    points of one segment (a lower bound of the distance from the origin to
+    every control-point hull of the loop)."""
+    A, Bp = [], []
     for cp in lp.cps:
         m = len(cp)
-        for i in range(m):
-            for j in range(i + 1, m):
-                a, b = cp[i], cp[j]
-                d = b - a
-                L2 = float(d @ d)
-                t = 0.0 if L2 == 0.0 else float(np.clip(-(a @ d) / L2, 0.0, 1.0))
-                p = a + t * d
-                best = min(best, float(np.hypot(p[0], p[1])))
-    return best
+        ii, jj = np.triu_indices(m, 1)
+        A.append(cp[ii])
+        Bp.append(cp[jj])
+    A = np.vstack(A)
+    Bp = np.vstack(Bp)
+    d = Bp - A
+    L2 = np.einsum("ij,ij->i", d, d)
+    t = np.where(L2 > 0, np.clip(-np.einsum("ij,ij->i", A, d) / np.where(L2 > 0, L2, 1.0), 0.0, 1.0), 0.0)
+    p = A + t[:, None] * d
+    return float(np.min(np.hypot(p[:, 0], p[:, 1])))
 
 
 def config2_face(seed: int, f: int, q_lo: int = 1024, q_hi: int = 65536, near_frac: float = 0.3,
@@ -323,14 +353,13 @@ def config2_face(seed: int, f: int, q_lo: int = 1024, q_hi: int = 65536, near_fr
     for _ in range(K):
         for _try in range(200):
             rho = rng.uniform(0.05, 0.15)
-            hc = StarCurve(rng, rho=rho)
-            rmax = hc.r_max()
+            rmax = StarCurve.radius_bound(rho)
             c = rng.uniform(-r_safe, r_safe, 2)
             if np.hypot(*c) + rmax > r_safe:
                 continue
             if any(np.hypot(*(c - c2)) <= rmax + r2 for c2, r2 in discs):
                 continue
-            hc.center = c
+            hc = StarCurve(rng, rho=rho, center=c)
             discs.append((c, rmax))
             ns = _loguniform_int(rng, seg_lo, seg_hi)
             hole = sampled_star_loop(hc, ns, rng.integers(1, 6, ns), weights_rng=rng)

@@ -1,0 +1,60 @@
+"""Helpers shared by the GPU tests: run the HIP library through its binding
+and compare with the CPU oracle."""
+import numpy as np
+
+FP64_TOL = 1e-12  # |omega_gpu - omega_oracle| bound for FP64 (far from curves)
+
+
+def run_wn(faces, queries, *, offsets_host=True, stride=1, **kw):
+    import torch
+
+    from paper_2510_25159_amd import wn
+
+    fs = kw.pop("faceset", None)
+    if fs is None:
+        fs = wn.FaceSet(faces, **kw.pop("create", {}))
+    dev = torch.device("cuda:0")
+    if stride == 1:
+        u = torch.from_numpy(np.ascontiguousarray(queries.u)).to(dev)
+        v = torch.from_numpy(np.ascontiguousarray(queries.v)).to(dev)
+    else:
+        inter = np.empty(2 * queries.num_points)
+        inter[0::2], inter[1::2] = queries.u, queries.v
+        t = torch.from_numpy(inter).to(dev)
+        u = t  # element i at u[2 i]
+        v = t[1:]  # element i at v[2 i]
+    offs = torch.from_numpy(np.ascontiguousarray(queries.face_point_offsets, dtype=np.int64)).to(dev)
+    if stride != 1:
+        n = queries.num_points
+        out_w = torch.empty(n, dtype=torch.float64, device=dev)
+        out_l = torch.empty(n, dtype=torch.uint8, device=dev)
+        fs.query(u, v, offs, queries.face_point_offsets if offsets_host else None, out_w, out_l, stride=stride, **kw)
+    else:
+        out_w, out_l = fs.query(u, v, offs, queries.face_point_offsets if offsets_host else None, **kw)
+    torch.cuda.synchronize()
+    return out_w.cpu().numpy(), out_l.cpu().numpy()
+
+
+def compare(w_gpu, lab_gpu, w_orc, near_orc, tol=FP64_TOL, rule=0):
+    """Return a dict of parity statistics; raises AssertionError on failure."""
+    w_gpu = np.asarray(w_gpu)
+    lab_gpu = np.asarray(lab_gpu)
+    far = near_orc == 0
+    # on-boundary may only be reported for points the oracle puts within 1e-9 of a curve
+    onb = lab_gpu == 2
+    assert not np.any(onb & far), f"{int(np.sum(onb & far))} on-boundary labels on certified-far points"
+    assert not np.any(lab_gpu == 3), "unexpected invalid labels"
+    if rule == 0:
+        want = (np.abs(w_orc) > 0.5).astype(np.uint8)
+    else:
+        want = (w_orc > 0.5).astype(np.uint8)
+    # ambiguous (omega within 1e-9 of a half integer) points are reported separately
+    amb = np.abs(np.abs(w_orc) - np.round(np.abs(w_orc) - 0.5) - 0.5) < 1e-9
+    cmp = far & ~amb
+    mism = int(np.sum(lab_gpu[cmp] != want[cmp]))
+    err = np.abs(w_gpu[cmp] - w_orc[cmp])
+    maxerr = float(err.max()) if err.size else 0.0
+    assert mism == 0, f"{mism} inside/outside mismatches"
+    assert maxerr <= tol, f"max |domega| = {maxerr:.3e} > {tol:.1e}"
+    return {"compared": int(cmp.sum()), "excluded_near": int((~far).sum()), "ambiguous": int((far & amb).sum()),
+            "mismatches": mism, "max_abs_err": maxerr}

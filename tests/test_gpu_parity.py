@@ -1,0 +1,158 @@
+"""GPU parity: the HIP library (through the C ABI binding) against the CPU
+oracle, element by element on the same seeded inputs.
+
+Bar: inside/outside identical for every point the oracle certifies farther
+than 1e-9 from every curve; |omega_gpu - omega_oracle| <= 1e-12 there (FP64).
+"""
+import numpy as np
+import pytest
+
+from paper_2510_25159_amd import workloads as W
+from tests import curves as C
+from tests.gpu_helpers import compare, run_wn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_25159_amd import wn
+
+    wn.lib()  # fail loudly if the library was not built
+    return torch
+
+
+@pytest.fixture(scope="module")
+def c1(oracle_lib):
+    f, q = W.config1()
+    w, near = oracle_lib.query_faces(f, q)
+    return f, q, w, near
+
+
+@pytest.fixture(scope="module")
+def c2_small(oracle_lib):
+    # 24 faces of the batched set: every degree, rational weights, holes,
+    # ragged query counts (1k..64k, never a multiple of the tile)
+    f, q = W.config2(face_ids=range(24))
+    w, near = oracle_lib.query_faces(f, q)
+    return f, q, w, near
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("qpw", [64, 256])
+def test_config1_parity(torch_cuda, c1, schedule, qpw):
+    f, q, w_o, n_o = c1
+    print(f"config1 schedule={schedule} qpw={qpw}", flush=True)
+    w, lab = run_wn(f, q, schedule=schedule, queries_per_wg=qpw)
+    st = compare(w, lab, w_o, n_o)
+    assert st["compared"] > 65000
+
+
+@pytest.mark.parametrize("schedule,policy", [(0, 0), (1, 1), (1, 2)])
+def test_config2_subset_parity(torch_cuda, c2_small, schedule, policy):
+    f, q, w_o, n_o = c2_small
+    print(f"config2[0:24] schedule={schedule} policy={policy} points={q.num_points}", flush=True)
+    w, lab = run_wn(f, q, schedule=schedule, queue_policy=policy)
+    st = compare(w, lab, w_o, n_o)
+    assert st["compared"] > 0.99 * q.num_points
+
+
+def test_near_queue_overflow_falls_back_in_line(torch_cuda, c2_small):
+    f, q, w_o, n_o = c2_small
+    w, lab = run_wn(f, q, schedule=1, near_capacity=1000)
+    compare(w, lab, w_o, n_o)
+
+
+def test_interleaved_points_and_device_offsets(torch_cuda, c2_small):
+    f, q, w_o, n_o = c2_small
+    w, lab = run_wn(f, q, schedule=0, stride=2, offsets_host=False)
+    compare(w, lab, w_o, n_o)
+    w, lab = run_wn(f, q, schedule=1, stride=2, offsets_host=False)
+    compare(w, lab, w_o, n_o)
+
+
+def test_edge_cases(torch_cuda, oracle_lib):
+    """Empty faces, a face without loops, a single point, degree-1 loops,
+    points on vertices (on-boundary), non-finite and huge points (invalid)."""
+    circ = C.circle_arcs(1.0)
+    sq = C.polygon([[-1, -1], [1, -1], [1, 1], [-1, 1]])
+    faces = W.faces_from_loops([[circ], [], [sq], [circ, C.circle_arcs(0.3, cw=True)], [sq]])
+    rng = np.random.default_rng(0)
+    pts = [rng.uniform(-1.5, 1.5, (5, 2)), rng.uniform(-1, 1, (3, 2)), np.zeros((0, 2)),
+           rng.uniform(-1.5, 1.5, (257, 2)), np.array([[0.25, 0.5]])]
+    q = W.queries_for_faces(pts)
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    for sched in (0, 1):
+        w, lab = run_wn(faces, q, schedule=sched)
+        compare(w, lab, w_o, n_o)
+        assert np.all(w[5:8] == 0.0)  # face without loops
+    # vertices and invalid points on the square face
+    special = np.array([[1.0, 1.0], [-1.0, 1.0], [np.nan, 0.0], [np.inf, 1.0], [2e15, 0.0], [0.0, 0.0]])
+    q2 = W.queries_for_faces([special])
+    f2 = W.faces_from_loops([[sq]])
+    for sched in (0, 1):
+        w, lab = run_wn(f2, q2, schedule=sched)
+        assert list(lab) == [2, 2, 3, 3, 3, 1]
+        assert np.all(np.isnan(w[:5])) and abs(w[5] - 1.0) < 1e-15
+
+
+def test_rule_positive(torch_cuda, oracle_lib):
+    faces = W.faces_from_loops([[C.circle_arcs(1.0, cw=True)]])
+    rng = np.random.default_rng(1)
+    P = rng.uniform(-1.5, 1.5, (1000, 2))
+    q = W.queries_for_faces([P])
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    for sched in (0, 1):
+        w, lab = run_wn(faces, q, schedule=sched, rule=1)
+        compare(w, lab, w_o, n_o, rule=1)
+        assert np.all(lab[np.hypot(P[:, 0], P[:, 1]) < 0.99] == 0)  # omega = -1 is outside under the positive rule
+
+
+def test_near_boundary_points(torch_cuda, oracle_lib):
+    """Points 1e-8..1e-3 from the curve recurse deeply; those within 1e-9 are excluded."""
+    rng = np.random.default_rng(4)
+    faces, _ = W.config2(face_ids=[7])
+    segs = []
+    for s in range(faces.num_segments):
+        a, b = faces.seg_cp_offsets[s], faces.seg_cp_offsets[s + 1]
+        segs.append((np.column_stack([faces.cp_u[a:b], faces.cp_v[a:b]]), faces.cp_w[a:b]))
+    P = []
+    for _ in range(3000):
+        cp, w = segs[rng.integers(len(segs))]
+        t = rng.uniform(0, 1)
+        p = C.eval_curve(cp, w, t)[0]
+        d = C.eval_deriv(cp, w, t)[0]
+        nrm = np.array([-d[1], d[0]]) / np.hypot(*d)
+        P.append(p + 10.0 ** rng.uniform(-11, -3) * rng.choice([-1, 1]) * nrm)
+    q = W.queries_for_faces([np.array(P)])
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    for sched in (0, 1):
+        w, lab = run_wn(faces, q, schedule=sched)
+        st = compare(w, lab, w_o, n_o)
+        assert st["compared"] > 1500
+
+
+def test_config2_full_sampled(torch_cuda, oracle_lib):
+    """Full batched set (2,000 faces, ~31M points) in the launch configuration
+    the benchmark times; sampled points compared with the oracle one by one."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+
+    faces, q = W.config2()
+    print(f"config2 full: {faces.num_segments} segments, {q.num_points} points", flush=True)
+    fs = wn.FaceSet(faces)
+    w, lab = run_wn(faces, q, faceset=fs, schedule=1)
+    rng = np.random.default_rng(22)
+    idx = np.sort(rng.choice(q.num_points, 20000, replace=False))
+    pf, u, v = W.subset_queries(q, idx)
+    w_o, n_o = oracle_lib.query(faces, pf, u, v)
+    st = compare(w[idx], lab[idx], w_o, n_o)
+    print(st, flush=True)
+    # every label is a valid code and no point is left unwritten
+    assert set(np.unique(lab)).issubset({0, 1, 2})
+    assert np.isfinite(w[lab != 2]).all()
