@@ -1,0 +1,185 @@
+"""Benchmark: batched generalized-winding-number containment on one MI355X.
+
+A step is one pass of the whole query path (work-item build, far-field pair
+pass, near-pair recursion pass, finalize) over the batched planar set:
+2,000 faces, 1 outer + 0-7 hole loops, 4-256 segments per loop of degree
+1-5 with rational weights, 1k-64k points per face, 30% of them within 1e-3
+of a curve.  Inputs sit in HBM before the timed region starts.
+
+Prints one JSON line (rank 0).  `value` is point x segment pair evaluations
+per second of the batched schedule; the plain schedule (one launch per face,
+in-line recursion) is reported beside it, together with queries/s, the
+dominant kernel's roofline position (HIP-event durations on the query
+stream) and the CPU oracle's throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "point×segment winding evals/s & queries/s, plain vs batched form, 0 mismatches"
+# Algorithmic FP64 work of one (query, segment) pair at the root of Alg. 1
+# (FMA = 2 flops, sqrt/atan2/compare = 1): two distances (2 x 6), the ellipse
+# comparison (2), the chord angle (cross 3 + dot 3 + atan2 1 + accumulate 1).
+FLOPS_PER_PAIR = 22
+PEAK_FP64_VALU = 78.6e12   # MI355X vector FP64, FLOP/s
+PEAK_HBM = 8.0e12          # B/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--faces", type=int, default=2000, help="faces of the batched set (default: the full set)")
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=200000, help="points of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--schedule", type=int, default=1)
+    ap.add_argument("--qpw", type=int, default=0)
+    ap.add_argument("--policy", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(queries and faces shard trivially; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    faces, q = W.config2(face_ids=range(args.faces))
+    S_f = faces.face_segment_counts()
+    Q_f = np.diff(q.face_point_offsets)
+    pairs = int(np.sum(S_f * Q_f))
+    N = q.num_points
+    log(f"generated {args.faces} faces, {faces.num_segments} segments, {N} points, {pairs:.3e} pairs "
+        f"in {time.time() - t0:.1f}s")
+
+    u = torch.from_numpy(q.u).to(dev)
+    v = torch.from_numpy(q.v).to(dev)
+    offs = torch.from_numpy(q.face_point_offsets).to(dev)
+    out_w = torch.empty(N, dtype=torch.float64, device=dev)
+    out_l = torch.empty(N, dtype=torch.uint8, device=dev)
+    fs = wn.FaceSet(faces)
+    stream = torch.cuda.current_stream()
+    prof = wn.Profile(capacity=8 * (args.steps + args.warmup) + 64)
+
+    def step(schedule, profile=None):
+        fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=schedule, queries_per_wg=args.qpw,
+                 queue_policy=args.policy, profile=profile, stream=stream)
+
+    # warmup
+    for _ in range(args.warmup):
+        step(args.schedule)
+    torch.cuda.synchronize()
+    prof.collect()
+    # timed region (batched schedule): events recorded around each library kernel
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step(args.schedule, prof)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    kern = prof.collect()
+    ms_step = (t2 - t1) * 1e3 / args.steps
+    value = pairs / (ms_step / 1e3)
+    log(f"batched: {ms_step:.3f} ms/step, {value:.3e} evals/s; kernels {kern}")
+    w_b = out_w.cpu().numpy()
+    lab_b = out_l.cpu().numpy()
+
+    # plain schedule beside it (one launch per face, in-line recursion)
+    step(0)
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        step(0)
+    torch.cuda.synchronize()
+    tp2 = time.perf_counter()
+    ms_plain = (tp2 - tp1) * 1e3 / args.plain_steps
+    lab_p = out_l.cpu().numpy()
+    w_p = out_w.cpu().numpy()
+    log(f"plain: {ms_plain:.3f} ms/step, {pairs / (ms_plain / 1e3):.3e} evals/s")
+    plain_agree = bool(np.array_equal(lab_p, lab_b))
+
+    far_launches, far_ms = kern.get("k_far", (0, float("nan")))
+    far_avg_ms = far_ms / max(far_launches, 1)
+    achieved = FLOPS_PER_PAIR * pairs / (far_avg_ms / 1e3)
+    roofline = {"bound": "alu", "kernel": "k_far (batched far-field pair pass)", "achieved": achieved / 1e12,
+                "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                "traffic": None, "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs,
+                "avg_launch_ms": far_avg_ms}
+    kernels = {k: {"launches": n, "avg_ms": t / max(n, 1)} for k, (n, t) in kern.items()}
+
+    # CPU oracle on a bounded sample of the same workload; also the parity check
+    cpu = None
+    mism = None
+    if not args.no_cpu:
+        import oracle
+
+        rng = np.random.default_rng(1234)
+        ns = min(args.cpu_sample, N)
+        idx = np.sort(rng.choice(N, ns, replace=False))
+        pf, su, sv = W.subset_queries(q, idx)
+        cores = min(16, os.cpu_count() or 1)
+        tc = time.perf_counter()
+        w_o, near = oracle.query(faces, pf, su, sv, nthreads=cores)
+        tcpu = time.perf_counter() - tc
+        sample_pairs = int(np.sum(S_f[pf]))
+        cpu = {"value": sample_pairs / tcpu, "unit": "evals/s", "cores": cores, "kind": "oracle",
+               "sample": f"{ns} points drawn uniformly from the timed set ({sample_pairs:.3e} pairs), "
+                         f"{tcpu:.1f} s"}
+        far = near == 0
+        want = (np.abs(w_o) > 0.5).astype(np.uint8)
+        mism = int(np.sum(lab_b[idx][far] != want[far]))
+        maxerr = float(np.max(np.abs(w_b[idx][far] - w_o[far])))
+        log(f"oracle sample: {ns} points in {tcpu:.1f}s on {cores} threads; mismatches {mism}, max err {maxerr:.2e}")
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched planar set: 2000 faces, 1 outer + 0-7 hole loops, 4-256 segments/loop "
+                               "(degree 1-5, rational weights U[0.5,2]), 1k-64k points/face, 30% within 1e-3 "
+                               "of a curve",
+                   "faces": args.faces, "segments": faces.num_segments, "points": N, "pairs": pairs,
+                   "schedule": {0: "plain", 1: "batched"}.get(args.schedule, str(args.schedule)), "eps": 1e-10},
+        "queries_per_s": N / (ms_step / 1e3),
+        "plain": {"ms_per_step": ms_plain, "evals_per_s": pairs / (ms_plain / 1e3),
+                  "queries_per_s": N / (ms_plain / 1e3), "labels_equal_batched": plain_agree},
+        "speedup_batched_vs_plain": ms_plain / ms_step,
+        "mismatches": mism,
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,6 +118,18 @@ typedef struct {
 
 typedef struct wn_faces wn_faces; /* opaque; owns all device copies */
 
+/* Kernel timing: a pool of HIP event pairs recorded on the query stream
+ * around each kernel the library launches (no allocation while recording). */
+typedef struct wn_profile wn_profile;
+enum {
+    WN_KERNEL_ITEMS = 0,
+    WN_KERNEL_FAR = 1,
+    WN_KERNEL_NEAR = 2,
+    WN_KERNEL_FINALIZE = 3,
+    WN_KERNEL_REDO = 4,
+    WN_KERNEL_KINDS = 8
+};
+
 /* Per-call overrides and diagnostics (all fields optional: 0/NULL = default). */
 typedef struct {
     int32_t schedule;        /* -1 = the handle's default, else wn_schedule               */
@@ -126,11 +138,12 @@ typedef struct {
     int32_t queries_per_wg;  /* 0 = tuned; else 64, 128 or 256 queries per workgroup       */
     int32_t queue_policy;    /* 0 = tuned, 1 = persistent workgroups popping an atomic work
                                 queue, 2 = one workgroup per work item (batched schedules)  */
-    int64_t near_capacity;   /* 0 = default (2 * num_points + 65536) near-queue entries    */
+    int64_t near_capacity;   /* 0 = default (8 * num_points + 65536) near-queue entries    */
     uint8_t* depth_log;      /* device [num_points * max_segments_per_face] or NULL.  Entry
                                 i * max_segments_per_face + j receives the deepest level Alg. 1
                                 reached for point i against segment j of its face (0 = decided
                                 at the whole segment).  Written by WN_SCHED_PLAIN only.     */
+    wn_profile* profile;     /* NULL, or a profile that records kernel durations            */
 } wn_query_opts;
 
 /* Fill `opt` with the defaults listed above.  Never fails. */
@@ -175,6 +188,17 @@ const char* wn_status_string(wn_status s);
  * for degree outside 1..5 or non-positive weights. */
 wn_status wn_segment_bound(const double* cp_u, const double* cp_v, const double* cp_w, int32_t degree,
                            double* out_B);
+
+/* Create a profile able to time `capacity` kernel launches (events are
+ * created here, on the current device).  Timing a launch beyond the capacity
+ * is skipped silently. */
+wn_status wn_profile_create(int32_t capacity, wn_profile** out);
+/* Wait for every recorded launch, then report per kernel kind (index
+ * WN_KERNEL_*) the number of timed launches and their summed duration in
+ * milliseconds (arrays of WN_KERNEL_KINDS entries, host).  Also resets the
+ * profile for reuse. */
+wn_status wn_profile_collect(wn_profile* p, int64_t* launches, double* total_ms);
+void wn_profile_destroy(wn_profile* p);
 
 /* Summary of a created handle (host copy of sizes). */
 typedef struct {

@@ -27,7 +27,30 @@ struct wn_faces {
     std::vector<int32_t> h_seg_begin;
 };
 
+struct wn_profile {
+    std::vector<hipEvent_t> ev;  // 2 per slot
+    std::vector<int> kind;
+    int used = 0;
+};
+
 namespace {
+
+// Records an event pair around one launch when a profile with room is given.
+struct ProfScope {
+    wn_profile* p;
+    int slot = -1;
+    hipStream_t st;
+    ProfScope(wn_profile* prof, int k, hipStream_t s) : p(prof), st(s) {
+        if (p && p->used < (int)p->kind.size()) {
+            slot = p->used++;
+            p->kind[slot] = k;
+            (void)hipEventRecord(p->ev[2 * slot], st);
+        }
+    }
+    ~ProfScope() {
+        if (slot >= 0) (void)hipEventRecord(p->ev[2 * slot + 1], st);
+    }
+};
 
 constexpr int kBinom[kCoef][kCoef] = {{1, 0, 0, 0, 0, 0}, {1, 1, 0, 0, 0, 0},  {1, 2, 1, 0, 0, 0},
                                       {1, 3, 3, 1, 0, 0}, {1, 4, 6, 4, 1, 0}, {1, 5, 10, 10, 5, 1}};
@@ -304,6 +327,55 @@ wn_status wn_get_faces_info(const wn_faces* h, wn_faces_info* info) {
     return WN_OK;
 }
 
+wn_status wn_profile_create(int32_t capacity, wn_profile** out) {
+    if (!out || capacity < 1 || capacity > (1 << 20)) return WN_E_INVALID;
+    *out = nullptr;
+    wn_profile* p = new (std::nothrow) wn_profile();
+    if (!p) return WN_E_NOMEM;
+    p->ev.resize((size_t)capacity * 2, nullptr);
+    p->kind.resize((size_t)capacity, 0);
+    for (auto& e : p->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            wn_profile_destroy(p);
+            return WN_E_DEVICE;
+        }
+    }
+    *out = p;
+    return WN_OK;
+}
+
+wn_status wn_profile_collect(wn_profile* p, int64_t* launches, double* total_ms) {
+    if (!p || !launches || !total_ms) return WN_E_INVALID;
+    for (int k = 0; k < WN_KERNEL_KINDS; ++k) {
+        launches[k] = 0;
+        total_ms[k] = 0.0;
+    }
+    wn_status st = WN_OK;
+    for (int i = 0; i < p->used; ++i) {
+        if (hipEventSynchronize(p->ev[2 * i + 1]) != hipSuccess) {
+            st = WN_E_DEVICE;
+            continue;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess) {
+            st = WN_E_DEVICE;
+            continue;
+        }
+        const int k = p->kind[i];
+        launches[k] += 1;
+        total_ms[k] += ms;
+    }
+    p->used = 0;
+    return st;
+}
+
+void wn_profile_destroy(wn_profile* p) {
+    if (!p) return;
+    for (auto& e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete p;
+}
+
 static int pick_qpw(int64_t n, int cu) {
     // enough workgroups to cover every CU a few times before using 4 query
     // groups per workgroup (segment split over waves otherwise)
@@ -361,6 +433,7 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
         for (int32_t f = 0; f < F && e == hipSuccess; ++f) {
             const int64_t nf = ho[f + 1] - ho[f];
             if (nf == 0) continue;
+            ProfScope ps(q.profile, WN_KERNEL_FAR, st);
             e = launch_far(true, qpw, h->sg, h->ft, pts, nullptr, nullptr, nullptr, f, (nf + qpw - 1) / qpw,
                            NearQueue{}, out, h->eps2, st);
         }
@@ -369,8 +442,8 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
 
     // batched: one persistent far launch over all faces, near queue, finalize
     const int64_t max_items = N / qpw + F + 1;
-    int64_t cap = q.near_capacity > 0 ? q.near_capacity : 2 * N + 65536;
-    cap = std::min<int64_t>(cap, 0xfffffff0ll);
+    int64_t cap = q.near_capacity > 0 ? q.near_capacity : 8 * N + 65536;
+    cap = std::min<int64_t>(cap, (int64_t)1 << 34);
     size_t total = 0;
     auto take = [&](size_t bytes) {
         const size_t off = total;
@@ -378,7 +451,7 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
         return off;
     };
     const size_t o_io = take(((size_t)F + 1) * 4), o_im = take((size_t)max_items * 8), o_ct = take(16);
-    const size_t o_nq = take((size_t)cap * 4), o_ns = take((size_t)cap * 4);
+    const size_t o_nq = take((size_t)cap * 8);
     const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
     void* scratch = nullptr;
     e = hipMallocAsync(&scratch, total, st);
@@ -387,17 +460,31 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     int32_t* item_offs = (int32_t*)(b + o_io);
     int2* item_map = (int2*)(b + o_im);
     uint32_t* counters = (uint32_t*)(b + o_ct);
-    NearQueue nq{(uint32_t*)(b + o_nq), (uint32_t*)(b + o_ns), counters + 1, (uint32_t)cap};
+    NearQueue nq{(uint2*)(b + o_nq), (unsigned long long*)(counters + 2), (uint64_t)cap};
     Out out{out_w ? out_w : (double*)(b + o_w), out_lab ? out_lab : (uint8_t*)(b + o_l), nullptr, 0, rule};
-    e = launch_build_items(h->ft, pts, qpw, item_offs, item_map, max_items, counters, st);
+    {
+        ProfScope ps(q.profile, WN_KERNEL_ITEMS, st);
+        e = launch_build_items(h->ft, pts, qpw, item_offs, item_map, max_items, counters, st);
+    }
     if (e == hipSuccess) {
         const bool persistent = q.queue_policy != 2;
         const int64_t grid = persistent ? (int64_t)h->cu_count * far_blocks_per_cu(false, qpw) : max_items;
+        ProfScope ps(q.profile, WN_KERNEL_FAR, st);
         e = launch_far(false, qpw, h->sg, h->ft, pts, item_offs, item_map, persistent ? counters : nullptr, -1, grid,
                        nq, out, h->eps2, st);
     }
-    if (e == hipSuccess) e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * 8, st);
-    if (e == hipSuccess) e = launch_finalize(pts, out, st);
+    if (e == hipSuccess) {
+        ProfScope ps(q.profile, WN_KERNEL_NEAR, st);
+        e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), st);
+    }
+    if (e == hipSuccess) {
+        ProfScope ps(q.profile, WN_KERNEL_FINALIZE, st);
+        e = launch_finalize(pts, out, st);
+    }
+    if (e == hipSuccess) {
+        ProfScope ps(q.profile, WN_KERNEL_REDO, st);
+        e = launch_redo(h->sg, h->ft, pts, out, h->eps2, st);
+    }
     const hipError_t e2 = hipFreeAsync(scratch, st);
     if (e == hipSuccess) e = e2;
     return hip_status(e);

@@ -15,6 +15,7 @@ constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kStackSlots = 8;      // LDS ring slots per lane for pending right end points
 constexpr int kDepthCap = 52;       // dyadic parameters a + 2^-k stay exact in FP64
 constexpr int kSegChunk = kWG;      // segments staged in LDS per chunk
+constexpr int kNearBuf = 256;       // per-wave LDS buffer of near pairs before one queue append
 // Relative inflation of the ellipse axis: the far decision is taken only when
 // it survives rounding (Lemma 1 boundary "<=" counts as inside, so inflating
 // the bound only sends borderline pairs to the recursion).
@@ -55,10 +56,9 @@ struct Points {
 };
 
 struct NearQueue {
-    uint32_t* q;       // [cap] query index
-    uint32_t* s;       // [cap] segment index
-    uint32_t* count;   // device counter (may exceed cap: overflow pairs are done in line)
-    uint32_t cap;
+    uint2* qs;                     // [cap] (query index, segment index)
+    unsigned long long* count;     // device counter (may exceed cap: overflow pairs are done in line)
+    uint64_t cap;
 };
 
 struct Out {
@@ -81,5 +81,7 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
                        hipStream_t st);
 hipError_t launch_finalize(const Points& pts, Out out, hipStream_t st);
+hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, int qpw);
+int near_blocks_per_cu();
 }  // namespace wn

@@ -37,6 +37,7 @@
 namespace wn {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr uint8_t kRedo = 4;  // label placeholder: query must be recomputed in line
 
 // ---------------------------------------------------------------------------
 // angle accumulator
@@ -200,6 +201,38 @@ __device__ int near_pair(Turn& T, const Coef& c, double B, double eta, double pn
     }
 }
 
+// Near pair with all segment data read from global memory.
+__device__ __forceinline__ int near_from_global(Turn& T, const Segs& sg, uint32_t s, double qx, double qy,
+                                                double eps2, double2* stk, bool& onb) {
+    const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
+    const double pnx = sg.pnx[s], pny = sg.pny[s];
+    const double bx = pnx - qx, by = pny - qy;
+    Coef c;
+    load_coef(sg, s, c);
+    return near_pair(T, c, sg.B[s], sg.eta[s], pnx, pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
+                     eps2, stk, onb);
+}
+
+// Append this wave's buffered near pairs to the global queue with one atomic.
+// Returns true for the lanes whose query lost a pair to a full queue (those
+// queries are recomputed in line by k_redo).
+__device__ __forceinline__ bool flush_near(const uint2* buf, int nfill, const NearQueue& nq, int lane, int64_t qi) {
+    if (nfill == 0) return false;
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(nq.count, (unsigned long long)nfill);
+    base = __shfl(base, 0);
+    for (int e = lane; e < nfill; e += kWave)
+        if (base + (unsigned long long)e < nq.cap) nq.qs[base + e] = buf[e];
+    bool lost = false;
+    if (base + (unsigned long long)nfill > nq.cap) {
+        for (int e = 0; e < nfill; ++e)
+            if (base + (unsigned long long)e >= nq.cap && (int64_t)buf[e].x == qi) lost = true;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return lost;
+}
+
 __device__ __forceinline__ uint8_t classify(double omega, int rule) {
     if (rule == 1) return omega > 0.5 ? 1 : 0;
     return fabs(omega) > 0.5 ? 1 : 0;
@@ -215,7 +248,7 @@ __global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, in
     const int F = ft.num_faces;
     const int chunk = (F + 1023) / 1024;
     const int r0 = min(F, tid * chunk), r1 = min(F, r0 + chunk);
-    if (tid < 4) counters[tid] = 0;
+    if (tid < 4) counters[tid] = 0;  // [0] item counter, [2..3] near-queue count (64-bit)
     auto tiles_of = [&](int r) -> int64_t {
         const int f = ft.order[r];
         int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
@@ -235,14 +268,22 @@ __global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, in
     }
     int64_t base = s_sum[tid] - local;
     for (int r = r0; r < r1; ++r) {
-        const int64_t t = tiles_of(r);
-        const int64_t b = base < map_cap ? base : map_cap;
-        item_offs[r] = (int32_t)b;
-        const int f = ft.order[r];
-        for (int64_t i = 0; i < t && base + i < map_cap; ++i) item_map[base + i] = make_int2(f, (int)i);
-        base += t;
+        item_offs[r] = (int32_t)(base < map_cap ? base : map_cap);
+        base += tiles_of(r);
     }
-    if (tid == 1023) item_offs[F] = (int32_t)(s_sum[1023] < map_cap ? s_sum[1023] : map_cap);
+    const int64_t total = s_sum[1023] < map_cap ? s_sum[1023] : map_cap;
+    if (tid == 1023) item_offs[F] = (int32_t)total;
+    __syncthreads();
+    // item i -> (face, tile): last r with item_offs[r] <= i
+    for (int64_t i = tid; i < total; i += 1024) {
+        int lo = 0, hi = F - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_offs[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        item_map[i] = make_int2(ft.order[lo], (int)(i - item_offs[lo]));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -261,16 +302,17 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
     constexpr int GS = kWavesPerWG / GQ;
     constexpr int QPW = kWave * GQ;
     __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
-    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    __shared__ double2 s_stack[INLINE ? kWavesPerWG * kStackSlots * kWave : 1];
     __shared__ double s_ang[kWavesPerWG][kWave];
     __shared__ int s_flag[kWavesPerWG][kWave];
+    __shared__ uint2 s_nbuf[INLINE ? 1 : kWavesPerWG][INLINE ? 1 : kNearBuf];
     __shared__ int s_item;
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
     const int gq = wave / GS, gs = wave % GS;
-    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    double2* stk = INLINE ? s_stack + wave * kStackSlots * kWave + lane : s_stack;
     const int total = single_face >= 0 ? (int)gridDim.x : item_offs[ft.num_faces];
 
     for (int iter = 0;; ++iter) {
@@ -310,6 +352,8 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         bool onb = false;
         const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
         int cnt = 0;
+        int nfill = 0;      // entries in this wave's near-pair buffer (wave-uniform)
+        bool lost = false;  // a near pair of this lane's query did not fit in the queue
         for (int c0 = s0; c0 < s1; c0 += kSegChunk) {
             __syncthreads();
             const int sj = c0 + tid;
@@ -335,19 +379,20 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                 if constexpr (!INLINE) {
                     const uint64_t m = __ballot(need);
                     if (m) {
-                        const int leader = __ffsll((unsigned long long)m) - 1;
-                        uint32_t base = 0;
-                        if (lane == leader) base = atomicAdd(nq.count, (uint32_t)__popcll(m));
-                        base = __shfl(base, leader);
-                        const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                        if (need && base + rank < nq.cap) {
-                            nq.q[base + rank] = (uint32_t)qi;
-                            nq.s[base + rank] = (uint32_t)(c0 + j);
+                        const int cntm = __popcll(m);
+                        if (nfill + cntm > kNearBuf) {
+                            lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
+                            nfill = 0;
+                        }
+                        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                        if (need) {
+                            s_nbuf[wave][nfill + rank] = make_uint2((uint32_t)qi, (uint32_t)(c0 + j));
                             need = false;
                         }
+                        nfill += cntm;
                     }
                 }
-                if (need) {  // INLINE, or queue overflow
+                if (INLINE && need) {
                     const int s = c0 + j;
                     Coef c;
                     load_coef(sg, s, c);
@@ -359,17 +404,19 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                 if ((++cnt & 3) == 0) turn_norm(T);
             }
         }
+        if constexpr (!INLINE) lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
         // combine the GS partial sums of each query group
         double ang = turn_angle(T);
         if constexpr (GS > 1) {
             s_ang[wave][lane] = ang;
-            s_flag[wave][lane] = onb ? 1 : 0;
+            s_flag[wave][lane] = (onb ? 1 : 0) | (lost ? 2 : 0);
             __syncthreads();
             if (gs == 0) {
 #pragma unroll
                 for (int g = 1; g < GS; ++g) {
                     ang += s_ang[wave + g][lane];
-                    onb = onb || s_flag[wave + g][lane];
+                    onb = onb || (s_flag[wave + g][lane] & 1);
+                    lost = lost || (s_flag[wave + g][lane] & 2);
                 }
             }
         }
@@ -391,41 +438,190 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                 if (out.lab) out.lab[qi] = lab;
             } else {
                 out.w[qi] = ang;
-                out.lab[qi] = !valid ? 3 : (onb ? 2 : 0);
+                out.lab[qi] = !valid ? 3 : (onb ? 2 : (lost ? kRedo : 0));
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// near pass: one lane per queued (query, segment) pair
+// near pass.  Each wave owns a contiguous chunk of the queue and keeps all
+// its lanes busy: a lane that finishes its pair takes the next pair of the
+// chunk (wave-local counter, no global atomics).  One node of Alg. 1 per
+// loop trip, so lanes with short and long recursions interleave.
 // ---------------------------------------------------------------------------
+struct NodeState {
+    Coef c;
+    double B, eta, pnx, pny, qx, qy;
+    double a, ax, ay, ra, bx, by, rb;
+    uint64_t pend, stored;
+    int k;
+    bool inside;
+};
+
+__device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_t s, double qx, double qy) {
+    load_coef(sg, s, st.c);
+    st.B = sg.B[s];
+    st.eta = sg.eta[s];
+    st.pnx = sg.pnx[s];
+    st.pny = sg.pny[s];
+    st.qx = qx;
+    st.qy = qy;
+    st.ax = sg.p0x[s] - qx;
+    st.ay = sg.p0y[s] - qy;
+    st.ra = st.ax * st.ax + st.ay * st.ay;
+    st.bx = st.pnx - qx;
+    st.by = st.pny - qy;
+    st.rb = st.bx * st.bx + st.by * st.by;
+    st.a = 0.0;
+    st.k = 0;
+    st.pend = st.stored = 0;
+    st.inside = true;  // queued pairs failed the root ellipse test
+}
+
+// One node of Alg. 1.  Returns true when the pair is finished.
+__device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, double2* stk, bool& onb) {
+    if (st.inside) {
+        if (st.k >= kDepthCap) {
+            onb = true;
+            return true;
+        }
+        const int k1 = st.k + 1;
+        stk[(k1 & (kStackSlots - 1)) * kWave] = make_double2(st.bx, st.by);
+        if (k1 >= kStackSlots) st.stored &= ~(1ull << (k1 - kStackSlots));
+        st.stored |= 1ull << k1;
+        st.pend |= 1ull << k1;
+        double mx, my;
+        bez_eval(st.c, st.a + ldexp(1.0, -k1), mx, my);
+        mx -= st.qx;
+        my -= st.qy;
+        const double rm = mx * mx + my * my;
+        if (rm < eps2) {
+            onb = true;
+            return true;
+        }
+        st.bx = mx;
+        st.by = my;
+        st.rb = rm;
+        st.k = k1;
+    } else {
+        turn_mul(T, st.ax * st.bx + st.ay * st.by, st.ax * st.by - st.ay * st.bx);
+        if (st.pend == 0) return true;
+        turn_norm(T);
+        const int kk = 63 - __clzll(st.pend);
+        st.pend &= ~(1ull << kk);
+        st.a += ldexp(1.0, -st.k);
+        st.ax = st.bx;
+        st.ay = st.by;
+        st.ra = st.rb;
+        if (st.stored & (1ull << kk)) {
+            const double2 p = stk[(kk & (kStackSlots - 1)) * kWave];
+            st.bx = p.x;
+            st.by = p.y;
+        } else {
+            const double t = st.a + ldexp(1.0, -kk);
+            if (t == 1.0) {
+                st.bx = st.pnx;
+                st.by = st.pny;
+            } else {
+                bez_eval(st.c, t, st.bx, st.by);
+            }
+            st.bx -= st.qx;
+            st.by -= st.qy;
+        }
+        st.stored &= ~(1ull << kk);
+        st.rb = st.bx * st.bx + st.by * st.by;
+        st.k = kk;
+    }
+    st.inside = !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k));
+    return false;
+}
+
 __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2) {
     __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     double2* stk = s_stack + wave * kStackSlots * kWave + lane;
-    uint32_t n = *nq.count;
+    unsigned long long n = *nq.count;
     n = n < nq.cap ? n : nq.cap;
-    for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
-        const uint32_t q = nq.q[i];
-        const uint32_t s = nq.s[i];
-        if ((int64_t)q >= pts.n) continue;
-        const double qx = pts.u[(int64_t)q * pts.stride], qy = pts.v[(int64_t)q * pts.stride];
-        const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
-        const double pnx = sg.pnx[s], pny = sg.pny[s];
-        const double bx = pnx - qx, by = pny - qy;
-        Coef c;
-        load_coef(sg, s, c);
-        Turn T{1.0, 0.0, 0};
-        bool onb = false;
-        near_pair(T, c, sg.B[s], sg.eta[s], pnx, pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
-                  eps2, stk, onb);
-        if (onb) {
-            out.lab[q] = 2;
-        } else {
-            unsafeAtomicAdd(&out.w[q], turn_angle(T));
+    const unsigned long long nw = (unsigned long long)gridDim.x * kWavesPerWG;
+    const unsigned long long gw = (unsigned long long)blockIdx.x * kWavesPerWG + wave;
+    const unsigned long long per = (n + nw - 1) / nw;
+    const unsigned long long c_begin = gw * per < n ? gw * per : n;
+    const unsigned long long c_end = c_begin + per < n ? c_begin + per : n;
+    unsigned long long next = c_begin;  // wave-uniform
+    NodeState st;
+    Turn T{1.0, 0.0, 0};
+    bool onb = false, has = false;
+    uint32_t q = 0;
+    for (;;) {
+        const uint64_t idle = __ballot(!has);
+        if (idle && next < c_end) {
+            const unsigned long long rank = (unsigned long long)__popcll(idle & ((1ull << lane) - 1ull));
+            if (!has && next + rank < c_end) {
+                const uint2 e = nq.qs[next + rank];
+                q = e.x;
+                if ((int64_t)q < pts.n) {
+                    const double qx = pts.u[(int64_t)q * pts.stride], qy = pts.v[(int64_t)q * pts.stride];
+                    node_init(st, sg, e.y, qx, qy);
+                    T = Turn{1.0, 0.0, 0};
+                    onb = false;
+                    has = true;
+                }
+            }
+            next += (unsigned long long)__popcll(idle);
         }
+        if (!__any(has)) {
+            if (next >= c_end) break;
+            continue;
+        }
+        if (has && node_step(st, T, eps2, stk, onb)) {
+            if (onb) out.lab[q] = 2;
+            else unsafeAtomicAdd(&out.w[q], turn_angle(T));
+            has = false;
+        }
+    }
+}
+
+// Queries that lost a near pair to a full queue: recompute the whole query
+// in line (one lane per query).  Runs after k_finalize and overwrites.
+__global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, Out out, double eps2) {
+    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= pts.n || out.lab[i] != kRedo) return;
+    // face of point i: last f with offs[f] <= i
+    int lo = 0, hi = ft.num_faces - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pts.offs[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const double qx = pts.u[i * pts.stride], qy = pts.v[i * pts.stride];
+    Turn T{1.0, 0.0, 0};
+    bool onb = false;
+    int cnt = 0;
+    for (int s = ft.seg_begin[lo]; s < ft.seg_begin[lo + 1] && !onb; ++s) {
+        const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
+        const double bx = sg.pnx[s] - qx, by = sg.pny[s] - qy;
+        const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
+        if (ra < eps2 || rb < eps2) {
+            onb = true;
+            break;
+        }
+        if (outside_ellipse(ra, rb, sg.hb2[s])) turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
+        else (void)near_from_global(T, sg, (uint32_t)s, qx, qy, eps2, stk, onb);
+        if ((++cnt & 3) == 0) turn_norm(T);
+    }
+    if (onb) {
+        out.w[i] = __builtin_nan("");
+        out.lab[i] = 2;
+    } else {
+        const double w = turn_angle(T) / kTwoPi;
+        out.w[i] = w;
+        out.lab[i] = classify(w, out.rule);
     }
 }
 
@@ -435,7 +631,9 @@ __global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out) {
     const uint8_t f = out.lab[i];
     double w = out.w[i];
     uint8_t lab;
-    if (f == 3) {
+    if (f == kRedo) {
+        return;  // recomputed by k_redo
+    } else if (f == 3) {
         w = __builtin_nan("");
         lab = 3;
     } else if (f == 2) {
@@ -504,6 +702,19 @@ hipError_t launch_finalize(const Points& pts, Out out, hipStream_t st) {
     const int64_t g = (pts.n + kWG - 1) / kWG;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWG), 0, st, pts, out);
     return hipGetLastError();
+}
+
+hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st) {
+    if (pts.n <= 0) return hipSuccess;
+    const int64_t g = (pts.n + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_redo, dim3((unsigned)g), dim3(kWG), 0, st, sg, ft, pts, out, eps2);
+    return hipGetLastError();
+}
+
+int near_blocks_per_cu() {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_near, kWG, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 int far_blocks_per_cu(bool inline_near, int qpw) {

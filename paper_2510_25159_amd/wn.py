@@ -24,7 +24,11 @@ OUTSIDE, INSIDE, ON_BOUNDARY, INVALID_POINT = 0, 1, 2, 3
 EXPORTS = [
     "wn_default_options", "wn_default_query_opts", "wn_create_faces", "wn_query", "wn_query_ex",
     "wn_destroy_faces", "wn_status_string", "wn_segment_bound", "wn_get_faces_info",
+    "wn_profile_create", "wn_profile_collect", "wn_profile_destroy",
 ]
+KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO = 0, 1, 2, 3, 4
+KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo"}
+KERNEL_KINDS = 8
 
 _P = ctypes.c_void_p
 
@@ -49,7 +53,7 @@ class wn_points(ctypes.Structure):
 class wn_query_opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("queries_per_wg", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
-                ("near_capacity", ctypes.c_int64), ("depth_log", _P)]
+                ("near_capacity", ctypes.c_int64), ("depth_log", _P), ("profile", _P)]
 
 
 class wn_faces_info(ctypes.Structure):
@@ -88,6 +92,11 @@ def lib():
         L.wn_destroy_faces.argtypes = [_P]
         L.wn_segment_bound.restype = ctypes.c_int
         L.wn_segment_bound.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.wn_profile_create.restype = ctypes.c_int
+        L.wn_profile_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_P)]
+        L.wn_profile_collect.restype = ctypes.c_int
+        L.wn_profile_collect.argtypes = [_P, _P, _P]
+        L.wn_profile_destroy.argtypes = [_P]
         L.wn_get_faces_info.restype = ctypes.c_int
         L.wn_get_faces_info.argtypes = [_P, ctypes.POINTER(wn_faces_info)]
         _lib = L
@@ -131,6 +140,40 @@ def _stream_ptr(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Profile:
+    """HIP-event timing of the library's kernels on the query stream."""
+
+    def __init__(self, capacity: int = 4096):
+        self._p = _P()
+        st = lib().wn_profile_create(capacity, ctypes.byref(self._p))
+        if st != WN_OK:
+            raise WnError(st, "wn_profile_create")
+
+    @property
+    def handle(self):
+        return self._p
+
+    def collect(self):
+        """{kernel name: (launches, total ms)}; resets the profile."""
+        n = np.zeros(KERNEL_KINDS, dtype=np.int64)
+        ms = np.zeros(KERNEL_KINDS, dtype=np.float64)
+        st = lib().wn_profile_collect(self._p, _np_ptr(n), _np_ptr(ms))
+        if st != WN_OK:
+            raise WnError(st, "wn_profile_collect")
+        return {KERNEL_NAMES[k]: (int(n[k]), float(ms[k])) for k in KERNEL_NAMES if n[k] > 0}
+
+    def close(self):
+        if self._p is not None and self._p.value:
+            lib().wn_profile_destroy(self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FaceSet:
@@ -180,7 +223,7 @@ class FaceSet:
     def query(self, u, v, offsets, offsets_host=None, out_w=None, out_lab=None, *, stride: int = 1,
               schedule: Optional[int] = None, precision: Optional[int] = None, rule: Optional[int] = None,
               queries_per_wg: int = 0, queue_policy: int = 0, near_capacity: int = 0, depth_log=None,
-              stream=None):
+              profile: Optional[Profile] = None, stream=None):
         """Run the query on torch CUDA tensors (float64 u, v; int64 offsets).
 
         Returns (out_w, out_lab) torch tensors (allocated when not given)."""
@@ -209,6 +252,7 @@ class FaceSet:
         q.queue_policy = queue_policy
         q.near_capacity = near_capacity
         q.depth_log = None if depth_log is None else depth_log.data_ptr()
+        q.profile = None if profile is None else profile.handle
         st = lib().wn_query_ex(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
                                _stream_ptr(stream))
         if st != WN_OK:
