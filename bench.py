@@ -45,7 +45,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--faces", type=int, default=2000, help="faces of the batched set (default: the full set)")
     ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=200000, help="points of the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=6000000, help="points of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--qpw", type=int, default=0)
@@ -118,14 +118,31 @@ def main():
     log(f"plain: {ms_plain:.3f} ms/step, {pairs / (ms_plain / 1e3):.3e} evals/s")
     plain_agree = bool(np.array_equal(lab_p, lab_b))
 
-    far_launches, far_ms = kern.get("k_far", (0, float("nan")))
-    far_avg_ms = far_ms / max(far_launches, 1)
-    achieved = FLOPS_PER_PAIR * pairs / (far_avg_ms / 1e3)
-    roofline = {"bound": "alu", "kernel": "k_far (batched far-field pair pass)", "achieved": achieved / 1e12,
-                "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
-                "traffic": None, "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs,
-                "avg_launch_ms": far_avg_ms}
+    # work counters of one (untimed) instrumented pass
+    stats = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device=dev)
+    fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, queries_per_wg=args.qpw,
+             queue_policy=args.policy, stats=stats, stream=stream)
+    torch.cuda.synchronize()
+    st = dict(zip(wn.STAT_NAMES, (int(x) for x in stats.cpu().numpy())))
+    log(f"work counters: {st}")
+
     kernels = {k: {"launches": n, "avg_ms": t / max(n, 1)} for k, (n, t) in kern.items()}
+    rooflines = {}
+    if "k_far" in kernels:
+        ms = kernels["k_far"]["avg_ms"]
+        a = FLOPS_PER_PAIR * pairs / (ms / 1e3)
+        rooflines["k_far"] = {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                              "frac": a / PEAK_FP64_VALU, "traffic": None, "avg_launch_ms": ms,
+                              "work": f"{pairs} pairs x {FLOPS_PER_PAIR} flops (root test + chord)"}
+    if "k_near" in kernels:
+        ms = kernels["k_near"]["avg_ms"]
+        a = st["near_flops"] / (ms / 1e3)
+        rooflines["k_near"] = {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                               "unit": "TFLOP/s", "frac": a / PEAK_FP64_VALU, "traffic": None, "avg_launch_ms": ms,
+                               "work": f"{st['near_pairs']} near pairs, {st['splits']} splits x (6n+15) + "
+                                       f"{st['leaves']} leaves x 11 = {st['near_flops']} flops"}
+    dom = max(rooflines, key=lambda k: rooflines[k]["avg_launch_ms"])
+    roofline = dict(rooflines[dom], kernel=dom)
 
     # CPU oracle on a bounded sample of the same workload; also the parity check
     cpu = None
@@ -175,7 +192,9 @@ def main():
         "speedup_batched_vs_plain": ms_plain / ms_step,
         "mismatches": mism,
         "kernels": kernels,
+        "work": st,
         "roofline": roofline,
+        "rooflines": rooflines,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

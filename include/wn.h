@@ -144,7 +144,21 @@ typedef struct {
                                 reached for point i against segment j of its face (0 = decided
                                 at the whole segment).  Written by WN_SCHED_PLAIN only.     */
     wn_profile* profile;     /* NULL, or a profile that records kernel durations            */
+    unsigned long long* stats; /* NULL, or device [WN_STATS_COUNT] counters the batched
+                                  schedules ADD to (zero them first): see WN_STAT_*          */
 } wn_query_opts;
+
+/* Work counters of the batched schedules (wn_query_opts.stats). */
+enum {
+    WN_STAT_NEAR_PAIRS = 0,   /* pairs whose root ellipse test failed (queued)           */
+    WN_STAT_SPLITS = 1,       /* Alg. 1 nodes split (one midpoint evaluation each)       */
+    WN_STAT_LEAVES = 2,       /* Alg. 1 leaves (one chord angle each)                    */
+    WN_STAT_REEVALS = 3,      /* pending end points re-evaluated after an LDS slot reuse */
+    WN_STAT_NEAR_FLOPS = 4,   /* algorithmic FP64 flops of the near pass (cost model:
+                                 split 6n+15, leaf 11; n = segment degree)                */
+    WN_STAT_MAX_DEPTH = 5,    /* deepest level reached (max, not sum)                    */
+    WN_STATS_COUNT = 8
+};
 
 /* Fill `opt` with the defaults listed above.  Never fails. */
 void wn_default_options(wn_options* opt);

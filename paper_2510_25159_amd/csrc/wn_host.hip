@@ -178,12 +178,6 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->precision = opt.precision;
     h->rule = opt.rule;
     h->schedule = opt.schedule;
-    if (hipGetDevice(&h->device) != hipSuccess ||
-        hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
-        delete h;
-        return WN_E_DEVICE;
-    }
-
     // per face: segment range, scale of the rounding margin
     h->h_seg_begin.resize((size_t)F + 1);
     std::vector<double> face_scale((size_t)F, 0.0);
@@ -243,6 +237,11 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     if (maxd > opt.stack_cap) {
         delete h;
         return WN_E_DEPTH;
+    }
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+        delete h;
+        return WN_E_DEVICE;
     }
 
     // faces ordered by segment count (largest first) for the work queue
@@ -475,7 +474,7 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     }
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_NEAR, st);
-        e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), st);
+        e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), Stats{q.stats}, st);
     }
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_FINALIZE, st);

@@ -61,6 +61,10 @@ struct NearQueue {
     uint64_t cap;
 };
 
+struct Stats {
+    unsigned long long* c;  // device [8] or nullptr
+};
+
 struct Out {
     double* w;      // [N] omega (or angle accumulator in the batched path)
     uint8_t* lab;   // [N] label (or on-boundary flag in the batched path)
@@ -79,7 +83,7 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
                       const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       hipStream_t st);
+                       Stats stats, hipStream_t st);
 hipError_t launch_finalize(const Points& pts, Out out, hipStream_t st);
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, int qpw);

@@ -479,9 +479,21 @@ __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_
     st.inside = true;  // queued pairs failed the root ellipse test
 }
 
-// One node of Alg. 1.  Returns true when the pair is finished.
-__device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, double2* stk, bool& onb) {
+struct NodeCount {
+    uint32_t split = 0, leaf = 0, reeval = 0, maxk = 0;
+    uint64_t flops = 0;
+};
+
+// One node of Alg. 1.  Returns true when the pair is finished.  COUNT
+// selects the instrumented variant (work counters).
+template <bool COUNT>
+__device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, double2* stk, bool& onb,
+                                          NodeCount& nc) {
     if (st.inside) {
+        if (COUNT) {
+            ++nc.split;
+            nc.flops += 6 * st.c.n + 15;
+        }
         if (st.k >= kDepthCap) {
             onb = true;
             return true;
@@ -504,7 +516,12 @@ __device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, d
         st.by = my;
         st.rb = rm;
         st.k = k1;
+        if (COUNT) nc.maxk = (uint32_t)k1 > nc.maxk ? (uint32_t)k1 : nc.maxk;
     } else {
+        if (COUNT) {
+            ++nc.leaf;
+            nc.flops += 11;
+        }
         turn_mul(T, st.ax * st.bx + st.ay * st.by, st.ax * st.by - st.ay * st.bx);
         if (st.pend == 0) return true;
         turn_norm(T);
@@ -525,6 +542,7 @@ __device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, d
                 st.by = st.pny;
             } else {
                 bez_eval(st.c, t, st.bx, st.by);
+                if (COUNT) ++nc.reeval;
             }
             st.bx -= st.qx;
             st.by -= st.qy;
@@ -537,7 +555,24 @@ __device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, d
     return false;
 }
 
-__global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2) {
+template <typename T_>
+__device__ __forceinline__ T_ wave_sum(T_ v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats) {
     __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
@@ -554,6 +589,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
     Turn T{1.0, 0.0, 0};
     bool onb = false, has = false;
     uint32_t q = 0;
+    NodeCount nc;
     for (;;) {
         const uint64_t idle = __ballot(!has);
         if (idle && next < c_end) {
@@ -575,10 +611,25 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
             if (next >= c_end) break;
             continue;
         }
-        if (has && node_step(st, T, eps2, stk, onb)) {
+        if (has && node_step<COUNT>(st, T, eps2, stk, onb, nc)) {
             if (onb) out.lab[q] = 2;
             else unsafeAtomicAdd(&out.w[q], turn_angle(T));
             has = false;
+        }
+    }
+    if (COUNT && stats.c) {
+        const unsigned long long sp = wave_sum((unsigned long long)nc.split);
+        const unsigned long long lf = wave_sum((unsigned long long)nc.leaf);
+        const unsigned long long re = wave_sum((unsigned long long)nc.reeval);
+        const unsigned long long fl = wave_sum((unsigned long long)nc.flops);
+        const uint32_t mk = wave_max(nc.maxk);
+        if (lane == 0) {
+            if (gw == 0) atomicAdd(&stats.c[0], n);
+            atomicAdd(&stats.c[1], sp);
+            atomicAdd(&stats.c[2], lf);
+            atomicAdd(&stats.c[3], re);
+            atomicAdd(&stats.c[4], fl);
+            atomicMax(&stats.c[5], (unsigned long long)mk);
         }
     }
 }
@@ -691,9 +742,12 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
 }
 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       hipStream_t st) {
+                       Stats stats, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_near, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2);
+    if (stats.c)
+        hipLaunchKernelGGL(k_near<true>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats);
+    else
+        hipLaunchKernelGGL(k_near<false>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats);
     return hipGetLastError();
 }
 
@@ -713,7 +767,7 @@ hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out
 
 int near_blocks_per_cu() {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_near, kWG, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_near<false>, kWG, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

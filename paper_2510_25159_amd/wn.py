@@ -29,6 +29,8 @@ EXPORTS = [
 KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO = 0, 1, 2, 3, 4
 KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo"}
 KERNEL_KINDS = 8
+STAT_NAMES = ["near_pairs", "splits", "leaves", "reevals", "near_flops", "max_depth"]
+STATS_COUNT = 8
 
 _P = ctypes.c_void_p
 
@@ -53,7 +55,7 @@ class wn_points(ctypes.Structure):
 class wn_query_opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("queries_per_wg", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
-                ("near_capacity", ctypes.c_int64), ("depth_log", _P), ("profile", _P)]
+                ("near_capacity", ctypes.c_int64), ("depth_log", _P), ("profile", _P), ("stats", _P)]
 
 
 class wn_faces_info(ctypes.Structure):
@@ -223,7 +225,7 @@ class FaceSet:
     def query(self, u, v, offsets, offsets_host=None, out_w=None, out_lab=None, *, stride: int = 1,
               schedule: Optional[int] = None, precision: Optional[int] = None, rule: Optional[int] = None,
               queries_per_wg: int = 0, queue_policy: int = 0, near_capacity: int = 0, depth_log=None,
-              profile: Optional[Profile] = None, stream=None):
+              profile: Optional[Profile] = None, stats=None, stream=None):
         """Run the query on torch CUDA tensors (float64 u, v; int64 offsets).
 
         Returns (out_w, out_lab) torch tensors (allocated when not given)."""
@@ -253,6 +255,7 @@ class FaceSet:
         q.near_capacity = near_capacity
         q.depth_log = None if depth_log is None else depth_log.data_ptr()
         q.profile = None if profile is None else profile.handle
+        q.stats = None if stats is None else stats.data_ptr()
         st = lib().wn_query_ex(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
                                _stream_ptr(stream))
         if st != WN_OK:
