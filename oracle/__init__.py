@@ -40,6 +40,7 @@ def _load():
         lib.wno_query.restype = ctypes.c_int
         lib.wno_query.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P, P, P,
                                   ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P]
+        lib.wno_set_periodic_options.argtypes = [ctypes.c_int32, ctypes.c_int32]
         lib.wno_segment_winding.restype = ctypes.c_double
         lib.wno_segment_winding.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_int32, P]
@@ -85,6 +86,12 @@ def query(faces, point_face, u, v, near_tol: float = 1e-9, nthreads: int | None 
     if st != 0:
         raise OracleError(f"oracle returned status {st}")
     return out_w, out_n
+
+
+def set_periodic_options(extra: int = 0, disable_pairing: bool = False):
+    """Widen periodic windows by ``extra`` copies/families; optionally disable
+    the nearest-left pairing (negative control)."""
+    _load().wno_set_periodic_options(int(extra), 1 if disable_pairing else 0)
 
 
 def query_faces(faces, queries, **kw):

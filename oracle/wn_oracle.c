@@ -20,8 +20,11 @@
  * branch and bound on de Casteljau pieces) or when that could not be decided;
  * 0 when its distance to every curve (copy) is certified >= near_tol.
  *
- * parity unpinned: none of the planar routine (pinned by closed forms, the
- * brute long-double twin and quadrature in the tests).
+ * parity: the planar routine is pinned by closed forms, the long double
+ * twin and quadrature; the periodic routine by closed-form straight bands on
+ * cylinders and tori, lattice-translation, seam re-cutting and window
+ * widening invariants.  parity unpinned: the pairing of wavy loops whose
+ * normal ranges interleave (checked only through the 0/1 postcondition).
  */
 #include <math.h>
 #include <pthread.h>
@@ -224,6 +227,11 @@ int wno_query(int32_t num_faces, const int32_t* face_loop_offsets, int32_t num_l
     }
     for (int64_t i = 0; i < num_points; ++i)
         if (point_face[i] < 0 || point_face[i] >= num_faces) return -2;
+    int pst = periodic_prepare(&fc);
+    if (pst != 0) {
+        periodic_release(&fc);
+        return pst;
+    }
     job_t J = {&fc, num_points, point_face, pu, pv, near_tol, use_long_double, out_w, out_near, 0, 0};
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
@@ -233,7 +241,16 @@ int wno_query(int32_t num_faces, const int32_t* face_loop_offsets, int32_t num_l
         if (pthread_create(&th[started], NULL, worker, &J) == 0) ++started;
     worker(&J);
     for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    periodic_release(&fc);
     return J.status;
+}
+
+/* Test knobs of the periodic formulation: widen every copy/family window by
+ * `extra` on each side; pair each alpha with the unshifted beta instead of
+ * its nearest left copy (negative control). */
+void wno_set_periodic_options(int32_t extra, int32_t disable_pairing) {
+    g_window_extra = extra < 0 ? 0 : extra;
+    g_disable_pairing = disable_pairing != 0;
 }
 
 /* Winding of a single planar segment (radians / 2pi) seen from (x, y);

@@ -403,6 +403,185 @@ def config2(seed: int = SEED_C2, num_faces: int = 2000, face_ids: Optional[Seque
 
 
 # --------------------------------------------------------------------------
+# Config 3: periodic faces (cylinder / torus parameter domains)
+# --------------------------------------------------------------------------
+TWO_PI = 2.0 * np.pi
+
+
+class WrappedCurve:
+    """alpha(t) = s0 + t * vec + A * nrm * f(t), t in [0, 1], on the covering
+    space; f is a 4-mode periodic Fourier series, so alpha(1) = alpha(0) + vec."""
+
+    def __init__(self, s0, vec, amp, rng, modes: int = 4):
+        self.s0 = np.asarray(s0, dtype=np.float64)
+        self.vec = np.asarray(vec, dtype=np.float64)
+        L = np.hypot(*self.vec)
+        self.nrm = np.array([-self.vec[1], self.vec[0]]) / L
+        k = np.arange(1, modes + 1, dtype=np.float64)
+        self.k = k
+        c = rng.uniform(-1, 1, modes) / k
+        d = rng.uniform(-1, 1, modes) / k
+        grid = np.linspace(0, 1, 2048, endpoint=False)
+        m = np.max(np.abs(np.cos(TWO_PI * grid[:, None] * k) @ c + np.sin(TWO_PI * grid[:, None] * k) @ d))
+        self.c = c * (amp / m if m > 0 else 0.0)
+        self.d = d * (amp / m if m > 0 else 0.0)
+
+    def f(self, t):
+        t = np.asarray(t, dtype=np.float64)[..., None]
+        return np.sum(self.c * np.cos(TWO_PI * self.k * t) + self.d * np.sin(TWO_PI * self.k * t), axis=-1)
+
+    def df(self, t):
+        t = np.asarray(t, dtype=np.float64)[..., None]
+        return np.sum(TWO_PI * self.k * (-self.c * np.sin(TWO_PI * self.k * t) + self.d * np.cos(TWO_PI * self.k * t)),
+                      axis=-1)
+
+    def point(self, t):
+        t = np.asarray(t, dtype=np.float64)
+        return self.s0 + t[..., None] * self.vec + self.f(t)[..., None] * self.nrm
+
+    def deriv(self, t):
+        t = np.asarray(t, dtype=np.float64)
+        return self.vec + self.df(t)[..., None] * self.nrm
+
+
+def _seam_crossings(curve: WrappedCurve, t0: float, t1: float, axis: int, T: float, tol: float = 1e-15):
+    """Parameters in (t0, t1) where coordinate ``axis`` crosses a multiple of T (bisection)."""
+    out = []
+    ts = np.linspace(t0, t1, 65)
+    vals = curve.point(ts)[:, axis] / T
+    for a, b, fa, fb in zip(ts[:-1], ts[1:], vals[:-1], vals[1:]):
+        ka, kb = np.floor(fa), np.floor(fb)
+        if ka == kb:
+            continue
+        # possibly several lines between a and b: handle each
+        lo_line, hi_line = (ka + 1, kb) if kb > ka else (kb + 1, ka)
+        for line in np.arange(lo_line, hi_line + 1):
+            lo, hi = a, b
+            glo = curve.point(lo)[axis] / T - line
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                gm = curve.point(mid)[axis] / T - line
+                if (gm > 0) == (glo > 0):
+                    lo, glo = mid, gm
+                else:
+                    hi = mid
+                if hi - lo < tol:
+                    break
+            out.append(0.5 * (lo + hi))
+    return sorted(out)
+
+
+def periodic_loop(curve: WrappedCurve, nseg: int, periods, axes) -> _Loop:
+    """Cubic Hermite pieces of ``curve`` between the segment parameters i/nseg
+    and every seam crossing; each piece translated by a lattice vector into
+    the base cell (so the loop is discontinuous at the seams)."""
+    breaks = [i / nseg for i in range(nseg + 1)]
+    cuts = set(breaks)
+    for ax in axes:
+        for i in range(nseg):
+            for t in _seam_crossings(curve, breaks[i], breaks[i + 1], ax, periods[ax]):
+                cuts.add(t)
+    ts = np.array(sorted(cuts))
+    ts = ts[np.concatenate([[True], np.diff(ts) > 1e-12])]
+    P = curve.point(ts)
+    D = curve.deriv(ts)
+    lp = _Loop()
+    for i in range(len(ts) - 1):
+        h = ts[i + 1] - ts[i]
+        cp = np.stack([P[i], P[i] + (h / 3) * D[i], P[i + 1] - (h / 3) * D[i + 1], P[i + 1]])
+        mid = curve.point(0.5 * (ts[i] + ts[i + 1]))
+        shift = np.zeros(2)
+        for ax in axes:
+            shift[ax] = -periods[ax] * np.floor(mid[ax] / periods[ax])
+        lp.cps.append(cp + shift)
+        lp.ws.append(None)
+    return lp
+
+
+def _open_and_noise(lp: _Loop, rng, open_loop: bool, gap_lo: float, gap_hi: float, sigma: float):
+    if open_loop:
+        g = rng.uniform(gap_lo, gap_hi)
+        phi = rng.uniform(0, TWO_PI)
+        lp.cps[-1] = lp.cps[-1].copy()
+        lp.cps[-1][-1] += g * np.array([np.cos(phi), np.sin(phi)])
+    if sigma > 0:
+        lp.cps = [cp + rng.normal(0.0, sigma, cp.shape) for cp in lp.cps]
+
+
+def _coprime_pair(rng):
+    while True:
+        h1, h2 = int(rng.integers(2, 6)), int(rng.integers(2, 6))
+        if np.gcd(h1, h2) == 1:
+            return h1, h2
+
+
+def config3_face(seed: int, f: int, queries: int = 2048, open_frac: float = 0.2, gap=(1e-4, 1e-2),
+                 sigma: float = 1e-5, seg_lo: int = 16, seg_hi: int = 64):
+    """Face f of the periodic set: even f cylinder (period 2pi in u, cell
+    [0,2pi) x [-pi,pi)), odd f torus (period 2pi in u and v)."""
+    rng = _face_rng(seed, f)
+    T = TWO_PI
+    loops = []
+    if f % 2 == 0:
+        domain, periods, axes = DOMAIN_CYLINDER_U, (T, 0.0), (0,)
+        nb = int(rng.integers(1, 3))
+        # disjoint bands [c1, c2] inside (-pi, pi)
+        edges = np.sort(rng.uniform(-0.85 * np.pi, 0.85 * np.pi, 2 * nb))
+        for b in range(nb):
+            c1, c2 = edges[2 * b], edges[2 * b + 1]
+            if c2 - c1 < 0.2:
+                c2 = c1 + 0.2
+            amp = min(0.2, 0.2 * (c2 - c1))
+            u0 = rng.uniform(0, T)
+            lo = WrappedCurve((u0, c1), (T, 0.0), amp, rng)
+            hi = WrappedCurve((u0 + rng.uniform(0, T), c2), (-T, 0.0), amp, rng)
+            for cv in (lo, hi):
+                lp = periodic_loop(cv, int(rng.integers(seg_lo, seg_hi + 1)), (T, T), axes)
+                _open_and_noise(lp, rng, rng.uniform() < open_frac, gap[0], gap[1], sigma)
+                loops.append(lp)
+        lo_v, hi_v = -np.pi, np.pi
+    else:
+        domain, periods, axes = DOMAIN_TORUS, (T, T), (0, 1)
+        kind = (f // 2) % 2
+        if kind == 0:
+            h1, h2 = _coprime_pair(rng)
+        else:
+            h1, h2 = [(1, 0), (0, 1), (1, 1)][int(rng.integers(0, 3))]
+        vec = np.array([h1 * T, h2 * T])
+        L = np.hypot(*vec)
+        delta = T * T / L
+        nrm = np.array([-vec[1], vec[0]]) / L
+        s0 = rng.uniform(0, T, 2)
+        amp = rng.uniform(0.05, 0.2) * delta
+        a = WrappedCurve(s0, vec, amp, rng)
+        b = WrappedCurve(s0 + 0.5 * delta * nrm + rng.uniform(0, 1) * vec, -vec, amp, rng)
+        for cv in (a, b):
+            lp = periodic_loop(cv, int(rng.integers(seg_lo, seg_hi + 1)), (T, T), axes)
+            _open_and_noise(lp, rng, rng.uniform() < open_frac, gap[0], gap[1], sigma)
+            loops.append(lp)
+        lo_v, hi_v = 0.0, T
+    pts = np.column_stack([rng.uniform(0, T, queries), rng.uniform(lo_v, hi_v, queries)])
+    return loops, pts, domain, (T, T)
+
+
+def config3(seed: int = SEED_C3, num_faces: int = 512, face_ids: Optional[Sequence[int]] = None, **kw):
+    ids = list(range(num_faces)) if face_ids is None else list(face_ids)
+    face_loops, pts_all, doms, pers, offs = [], [], [], [], [0]
+    for f in ids:
+        loops, pts, dom, per = config3_face(seed, f, **kw)
+        face_loops.append(loops)
+        pts_all.append(pts)
+        doms.append(dom)
+        pers.append(per)
+        offs.append(offs[-1] + len(pts))
+    faces = _assemble(face_loops, doms, pers, rational=False)
+    P = np.concatenate(pts_all)
+    q = Queries(u=np.ascontiguousarray(P[:, 0]), v=np.ascontiguousarray(P[:, 1]),
+                face_point_offsets=np.asarray(offs, dtype=np.int64))
+    return faces, q
+
+
+# --------------------------------------------------------------------------
 # helpers for tests
 # --------------------------------------------------------------------------
 def faces_from_loops(face_loops, domains=None, periods=None, rational=None) -> Faces:
