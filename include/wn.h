@@ -127,6 +127,7 @@ enum {
     WN_KERNEL_NEAR = 2,
     WN_KERNEL_FINALIZE = 3,
     WN_KERNEL_REDO = 4,
+    WN_KERNEL_FAR_PERIODIC = 5,
     WN_KERNEL_KINDS = 8
 };
 
@@ -217,6 +218,7 @@ void wn_profile_destroy(wn_profile* p);
 /* Summary of a created handle (host copy of sizes). */
 typedef struct {
     int32_t num_faces, num_loops, num_segments;
+    int32_t num_periodic_faces;
     int32_t max_segments_per_face;
     int32_t max_depth_bound;   /* largest ceil(log2(B/eps))+3 over segments */
     int64_t device_bytes;      /* device memory held by the handle */

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwn.so")
-SOURCES = ["wn_host.hip", "wn_kernels.hip"]
+SOURCES = ["wn_host.hip", "wn_kernels.hip", "wn_periodic.hip", "wn_topology.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -2,6 +2,7 @@
 // device packing and query scheduling behind the C ABI of include/wn.h.
 #include "../../include/wn.h"
 #include "wn_internal.h"
+#include "wn_topology.h"
 
 #include <math.h>
 #include <string.h>
@@ -18,13 +19,18 @@ struct wn_faces {
     void* dmem = nullptr;
     int64_t dbytes = 0;
     Segs sg{};
-    FaceTab ft{};
+    FaceTab ft_plan{};   // planar faces, largest first
+    FaceTab ft_per{};    // periodic faces, largest first
+    PerTab pt{};
     int32_t num_faces = 0, num_loops = 0, num_segments = 0;
+    int32_t num_planar = 0, num_periodic = 0;
     int32_t max_spf = 0, max_depth = 0;
     double eps = 1e-10, eps2 = 1e-20;
     int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
     int cu_count = 0;
     std::vector<int32_t> h_seg_begin;
+    std::vector<int32_t> h_dom;
+    std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
 };
 
 struct wn_profile {
@@ -163,9 +169,17 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         if (!finite_small(d->cp_u[i]) || !finite_small(d->cp_v[i])) return WN_E_INVALID;
         if (d->cp_w && !(d->cp_w[i] > 0.0 && isfinite(d->cp_w[i]) && d->cp_w[i] < 1e100)) return WN_E_INVALID;
     }
+    std::vector<int32_t> dom((size_t)F, WN_DOMAIN_PLANE);
+    int32_t nper = 0;
     for (int32_t f = 0; f < F; ++f) {
-        const int dom = d->face_domain ? d->face_domain[f] : WN_DOMAIN_PLANE;
-        if (dom != WN_DOMAIN_PLANE) return WN_E_UNSUPPORTED;
+        dom[f] = d->face_domain ? d->face_domain[f] : WN_DOMAIN_PLANE;
+        if (dom[f] < WN_DOMAIN_PLANE || dom[f] > WN_DOMAIN_TORUS) return WN_E_INVALID;
+        if (dom[f] != WN_DOMAIN_PLANE) {
+            if (!d->face_period) return WN_E_INVALID;
+            const double Tu = d->face_period[2 * f], Tv = d->face_period[2 * f + 1];
+            if (!(Tu > 0.0 && Tu < 1e6) || (dom[f] == WN_DOMAIN_TORUS && !(Tv > 0.0 && Tv < 1e6))) return WN_E_INVALID;
+            ++nper;
+        }
     }
 
     wn_faces* h = new (std::nothrow) wn_faces();
@@ -173,11 +187,15 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->num_faces = F;
     h->num_loops = L;
     h->num_segments = S;
+    h->num_periodic = nper;
+    h->num_planar = F - nper;
     h->eps = opt.eps;
     h->eps2 = opt.eps * opt.eps;
     h->precision = opt.precision;
     h->rule = opt.rule;
     h->schedule = opt.schedule;
+    h->h_dom = dom;
+
     // per face: segment range, scale of the rounding margin
     h->h_seg_begin.resize((size_t)F + 1);
     std::vector<double> face_scale((size_t)F, 0.0);
@@ -194,7 +212,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     // per segment host arrays
     std::vector<double> p0x(S), p0y(S), pnx(S), pny(S), hb2(S), Bv(S), eta(S);
     std::vector<double> coef((size_t)S * kCoef * 4, 0.0);
-    std::vector<uint8_t> deg(S), rat(S);
+    std::vector<uint8_t> deg(S), rat(S), segper(S, 0);
     int32_t maxd = 0;
     for (int32_t f = 0; f < F; ++f) {
         const double e = 8.0 * 1.1102230246251565e-16 * (1.0 + face_scale[f]);
@@ -221,6 +239,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
             hb2[s] = 0.5 * Be * Be;
             deg[s] = (uint8_t)n;
             rat[s] = is_rat ? 1 : 0;
+            segper[s] = dom[f] != WN_DOMAIN_PLANE ? 1 : 0;
             for (int j = 0; j <= n; ++j) {
                 const int i = n - j;
                 const double wi = is_rat ? w[i] : 1.0;
@@ -244,12 +263,16 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         return WN_E_DEVICE;
     }
 
-    // faces ordered by segment count (largest first) for the work queue
-    std::vector<int32_t> order((size_t)F);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    // faces ordered by segment count (largest first) for the work queues
+    std::vector<int32_t> ord_plan, ord_per;
+    for (int32_t f = 0; f < F; ++f) (dom[f] == WN_DOMAIN_PLANE ? ord_plan : ord_per).push_back(f);
+    auto by_size = [&](int32_t a, int32_t b) {
         return (h->h_seg_begin[a + 1] - h->h_seg_begin[a]) > (h->h_seg_begin[b + 1] - h->h_seg_begin[b]);
-    });
+    };
+    std::stable_sort(ord_plan.begin(), ord_plan.end(), by_size);
+    std::stable_sort(ord_per.begin(), ord_per.end(), by_size);
+    h->per_pos.assign((size_t)F, 0);
+    for (size_t r = 0; r < ord_per.size(); ++r) h->per_pos[ord_per[r]] = (int32_t)r;
 
     // one device allocation, 256-byte aligned sub-buffers
     struct Part {
@@ -269,9 +292,13 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     const size_t o_pnx = add(pnx.data(), S * 8), o_pny = add(pny.data(), S * 8);
     const size_t o_hb2 = add(hb2.data(), S * 8), o_B = add(Bv.data(), S * 8), o_eta = add(eta.data(), S * 8);
     const size_t o_coef = add(coef.data(), coef.size() * 8);
-    const size_t o_deg = add(deg.data(), S), o_rat = add(rat.data(), S);
+    const size_t o_deg = add(deg.data(), S), o_rat = add(rat.data(), S), o_sper = add(segper.data(), S);
     const size_t o_sb = add(h->h_seg_begin.data(), ((size_t)F + 1) * 4);
-    const size_t o_ord = add(order.data(), (size_t)F * 4);
+    const size_t o_op = add(ord_plan.data(), ord_plan.size() * 4), o_oq = add(ord_per.data(), ord_per.size() * 4);
+    // periodic tables (filled after the lift)
+    const size_t o_ploop = add(nullptr, nper ? (size_t)L * sizeof(PLoop) : 0);
+    const size_t o_pface = add(nullptr, nper ? (size_t)F * sizeof(PFace) : 0);
+    const size_t o_punit = add(nullptr, nper ? (size_t)(2 * L + 1) * sizeof(PUnit) : 0);
     if (total == 0) total = 256;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMalloc(&h->dmem, total);
@@ -282,16 +309,17 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->dbytes = (int64_t)total;
     char* base = (char*)h->dmem;
     for (const Part& p : parts) {
-        if (p.bytes == 0) continue;
+        if (p.bytes == 0 || !p.src) continue;
         e = hipMemcpyAsync(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
+    auto fail = [&](wn_status code) {
         (void)hipFree(h->dmem);
         delete h;
-        return hip_status(e);
-    }
+        return code;
+    };
+    if (e != hipSuccess) return fail(hip_status(e));
     h->sg.p0x = (const double*)(base + o_p0x);
     h->sg.p0y = (const double*)(base + o_p0y);
     h->sg.pnx = (const double*)(base + o_pnx);
@@ -302,9 +330,114 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->sg.coef = (const double*)(base + o_coef);
     h->sg.deg = (const uint8_t*)(base + o_deg);
     h->sg.rat = (const uint8_t*)(base + o_rat);
-    h->ft.seg_begin = (const int32_t*)(base + o_sb);
-    h->ft.order = (const int32_t*)(base + o_ord);
-    h->ft.num_faces = F;
+    const int32_t* d_sb = (const int32_t*)(base + o_sb);
+    h->ft_plan = FaceTab{d_sb, (const int32_t*)(base + o_op), (int32_t)ord_plan.size()};
+    h->ft_per = FaceTab{d_sb, (const int32_t*)(base + o_oq), (int32_t)ord_per.size()};
+    h->pt.seg_periodic = (const uint8_t*)(base + o_sper);
+
+    if (nper > 0) {
+        // ---- covering-space lift on the GPU (k_lift), read back for the topology
+        std::vector<int32_t> lift_loops, loop_face((size_t)L, 0);
+        for (int32_t f = 0; f < F; ++f)
+            for (int32_t l = d->face_loop_offsets[f]; l < d->face_loop_offsets[f + 1]; ++l) {
+                loop_face[l] = f;
+                if (dom[f] != WN_DOMAIN_PLANE) lift_loops.push_back(l);
+            }
+        std::vector<double> per2((size_t)2 * F, 0.0);
+        for (int32_t f = 0; f < F; ++f)
+            if (dom[f] != WN_DOMAIN_PLANE) {
+                per2[2 * f] = d->face_period[2 * f];
+                per2[2 * f + 1] = d->face_period[2 * f + 1];
+            }
+        size_t tt = 0;
+        auto tk = [&](size_t bytes) {
+            const size_t off = tt;
+            tt += (bytes + 255) & ~(size_t)255;
+            return off;
+        };
+        const size_t t_loops = tk(lift_loops.size() * 4), t_lf = tk((size_t)L * 4), t_dom = tk((size_t)F * 4);
+        const size_t t_per = tk((size_t)F * 16), t_ls = tk(((size_t)L + 1) * 4), t_sc = tk(((size_t)S + 1) * 8);
+        const size_t t_cu = tk((size_t)d->num_cps * 8), t_cv = tk((size_t)d->num_cps * 8);
+        const size_t t_off = tk((size_t)S * 16);
+        void* tmp = nullptr;
+        e = hipMalloc(&tmp, tt ? tt : 256);
+        if (e != hipSuccess) return fail(hip_status(e));
+        char* tb = (char*)tmp;
+        const std::pair<size_t, std::pair<const void*, size_t>> ups[] = {
+            {t_loops, {lift_loops.data(), lift_loops.size() * 4}},
+            {t_lf, {loop_face.data(), (size_t)L * 4}},
+            {t_dom, {dom.data(), (size_t)F * 4}},
+            {t_per, {per2.data(), (size_t)F * 16}},
+            {t_ls, {d->loop_seg_offsets, ((size_t)L + 1) * 4}},
+            {t_sc, {d->seg_cp_offsets, ((size_t)S + 1) * 8}},
+            {t_cu, {d->cp_u, (size_t)d->num_cps * 8}},
+            {t_cv, {d->cp_v, (size_t)d->num_cps * 8}},
+        };
+        for (const auto& u : ups)
+            if (e == hipSuccess && u.second.second)
+                e = hipMemcpyAsync(tb + u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, st);
+        PLoop* d_ploop = (PLoop*)(base + o_ploop);
+        LiftArgs la{(const int32_t*)(tb + t_loops), (int32_t)lift_loops.size(), (const int32_t*)(tb + t_lf),
+                    (const int32_t*)(tb + t_dom), (const double*)(tb + t_per), (const int32_t*)(tb + t_ls),
+                    (const int64_t*)(tb + t_sc), (const double*)(tb + t_cu), (const double*)(tb + t_cv),
+                    (double*)(tb + t_off), d_ploop};
+        if (e == hipSuccess) e = hipMemsetAsync(d_ploop, 0, (size_t)L * sizeof(PLoop), st);
+        if (e == hipSuccess) e = launch_lift(la, h->sg, st);
+        std::vector<PLoop> ploop((size_t)L);
+        std::vector<double> seg_off((size_t)2 * S, 0.0);
+        if (e == hipSuccess) e = hipMemcpyAsync(ploop.data(), d_ploop, (size_t)L * sizeof(PLoop), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(seg_off.data(), tb + t_off, (size_t)S * 16, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(hip_status(e));
+
+        // ---- loop classes, homology checks, pairing (host)
+        std::vector<HostSeg> hsegs((size_t)S);
+        for (int32_t f = 0; f < F; ++f) {
+            if (dom[f] == WN_DOMAIN_PLANE) continue;
+            for (int32_t s = h->h_seg_begin[f]; s < h->h_seg_begin[f + 1]; ++s) {
+                const int64_t c0 = d->seg_cp_offsets[s];
+                HostSeg& g = hsegs[s];
+                g.n = deg[s];
+                g.B = Bv[s];
+                for (int i = 0; i <= g.n; ++i) {
+                    g.x[i] = d->cp_u[c0 + i] + seg_off[2 * s];
+                    g.y[i] = d->cp_v[c0 + i] + seg_off[2 * s + 1];
+                    g.w[i] = (rat[s] && d->cp_w) ? d->cp_w[c0 + i] : 1.0;
+                }
+            }
+        }
+        std::vector<PUnit> units;
+        std::vector<PFace> pface((size_t)F);
+        for (int32_t f = 0; f < F; ++f) {
+            if (dom[f] == WN_DOMAIN_PLANE) continue;
+            if (build_periodic_face(dom[f], d->face_period[2 * f], d->face_period[2 * f + 1], d->face_loop_offsets[f],
+                                    d->face_loop_offsets[f + 1], hsegs, ploop, units, pface[f]) != 0)
+                return fail(WN_E_TOPOLOGY);
+            // rounding margin for the magnitudes met by translated copies
+            double reach = fabs(pface[f].t1x) + fabs(pface[f].t1y) + 2.0 * (d->face_period[2 * f] + d->face_period[2 * f + 1]);
+            for (int32_t l = d->face_loop_offsets[f]; l < d->face_loop_offsets[f + 1]; ++l)
+                reach = std::max(reach, 3.0 * ploop[l].lv + 4.0 * (fabs(ploop[l].bb[0]) + fabs(ploop[l].bb[1]) +
+                                                                   fabs(ploop[l].bb[2]) + fabs(ploop[l].bb[3])));
+            const double em = 8.0 * 1.1102230246251565e-16 * (1.0 + face_scale[f] + reach);
+            for (int32_t s = h->h_seg_begin[f]; s < h->h_seg_begin[f + 1]; ++s) {
+                eta[s] = em;
+                const double Be = Bv[s] * (1.0 + kAxisInflate) + em;
+                hb2[s] = 0.5 * Be * Be;
+            }
+        }
+        if (units.size() > (size_t)(2 * L + 1)) return fail(WN_E_TOPOLOGY);
+        e = hipMemcpyAsync(base + o_eta, eta.data(), (size_t)S * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(base + o_hb2, hb2.data(), (size_t)S * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !units.empty())
+            e = hipMemcpyAsync(base + o_punit, units.data(), units.size() * sizeof(PUnit), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(base + o_pface, pface.data(), (size_t)F * sizeof(PFace), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(hip_status(e));
+        h->pt.loop = d_ploop;
+        h->pt.unit = (const PUnit*)(base + o_punit);
+        h->pt.face = (const PFace*)(base + o_pface);
+    }
     *out = h;
     return WN_OK;
 }
@@ -320,6 +453,7 @@ wn_status wn_get_faces_info(const wn_faces* h, wn_faces_info* info) {
     info->num_faces = h->num_faces;
     info->num_loops = h->num_loops;
     info->num_segments = h->num_segments;
+    info->num_periodic_faces = h->num_periodic;
     info->max_segments_per_face = h->max_spf;
     info->max_depth_bound = h->max_depth;
     info->device_bytes = h->dbytes;
@@ -413,36 +547,15 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     hipStream_t st = (hipStream_t)stream;
     const Points pts{p->u, p->v, p->stride, p->face_point_offsets, N};
     const int qpw = q.queries_per_wg ? q.queries_per_wg : pick_qpw(N, h->cu_count);
+    const bool periodic = h->num_periodic > 0;
     hipError_t e = hipSuccess;
 
-    if (sched == WN_SCHED_PLAIN) {
-        std::vector<int64_t> offs;
-        const int64_t* ho = p->face_point_offsets_host;
-        if (!ho) {
-            offs.resize((size_t)F + 1);
-            e = hipMemcpyAsync(offs.data(), p->face_point_offsets, offs.size() * 8, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return hip_status(e);
-            if (offs[0] != 0 || offs[F] != N) return WN_E_INVALID;
-            for (int32_t f = 0; f < F; ++f)
-                if (offs[f + 1] < offs[f]) return WN_E_INVALID;
-            ho = offs.data();
-        }
-        const Out out{out_w, out_lab, q.depth_log, h->max_spf, rule};
-        for (int32_t f = 0; f < F && e == hipSuccess; ++f) {
-            const int64_t nf = ho[f + 1] - ho[f];
-            if (nf == 0) continue;
-            ProfScope ps(q.profile, WN_KERNEL_FAR, st);
-            e = launch_far(true, qpw, h->sg, h->ft, pts, nullptr, nullptr, nullptr, f, (nf + qpw - 1) / qpw,
-                           NearQueue{}, out, h->eps2, st);
-        }
-        return hip_status(e);
-    }
-
-    // batched: one persistent far launch over all faces, near queue, finalize
-    const int64_t max_items = N / qpw + F + 1;
+    // scratch: item tables, counters, near queue (+ copy translations), temporaries
+    const bool plain = sched == WN_SCHED_PLAIN;
+    const int64_t max_items = N / 64 + F + 1;
     int64_t cap = q.near_capacity > 0 ? q.near_capacity : 8 * N + 65536;
     cap = std::min<int64_t>(cap, (int64_t)1 << 34);
+    if (plain) cap = 0;  // periodic faces of the plain schedule recurse in line
     size_t total = 0;
     auto take = [&](size_t bytes) {
         const size_t off = total;
@@ -450,7 +563,7 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
         return off;
     };
     const size_t o_io = take(((size_t)F + 1) * 4), o_im = take((size_t)max_items * 8), o_ct = take(16);
-    const size_t o_nq = take((size_t)cap * 8);
+    const size_t o_nq = take((size_t)cap * 8), o_sh = take(periodic ? (size_t)cap * 16 : 0);
     const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
     void* scratch = nullptr;
     e = hipMallocAsync(&scratch, total, st);
@@ -459,30 +572,91 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     int32_t* item_offs = (int32_t*)(b + o_io);
     int2* item_map = (int2*)(b + o_im);
     uint32_t* counters = (uint32_t*)(b + o_ct);
-    NearQueue nq{(uint2*)(b + o_nq), (unsigned long long*)(counters + 2), (uint64_t)cap};
+    NearQueue nq{(uint2*)(b + o_nq), periodic ? (double2*)(b + o_sh) : nullptr, (unsigned long long*)(counters + 2),
+                 (uint64_t)cap};
     Out out{out_w ? out_w : (double*)(b + o_w), out_lab ? out_lab : (uint8_t*)(b + o_l), nullptr, 0, rule};
-    {
-        ProfScope ps(q.profile, WN_KERNEL_ITEMS, st);
-        e = launch_build_items(h->ft, pts, qpw, item_offs, item_map, max_items, counters, st);
+    bool zero_near = true;
+
+    if (plain) {
+        std::vector<int64_t> offs;
+        const int64_t* ho = p->face_point_offsets_host;
+        if (!ho) {
+            offs.resize((size_t)F + 1);
+            e = hipMemcpyAsync(offs.data(), p->face_point_offsets, offs.size() * 8, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            bool ok = e == hipSuccess && offs[0] == 0 && offs[F] == N;
+            for (int32_t f = 0; ok && f < F; ++f) ok = offs[f + 1] >= offs[f];
+            if (!ok) {
+                (void)hipFreeAsync(scratch, st);
+                return e != hipSuccess ? hip_status(e) : WN_E_INVALID;
+            }
+            ho = offs.data();
+        }
+        const Out pout{out.w, out.lab, q.depth_log, h->max_spf, rule};
+        for (int32_t f = 0; f < F && e == hipSuccess; ++f) {
+            const int64_t nf = ho[f + 1] - ho[f];
+            if (nf == 0) continue;
+            ProfScope ps(q.profile, WN_KERNEL_FAR, st);
+            if (h->h_dom[f] == WN_DOMAIN_PLANE) {
+                e = launch_far(true, qpw, h->sg, h->ft_plan, pts, nullptr, nullptr, nullptr, f, (nf + qpw - 1) / qpw,
+                               NearQueue{}, pout, h->eps2, st);
+            } else {
+                // one-face item table, in-line recursion (queue capacity 0), finalize of its range
+                const FaceTab one{h->ft_per.seg_begin, h->ft_per.order + h->per_pos[f], 1};
+                e = launch_build_items(one, pts, 256, item_offs, item_map, max_items, counters, zero_near, st);
+                zero_near = false;
+                if (e == hipSuccess)
+                    e = launch_far_periodic(h->sg, one, pts, item_offs, item_map, nullptr, (nf + 255) / 256, nq, out,
+                                            h->eps2, h->pt, st);
+                if (e == hipSuccess) e = launch_finalize(pts, out, ho[f], ho[f + 1], st);
+            }
+        }
+        const hipError_t e2 = hipFreeAsync(scratch, st);
+        if (e == hipSuccess) e = e2;
+        return hip_status(e);
     }
-    if (e == hipSuccess) {
-        const bool persistent = q.queue_policy != 2;
-        const int64_t grid = persistent ? (int64_t)h->cu_count * far_blocks_per_cu(false, qpw) : max_items;
-        ProfScope ps(q.profile, WN_KERNEL_FAR, st);
-        e = launch_far(false, qpw, h->sg, h->ft, pts, item_offs, item_map, persistent ? counters : nullptr, -1, grid,
-                       nq, out, h->eps2, st);
+
+    // batched: persistent far launches (planar, periodic), near queue, finalize
+    if (h->num_planar > 0) {
+        {
+            ProfScope ps(q.profile, WN_KERNEL_ITEMS, st);
+            e = launch_build_items(h->ft_plan, pts, qpw, item_offs, item_map, max_items, counters, zero_near, st);
+            zero_near = false;
+        }
+        if (e == hipSuccess) {
+            const bool persistent = q.queue_policy != 2;
+            const int64_t grid = persistent ? (int64_t)h->cu_count * far_blocks_per_cu(false, qpw) : max_items;
+            ProfScope ps(q.profile, WN_KERNEL_FAR, st);
+            e = launch_far(false, qpw, h->sg, h->ft_plan, pts, item_offs, item_map, persistent ? counters : nullptr,
+                           -1, grid, nq, out, h->eps2, st);
+        }
+    }
+    if (e == hipSuccess && periodic) {
+        {
+            ProfScope ps(q.profile, WN_KERNEL_ITEMS, st);
+            e = launch_build_items(h->ft_per, pts, 256, item_offs, item_map, max_items, counters, zero_near, st);
+            zero_near = false;
+        }
+        if (e == hipSuccess) {
+            const bool persistent = q.queue_policy != 2;
+            const int64_t grid = persistent ? (int64_t)h->cu_count * far_periodic_blocks_per_cu() : max_items;
+            ProfScope ps(q.profile, WN_KERNEL_FAR_PERIODIC, st);
+            e = launch_far_periodic(h->sg, h->ft_per, pts, item_offs, item_map, persistent ? counters : nullptr, grid,
+                                    nq, out, h->eps2, h->pt, st);
+        }
     }
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_NEAR, st);
-        e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), Stats{q.stats}, st);
+        e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), Stats{q.stats},
+                        h->pt.seg_periodic, st);
     }
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_FINALIZE, st);
-        e = launch_finalize(pts, out, st);
+        e = launch_finalize(pts, out, 0, N, st);
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess && h->num_planar > 0) {
         ProfScope ps(q.profile, WN_KERNEL_REDO, st);
-        e = launch_redo(h->sg, h->ft, pts, out, h->eps2, st);
+        e = launch_redo(h->sg, FaceTab{h->ft_plan.seg_begin, nullptr, F}, pts, out, h->eps2, st);
     }
     const hipError_t e2 = hipFreeAsync(scratch, st);
     if (e == hipSuccess) e = e2;

@@ -57,8 +57,59 @@ struct Points {
 
 struct NearQueue {
     uint2* qs;                     // [cap] (query index, segment index)
+    double2* shift;                // [cap] translation of the segment copy (periodic faces), or nullptr
     unsigned long long* count;     // device counter (may exceed cap: overflow pairs are done in line)
     uint64_t cap;
+};
+
+// Periodic faces (Sec. 4.3-4.5).  Segments of periodic faces are stored
+// lifted (translated by their lattice offsets) after creation.
+struct PLoop {
+    int32_t s0, s1;       // segments
+    int32_t h0, h1;       // homology
+    double vx, vy;        // lifted end - lifted start
+    double dx, dy, lv;    // unit tangent of v, |v|
+    double b0x, b0y;      // lifted start
+    double xi_lo, xi_hi;  // tangent extent of lifted control points relative to b0
+    double bb[4];         // lifted control-point box umin, umax, vmin, vmax
+};
+
+enum { kUnitExtended = 1, kUnitContractible = 2, kUnitPair = 3 };
+
+struct PUnit {
+    int32_t kind;
+    int32_t la, lb;          // loop(s): extended curve / contractible loop / pair (alpha, beta)
+    int32_t pad;
+    double pshx, pshy;       // translation of the paired beta copy
+    double eta_lo, eta_hi;   // normal extent of the pair relative to alpha's start
+};
+
+struct PFace {
+    int32_t dom, u0, u1, pad;  // domain, units [u0, u1)
+    double Tu, Tv;             // periods
+    double t1x, t1y;           // family step t_1 (torus)
+    double Delta, nx, ny;      // family spacing and left normal of h* (T_u, T_v) (torus)
+};
+
+struct PerTab {
+    const PLoop* loop;   // [L]
+    const PUnit* unit;   // [U]
+    const PFace* face;   // [F]
+    const uint8_t* seg_periodic;  // [S] 1 for segments of periodic faces
+};
+
+struct LiftArgs {
+    const int32_t* loops;      // loop ids to lift
+    int32_t nloops;
+    const int32_t* loop_face;  // [L]
+    const int32_t* face_dom;   // [F]
+    const double* face_per;    // [2F]
+    const int32_t* loop_seg;   // [L+1]
+    const int64_t* seg_cp;     // [S+1]
+    const double* cpu;         // raw control points
+    const double* cpv;
+    double* seg_off;           // [2S] out: lattice offset per segment
+    PLoop* out;                // [L]
 };
 
 struct Stats {
@@ -78,14 +129,19 @@ struct Out {
 // Kernel launchers (wn_kernels.hip).
 namespace wn {
 hipError_t launch_build_items(const FaceTab& ft, const Points& pts, int qpw, int32_t* item_offs, int2* item_map,
-                              int64_t map_cap, uint32_t* counters, hipStream_t st);
+                              int64_t map_cap, uint32_t* counters, bool zero_near, hipStream_t st);
 hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
                       const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       Stats stats, hipStream_t st);
-hipError_t launch_finalize(const Points& pts, Out out, hipStream_t st);
+                       Stats stats, const uint8_t* seg_per, hipStream_t st);
+hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, hipStream_t st);
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, int qpw);
 int near_blocks_per_cu();
+hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);
+hipError_t launch_far_periodic(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+                               const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
+                               double eps2, PerTab pt, hipStream_t st);
+int far_periodic_blocks_per_cu();
 }  // namespace wn

@@ -30,188 +30,9 @@
 //  * Curve points: O(n) Bernstein evaluation (Horner in t with powers of
 //    1 - t over pre-scaled coefficients C(n,i) w_i P_i; one reciprocal for
 //    rational segments).
-#include "wn_internal.h"
-
-#include <math.h>
+#include "wn_device.h"
 
 namespace wn {
-
-constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr uint8_t kRedo = 4;  // label placeholder: query must be recomputed in line
-
-// ---------------------------------------------------------------------------
-// angle accumulator
-// ---------------------------------------------------------------------------
-struct Turn {
-    double zr, zi;
-    int K;
-};
-
-__device__ __forceinline__ int sign_bit(double x) { return (int)((unsigned)__double2hiint(x) >> 31); }
-
-__device__ __forceinline__ void turn_mul(Turn& t, double wr, double wi) {
-    const double nr = fma(t.zr, wr, -(t.zi * wi));
-    const double ni = fma(t.zr, wi, t.zi * wr);
-    const int sz = sign_bit(t.zi), sw = sign_bit(wi), sn = sign_bit(ni);
-    t.K += (sz == sw) ? (sn - sz) : 0;
-    t.zr = nr;
-    t.zi = ni;
-}
-
-// Rescale z by a power of two (exact) so that products of a few factors can
-// neither overflow nor underflow.
-__device__ __forceinline__ void turn_norm(Turn& t) {
-    int e;
-    (void)frexp(fmax(fabs(t.zr), fabs(t.zi)), &e);
-    t.zr = ldexp(t.zr, -e);
-    t.zi = ldexp(t.zi, -e);
-}
-
-__device__ __forceinline__ double turn_angle(const Turn& t) { return atan2(t.zi, t.zr) + kTwoPi * (double)t.K; }
-
-// ---------------------------------------------------------------------------
-// ellipse test (Lemma 1 / sub-segment bound), square-root free
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool outside_ellipse(double ra, double rb, double hb2) {
-    const double R = fma(-0.5, ra + rb, hb2);
-    return (R < 0.0) || (ra * rb > R * R);
-}
-
-__device__ __forceinline__ double half_axis2(double B, double eta, int k) {
-    const double Bk = fma(ldexp(B, -k), 1.0 + kAxisInflate, eta);
-    return 0.5 * Bk * Bk;
-}
-
-// ---------------------------------------------------------------------------
-// curve evaluation
-// ---------------------------------------------------------------------------
-struct Coef {
-    double x[kCoef], y[kCoef], w[kCoef];
-    int n;
-    bool rat;
-};
-
-__device__ __forceinline__ void load_coef(const Segs& sg, int s, Coef& c) {
-    const double4* cf = reinterpret_cast<const double4*>(sg.coef) + (size_t)s * kCoef;
-#pragma unroll
-    for (int j = 0; j < kCoef; ++j) {
-        const double4 v = cf[j];
-        c.x[j] = v.x;
-        c.y[j] = v.y;
-        c.w[j] = v.z;
-    }
-    c.n = sg.deg[s];
-    c.rat = sg.rat[s] != 0;
-}
-
-// gamma(t) = sum_i C(n,i) w_i P_i t^i (1-t)^(n-i) / sum_i C(n,i) w_i t^i (1-t)^(n-i).
-// Slot j holds index i = n - j, so Horner in t runs j = 0..n with (1-t)^j.
-__device__ __forceinline__ void bez_eval(const Coef& c, double t, double& X, double& Y) {
-    const double s = 1.0 - t;
-    double ax = c.x[0], ay = c.y[0], aw = c.w[0], sp = 1.0;
-#pragma unroll
-    for (int j = 1; j < kCoef; ++j) {
-        if (j <= c.n) {
-            sp *= s;
-            ax = fma(ax, t, c.x[j] * sp);
-            ay = fma(ay, t, c.y[j] * sp);
-            aw = fma(aw, t, c.w[j] * sp);
-        }
-    }
-    if (c.rat) {
-        const double r = 1.0 / aw;
-        X = ax * r;
-        Y = ay * r;
-    } else {
-        X = ax;
-        Y = ay;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// near pair: Alg. 1 on an explicit stack.  The root [0,1] is known to be
-// inside its ellipse and not on the boundary.  Points are kept relative to
-// the query.  `stk` is this lane's slot 0 in LDS (slot stride kWave).
-// Returns the deepest level reached; sets onb on an eps hit.
-// ---------------------------------------------------------------------------
-__device__ int near_pair(Turn& T, const Coef& c, double B, double eta, double pnx, double pny, double qx, double qy,
-                         double ax, double ay, double ra, double bx, double by, double rb, double eps2,
-                         double2* stk, bool& onb) {
-    double a = 0.0;  // left end of the current node, exact dyadic
-    int k = 0;       // level: node = [a, a + 2^-k]
-    uint64_t pend = 0, stored = 0;
-    int maxk = 0;
-    bool inside = true;
-    for (;;) {
-        if (inside) {
-            if (k >= kDepthCap) {
-                onb = true;  // cannot happen for a validated eps (depth bound <= cap)
-                return maxk;
-            }
-            const int k1 = k + 1;
-            const int slot = k1 & (kStackSlots - 1);
-            stk[slot * kWave] = make_double2(bx, by);
-            if (k1 >= kStackSlots) stored &= ~(1ull << (k1 - kStackSlots));
-            stored |= 1ull << k1;
-            pend |= 1ull << k1;
-            double mx, my;
-            bez_eval(c, a + ldexp(1.0, -k1), mx, my);
-            mx -= qx;
-            my -= qy;
-            const double rm = mx * mx + my * my;
-            if (rm < eps2) {
-                onb = true;
-                return k1;
-            }
-            bx = mx;
-            by = my;
-            rb = rm;
-            k = k1;
-            maxk = k1 > maxk ? k1 : maxk;
-        } else {
-            turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
-            if (pend == 0) return maxk;
-            turn_norm(T);
-            const int kk = 63 - __clzll(pend);
-            pend &= ~(1ull << kk);
-            a += ldexp(1.0, -k);
-            ax = bx;
-            ay = by;
-            ra = rb;
-            if (stored & (1ull << kk)) {
-                const double2 p = stk[(kk & (kStackSlots - 1)) * kWave];
-                bx = p.x;
-                by = p.y;
-            } else {
-                const double t = a + ldexp(1.0, -kk);
-                if (t == 1.0) {
-                    bx = pnx;
-                    by = pny;
-                } else {
-                    bez_eval(c, t, bx, by);
-                }
-                bx -= qx;
-                by -= qy;
-            }
-            stored &= ~(1ull << kk);
-            rb = bx * bx + by * by;
-            k = kk;
-        }
-        inside = !outside_ellipse(ra, rb, half_axis2(B, eta, k));
-    }
-}
-
-// Near pair with all segment data read from global memory.
-__device__ __forceinline__ int near_from_global(Turn& T, const Segs& sg, uint32_t s, double qx, double qy,
-                                                double eps2, double2* stk, bool& onb) {
-    const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
-    const double pnx = sg.pnx[s], pny = sg.pny[s];
-    const double bx = pnx - qx, by = pny - qy;
-    Coef c;
-    load_coef(sg, s, c);
-    return near_pair(T, c, sg.B[s], sg.eta[s], pnx, pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
-                     eps2, stk, onb);
-}
 
 // Append this wave's buffered near pairs to the global queue with one atomic.
 // Returns true for the lanes whose query lost a pair to a full queue (those
@@ -233,22 +54,21 @@ __device__ __forceinline__ bool flush_near(const uint2* buf, int nfill, const Ne
     return lost;
 }
 
-__device__ __forceinline__ uint8_t classify(double omega, int rule) {
-    if (rule == 1) return omega > 0.5 ? 1 : 0;
-    return fabs(omega) > 0.5 ? 1 : 0;
-}
 
 // ---------------------------------------------------------------------------
 // work items: (face, tile of QPW queries), faces in descending segment count
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, int qpw, int32_t* item_offs,
-                                                      int2* item_map, int64_t map_cap, uint32_t* counters) {
+                                                      int2* item_map, int64_t map_cap, uint32_t* counters,
+                                                      int zero_near) {
     __shared__ int64_t s_sum[1024];
     const int tid = threadIdx.x;
     const int F = ft.num_faces;
     const int chunk = (F + 1023) / 1024;
     const int r0 = min(F, tid * chunk), r1 = min(F, r0 + chunk);
-    if (tid < 4) counters[tid] = 0;  // [0] item counter, [2..3] near-queue count (64-bit)
+    // [0] item counter, [2..3] near-queue count (64-bit, reset by the first build of a query only)
+    if (tid == 0) counters[0] = 0;
+    if (zero_near && (tid == 2 || tid == 3)) counters[tid] = 0;
     auto tiles_of = [&](int r) -> int64_t {
         const int f = ft.order[r];
         int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
@@ -572,7 +392,8 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats) {
+__global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats,
+                                              const uint8_t* seg_per) {
     __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
@@ -598,7 +419,12 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
                 const uint2 e = nq.qs[next + rank];
                 q = e.x;
                 if ((int64_t)q < pts.n) {
-                    const double qx = pts.u[(int64_t)q * pts.stride], qy = pts.v[(int64_t)q * pts.stride];
+                    double qx = pts.u[(int64_t)q * pts.stride], qy = pts.v[(int64_t)q * pts.stride];
+                    if (nq.shift && seg_per[e.y]) {  // periodic copy: translate the query (App. C.1)
+                        const double2 sh = nq.shift[next + rank];
+                        qx -= sh.x;
+                        qy -= sh.y;
+                    }
                     node_init(st, sg, e.y, qx, qy);
                     T = Turn{1.0, 0.0, 0};
                     onb = false;
@@ -676,9 +502,9 @@ __global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, O
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out) {
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (i >= pts.n) return;
+__global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out, int64_t q0, int64_t q1) {
+    const int64_t i = q0 + (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= q1 || i >= pts.n) return;
     const uint8_t f = out.lab[i];
     double w = out.w[i];
     uint8_t lab;
@@ -702,9 +528,9 @@ __global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out) {
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_build_items(const FaceTab& ft, const Points& pts, int qpw, int32_t* item_offs, int2* item_map,
-                              int64_t map_cap, uint32_t* counters, hipStream_t st) {
+                              int64_t map_cap, uint32_t* counters, bool zero_near, hipStream_t st) {
     hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, ft, pts, qpw, item_offs, item_map, map_cap,
-                       counters);
+                       counters, zero_near ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -742,19 +568,21 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
 }
 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       Stats stats, hipStream_t st) {
+                       Stats stats, const uint8_t* seg_per, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     if (stats.c)
-        hipLaunchKernelGGL(k_near<true>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats);
+        hipLaunchKernelGGL(k_near<true>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
+                           seg_per);
     else
-        hipLaunchKernelGGL(k_near<false>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats);
+        hipLaunchKernelGGL(k_near<false>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
+                           seg_per);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Points& pts, Out out, hipStream_t st) {
-    if (pts.n <= 0) return hipSuccess;
-    const int64_t g = (pts.n + kWG - 1) / kWG;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWG), 0, st, pts, out);
+hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, hipStream_t st) {
+    if (q1 <= q0) return hipSuccess;
+    const int64_t g = (q1 - q0 + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWG), 0, st, pts, out, q0, q1);
     return hipGetLastError();
 }
 

@@ -1,0 +1,325 @@
+// Periodic domains on the GPU (gfx950): covering-space lift and the
+// far-field pass over lifted loop copies (Sec. 4.3-4.5).
+//
+// Lift (Sec. 4.3): one lane per loop walks its segments and translates
+// segment i by o_i = o_{i-1} + T * round((end_{i-1} - start_i) / T) on each
+// periodic axis, so that the loop becomes a connected curve of the covering
+// space; v = lifted end - start, homology h = round(v / T).
+//
+// Far field over copies: a query x of a periodic face sums
+//   - extended curves (cylinder, Sec. 4.4): copies x - k v for k in the
+//     query's own window [k_lo, k_hi] plus two rays along v outside it;
+//   - contractible loops: lattice copies whose box (widened by one period)
+//     holds x;
+//   - torus pairs (eq. bandWN): families m in the query's window, each the
+//     extended curves of alpha and of the paired beta copy, shifted by t_m.
+// Each lane uses exactly its own windows (the truncation is part of the
+// definition for loops with open joints); a wave walks the union of its
+// lanes' windows and masks the lanes outside.  Segment data is read with
+// wave-uniform addresses (broadcast through the scalar/vector caches).
+#include "wn_device.h"
+
+namespace wn {
+
+__device__ __forceinline__ long iround_d(double x) { return (long)floor(x + 0.5); }
+
+__global__ __launch_bounds__(256) void k_lift(LiftArgs a, Segs sg) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.nloops) return;
+    const int l = a.loops[t];
+    const int f = a.loop_face[l];
+    const int dom = a.face_dom[f];
+    const double Tu = a.face_per[2 * f], Tv = a.face_per[2 * f + 1];
+    const bool perv = dom == 2;
+    const int s0 = a.loop_seg[l], s1 = a.loop_seg[l + 1];
+    double* p0x = const_cast<double*>(sg.p0x);
+    double* p0y = const_cast<double*>(sg.p0y);
+    double* pnx = const_cast<double*>(sg.pnx);
+    double* pny = const_cast<double*>(sg.pny);
+    double* coef = const_cast<double*>(sg.coef);
+    double ox = 0.0, oy = 0.0, ex = 0.0, ey = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const int64_t c0 = a.seg_cp[s], c1 = a.seg_cp[s + 1] - 1;
+        if (s > s0) {
+            ox += Tu * (double)iround_d((ex - a.cpu[c0]) / Tu);
+            if (perv) oy += Tv * (double)iround_d((ey - a.cpv[c0]) / Tv);
+        }
+        a.seg_off[2 * s] = ox;
+        a.seg_off[2 * s + 1] = oy;
+        ex = a.cpu[c1];
+        ey = a.cpv[c1];
+        p0x[s] = a.cpu[c0] + ox;
+        p0y[s] = a.cpv[c0] + oy;
+        pnx[s] = a.cpu[c1] + ox;
+        pny[s] = a.cpv[c1] + oy;
+        const int n = (int)(c1 - c0);
+        for (int j = 0; j <= n; ++j) {
+            double* slot = coef + ((size_t)s * kCoef + j) * 4;
+            slot[0] = a.cpu[c1 - j] * slot[2] + ox * slot[2];
+            slot[1] = a.cpv[c1 - j] * slot[2] + oy * slot[2];
+        }
+    }
+    PLoop L{};
+    L.s0 = s0;
+    L.s1 = s1;
+    if (s1 > s0) {
+        const int64_t cs = a.seg_cp[s0], ce = a.seg_cp[s1] - 1;
+        L.b0x = a.cpu[cs];
+        L.b0y = a.cpv[cs];
+        L.vx = a.cpu[ce] + a.seg_off[2 * (s1 - 1)] - L.b0x;
+        L.vy = a.cpv[ce] + a.seg_off[2 * (s1 - 1) + 1] - L.b0y;
+        L.h0 = (int)iround_d(L.vx / Tu);
+        L.h1 = perv ? (int)iround_d(L.vy / Tv) : 0;
+        L.lv = hypot(L.vx, L.vy);
+        if (L.lv > 0.0) {
+            L.dx = L.vx / L.lv;
+            L.dy = L.vy / L.lv;
+        }
+        L.bb[0] = L.bb[2] = INFINITY;
+        L.bb[1] = L.bb[3] = -INFINITY;
+        L.xi_lo = INFINITY;
+        L.xi_hi = -INFINITY;
+        for (int s = s0; s < s1; ++s) {
+            const double o0 = a.seg_off[2 * s], o1 = a.seg_off[2 * s + 1];
+            for (int64_t c = a.seg_cp[s]; c < a.seg_cp[s + 1]; ++c) {
+                const double px = a.cpu[c] + o0, py = a.cpv[c] + o1;
+                L.bb[0] = fmin(L.bb[0], px);
+                L.bb[1] = fmax(L.bb[1], px);
+                L.bb[2] = fmin(L.bb[2], py);
+                L.bb[3] = fmax(L.bb[3], py);
+                const double xi = L.dx * (px - L.b0x) + L.dy * (py - L.b0y);
+                L.xi_lo = fmin(L.xi_lo, xi);
+                L.xi_hi = fmax(L.xi_hi, xi);
+            }
+        }
+    }
+    a.out[l] = L;
+}
+
+hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st) {
+    if (a.nloops <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lift, dim3((a.nloops + 255) / 256), dim3(256), 0, st, a, sg_mut);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// periodic far-field kernel: 4 waves per workgroup, each wave owns 64 queries
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long wave_min_l(long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ long wave_max_l(long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+struct PerLane {
+    double qx, qy;
+    int64_t qi;
+    bool valid, onb;
+    Turn T;
+    int nfill;
+    int cnt;
+};
+
+// Append buffered near pairs (with their copy translation); pairs that do
+// not fit in the queue are recursed here by the lane owning the query.
+__device__ void flush_near_per(const uint2* buf, const double2* sbuf, int nfill, const NearQueue& nq, int lane,
+                               PerLane& P, const Segs& sg, double eps2, double2* stk) {
+    if (nfill == 0) return;
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(nq.count, (unsigned long long)nfill);
+    base = __shfl(base, 0);
+    for (int e = lane; e < nfill; e += kWave) {
+        if (base + (unsigned long long)e < nq.cap) {
+            nq.qs[base + e] = buf[e];
+            nq.shift[base + e] = sbuf[e];
+        }
+    }
+    if (base + (unsigned long long)nfill > nq.cap) {
+        for (int e = 0; e < nfill; ++e) {
+            if (base + (unsigned long long)e < nq.cap) continue;
+            const uint2 ent = buf[e];
+            if ((int64_t)ent.x == P.qi && !P.onb) {
+                const double2 sh = sbuf[e];
+                (void)near_from_global(P.T, sg, ent.y, P.qx - sh.x, P.qy - sh.y, eps2, stk, P.onb);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// All segments of loop L seen from the query translated by -(shx, shy);
+// lanes with act == false contribute nothing.
+__device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double shx, double shy, bool act,
+                                          PerLane& P, uint2* buf, double2* sbuf, const NearQueue& nq, int lane,
+                                          double eps2, double2* stk) {
+    const double xq = P.qx - shx, yq = P.qy - shy;
+    for (int s = L.s0; s < L.s1; ++s) {
+        const double ax = sg.p0x[s] - xq, ay = sg.p0y[s] - yq;
+        const double bx = sg.pnx[s] - xq, by = sg.pny[s] - yq;
+        const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
+        const bool work = act && P.valid && !P.onb;
+        if (work && (ra < eps2 || rb < eps2)) P.onb = true;
+        const bool far = outside_ellipse(ra, rb, sg.hb2[s]);
+        if (work && far) turn_mul(P.T, ax * bx + ay * by, ax * by - ay * bx);
+        const bool need = work && !P.onb && !far;
+        const uint64_t m = __ballot(need);
+        if (m) {
+            const int cntm = __popcll(m);
+            if (P.nfill + cntm > kNearBuf) {
+                flush_near_per(buf, sbuf, P.nfill, nq, lane, P, sg, eps2, stk);
+                P.nfill = 0;
+            }
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            if (need) {
+                buf[P.nfill + rank] = make_uint2((uint32_t)P.qi, (uint32_t)s);
+                sbuf[P.nfill + rank] = make_double2(shx, shy);
+            }
+            P.nfill += cntm;
+        }
+        if ((++P.cnt & 3) == 0) turn_norm(P.T);
+    }
+}
+
+// Extended curve of loop L (Sec. 4.4) seen from the query translated by -(sx, sy).
+__device__ __forceinline__ void extended(const Segs& sg, const PLoop& L, double sx, double sy, bool act,
+                                         PerLane& P, uint2* buf, double2* sbuf, const NearQueue& nq, int lane,
+                                         double eps2, double2* stk) {
+    const double xs = P.qx - sx, ys = P.qy - sy;
+    const double xi = L.dx * (xs - L.b0x) + L.dy * (ys - L.b0y);
+    const bool a = act && P.valid;
+    const long klo = (long)floor((xi - L.xi_hi) / L.lv) - 1;
+    const long khi = (long)ceil((xi - L.xi_lo) / L.lv) + 1;
+    const long Klo = wave_min_l(a ? klo : LONG_MAX);
+    const long Khi = wave_max_l(a ? khi : LONG_MIN);
+    for (long k = Klo; k <= Khi; ++k) {
+        const bool in = a && k >= klo && k <= khi;
+        loop_copy(sg, L, sx + (double)k * L.vx, sy + (double)k * L.vy, in, P, buf, sbuf, nq, lane, eps2, stk);
+    }
+    if (a) {
+        const double ax = L.b0x + (double)klo * L.vx - xs, ay = L.b0y + (double)klo * L.vy - ys;
+        const double bx = L.b0x + (double)(khi + 1) * L.vx - xs, by = L.b0y + (double)(khi + 1) * L.vy - ys;
+        // back ray: from direction -d to a; forward ray: from b to direction d
+        turn_mul(P.T, -L.dx * ax - L.dy * ay, -L.dx * ay + L.dy * ax);
+        turn_norm(P.T);
+        turn_mul(P.T, bx * L.dx + by * L.dy, bx * L.dy - by * L.dx);
+        turn_norm(P.T);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
+                                                      const int2* item_map, uint32_t* item_counter, NearQueue nq,
+                                                      Out out, double eps2, PerTab pt) {
+    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
+    __shared__ double2 s_nsh[kWavesPerWG][kNearBuf];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    const int total = item_offs[ft.num_faces];
+    for (int iter = 0;; ++iter) {
+        int item;
+        if (item_counter) {
+            __syncthreads();
+            if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
+            __syncthreads();
+            item = s_item;
+        } else {
+            if (iter > 0) break;
+            item = blockIdx.x;
+        }
+        if (item >= total) break;
+        const int2 mp = item_map[item];
+        const int f = mp.x, tile = mp.y;
+        int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+        qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
+        qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+        PerLane P;
+        P.qi = qb + (int64_t)tile * (kWave * kWavesPerWG) + wave * kWave + lane;
+        const bool active = P.qi < qe;
+        P.qx = P.qy = 0.0;
+        if (active) {
+            P.qx = pts.u[P.qi * pts.stride];
+            P.qy = pts.v[P.qi * pts.stride];
+        }
+        P.valid = active && fabs(P.qx) < kCoordLimit && fabs(P.qy) < kCoordLimit;
+        if (!P.valid) P.qx = P.qy = 0.0;
+        P.onb = false;
+        P.T = Turn{1.0, 0.0, 0};
+        P.nfill = 0;
+        P.cnt = 0;
+        const PFace pf = pt.face[f];
+        for (int u = pf.u0; u < pf.u1; ++u) {
+            const PUnit U = pt.unit[u];
+            if (U.kind == kUnitExtended) {
+                extended(sg, pt.loop[U.la], 0.0, 0.0, true, P, s_nbuf[wave], s_nsh[wave], nq, lane, eps2, stk);
+            } else if (U.kind == kUnitContractible) {
+                const PLoop L = pt.loop[U.la];
+                const long ilo = (long)ceil((P.qx - L.bb[1]) / pf.Tu) - 1;
+                const long ihi = (long)floor((P.qx - L.bb[0]) / pf.Tu) + 1;
+                long jlo = 0, jhi = 0;
+                if (pf.dom == 2) {
+                    jlo = (long)ceil((P.qy - L.bb[3]) / pf.Tv) - 1;
+                    jhi = (long)floor((P.qy - L.bb[2]) / pf.Tv) + 1;
+                }
+                const long Ilo = wave_min_l(P.valid ? ilo : LONG_MAX), Ihi = wave_max_l(P.valid ? ihi : LONG_MIN);
+                const long Jlo = wave_min_l(P.valid ? jlo : LONG_MAX), Jhi = wave_max_l(P.valid ? jhi : LONG_MIN);
+                for (long i = Ilo; i <= Ihi; ++i)
+                    for (long j = Jlo; j <= Jhi; ++j) {
+                        const bool in = P.valid && i >= ilo && i <= ihi && j >= jlo && j <= jhi;
+                        loop_copy(sg, L, (double)i * pf.Tu, (double)j * pf.Tv, in, P, s_nbuf[wave], s_nsh[wave], nq,
+                                  lane, eps2, stk);
+                    }
+            } else {
+                const PLoop La = pt.loop[U.la];
+                const double eta = pf.nx * (P.qx - La.b0x) + pf.ny * (P.qy - La.b0y);
+                const long mlo = (long)floor((eta - U.eta_hi) / pf.Delta) - 1;
+                const long mhi = (long)ceil((eta - U.eta_lo) / pf.Delta) + 1;
+                const long Mlo = wave_min_l(P.valid ? mlo : LONG_MAX), Mhi = wave_max_l(P.valid ? mhi : LONG_MIN);
+                for (long m = Mlo; m <= Mhi; ++m) {
+                    const bool in = P.valid && m >= mlo && m <= mhi;
+                    const double tx = (double)m * pf.t1x, ty = (double)m * pf.t1y;
+                    extended(sg, La, tx, ty, in, P, s_nbuf[wave], s_nsh[wave], nq, lane, eps2, stk);
+                    extended(sg, pt.loop[U.lb], tx + U.pshx, ty + U.pshy, in, P, s_nbuf[wave], s_nsh[wave], nq, lane,
+                             eps2, stk);
+                }
+            }
+        }
+        flush_near_per(s_nbuf[wave], s_nsh[wave], P.nfill, nq, lane, P, sg, eps2, stk);
+        if (active) {
+            out.w[P.qi] = turn_angle(P.T);
+            out.lab[P.qi] = !P.valid ? 3 : (P.onb ? 2 : 0);
+        }
+    }
+}
+
+hipError_t launch_far_periodic(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+                               const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
+                               double eps2, PerTab pt, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_far_periodic, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+                       item_counter, nq, out, eps2, pt);
+    return hipGetLastError();
+}
+
+int far_periodic_blocks_per_cu() {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far_periodic, kWG, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+}  // namespace wn

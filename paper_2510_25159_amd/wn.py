@@ -26,8 +26,8 @@ EXPORTS = [
     "wn_destroy_faces", "wn_status_string", "wn_segment_bound", "wn_get_faces_info",
     "wn_profile_create", "wn_profile_collect", "wn_profile_destroy",
 ]
-KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO = 0, 1, 2, 3, 4
-KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo"}
+KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO, KERNEL_FAR_PERIODIC = 0, 1, 2, 3, 4, 5
+KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo", 5: "k_far_periodic"}
 KERNEL_KINDS = 8
 STAT_NAMES = ["near_pairs", "splits", "leaves", "reevals", "near_flops", "max_depth"]
 STATS_COUNT = 8
@@ -60,6 +60,7 @@ class wn_query_opts(ctypes.Structure):
 
 class wn_faces_info(ctypes.Structure):
     _fields_ = [("num_faces", ctypes.c_int32), ("num_loops", ctypes.c_int32), ("num_segments", ctypes.c_int32),
+                ("num_periodic_faces", ctypes.c_int32),
                 ("max_segments_per_face", ctypes.c_int32), ("max_depth_bound", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64)]
 

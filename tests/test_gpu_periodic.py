@@ -1,0 +1,105 @@
+"""GPU parity on periodic faces (cylinder / torus, Sec. 4.3-4.5): the HIP
+library's lift, pairing and copy windows against the CPU oracle."""
+import numpy as np
+import pytest
+
+from paper_2510_25159_amd import workloads as W
+from tests.gpu_helpers import compare, run_wn
+
+pytestmark = pytest.mark.gpu
+T = 2 * np.pi
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_25159_amd import wn
+
+    wn.lib()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def c3_small(oracle_lib):
+    f, q = W.config3(face_ids=range(32))
+    w, near = oracle_lib.query_faces(f, q)
+    return f, q, w, near
+
+
+@pytest.mark.parametrize("schedule", [1, 0])
+def test_config3_subset_parity(torch_cuda, c3_small, schedule):
+    f, q, w_o, n_o = c3_small
+    print(f"config3[0:32] schedule={schedule} points={q.num_points}", flush=True)
+    w, lab = run_wn(f, q, schedule=schedule)
+    st = compare(w, lab, w_o, n_o)
+    assert st["compared"] > 0.99 * q.num_points
+
+
+def test_closed_noise_free_bands(torch_cuda, oracle_lib):
+    f, q = W.config3(face_ids=range(40, 56), sigma=0.0, open_frac=0.0)
+    w_o, n_o = oracle_lib.query_faces(f, q)
+    w, lab = run_wn(f, q, schedule=1)
+    compare(w, lab, w_o, n_o)
+    ok = lab < 2
+    assert np.max(np.abs(w[ok] - np.round(w[ok]))) < 1e-12
+
+
+def test_mixed_planar_and_periodic_faces(torch_cuda, oracle_lib):
+    """Planar and periodic faces in one handle and one query."""
+    fp, qp = W.config2(face_ids=[0, 1])
+    fc, qc = W.config3(face_ids=[2, 3])
+    loops = []
+
+    def loops_of(faces, fi):
+        out = []
+        for l in range(faces.face_loop_offsets[fi], faces.face_loop_offsets[fi + 1]):
+            segs = []
+            for s in range(faces.loop_seg_offsets[l], faces.loop_seg_offsets[l + 1]):
+                a, b = faces.seg_cp_offsets[s], faces.seg_cp_offsets[s + 1]
+                cp = np.column_stack([faces.cp_u[a:b], faces.cp_v[a:b]])
+                segs.append((cp, None if faces.cp_w is None else faces.cp_w[a:b]))
+            out.append(segs)
+        return out
+
+    face_loops = [loops_of(fp, 0), loops_of(fc, 0), loops_of(fp, 1), loops_of(fc, 1)]
+    faces = W.faces_from_loops(face_loops, domains=[0, fc.face_domain[0], 0, fc.face_domain[1]],
+                               periods=[[0, 0], [T, T], [0, 0], [T, T]], rational=True)
+    pts = [np.column_stack([qp.u[qp.face_point_offsets[0]:qp.face_point_offsets[1]],
+                            qp.v[qp.face_point_offsets[0]:qp.face_point_offsets[1]]]),
+           np.column_stack([qc.u[:2048], qc.v[:2048]]),
+           np.column_stack([qp.u[qp.face_point_offsets[1]:qp.face_point_offsets[2]],
+                            qp.v[qp.face_point_offsets[1]:qp.face_point_offsets[2]]]),
+           np.column_stack([qc.u[2048:], qc.v[2048:]])]
+    q = W.queries_for_faces(pts)
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    for sched in (0, 1):
+        w, lab = run_wn(faces, q, schedule=sched)
+        compare(w, lab, w_o, n_o)
+
+
+def test_topology_error_reported(torch_cuda):
+    from paper_2510_25159_amd import wn
+
+    rng = np.random.default_rng(1)
+    a = W.WrappedCurve((0.5, 0.5), (2 * T, 3 * T), 0.0, rng)
+    lp = W.periodic_loop(a, 9, (T, T), (0, 1))
+    f = W.faces_from_loops([[[(cp, None) for cp in lp.cps]]], domains=[W.DOMAIN_TORUS], periods=[[T, T]])
+    with pytest.raises(wn.WnError) as ei:
+        wn.FaceSet(f)
+    assert ei.value.status == wn.WN_E_TOPOLOGY
+
+
+def test_config3_full_sampled(torch_cuda, oracle_lib):
+    """Full periodic set (512 faces, 2^20 points), sampled parity."""
+    f, q = W.config3()
+    w, lab = run_wn(f, q, schedule=1)
+    rng = np.random.default_rng(3)
+    idx = np.sort(rng.choice(q.num_points, 30000, replace=False))
+    pf, u, v = W.subset_queries(q, idx)
+    w_o, n_o = oracle_lib.query(f, pf, u, v)
+    st = compare(w[idx], lab[idx], w_o, n_o)
+    print(st, flush=True)
+    assert set(np.unique(lab)).issubset({0, 1, 2})
