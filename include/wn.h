@@ -128,7 +128,25 @@ enum {
     WN_KERNEL_FINALIZE = 3,
     WN_KERNEL_REDO = 4,
     WN_KERNEL_FAR_PERIODIC = 5,
+    WN_KERNEL_BIN = 6,
     WN_KERNEL_KINDS = 8
+};
+
+/* Learned depth predictor: an MLP 16 -> 64 -> 64 -> 1 (ReLU; BF16 weights,
+ * FP32 accumulation; FP32 master weights for training) that predicts the
+ * recursion depth Alg. 1 reaches on a near pair (root ellipse test failed)
+ * from 16 features of the pair, used to order the near queue into
+ * uniform-depth bins (WN_SCHED_BINNED).  Binning never changes results. */
+typedef struct wn_predictor wn_predictor;
+#define WN_MLP_IN 16
+#define WN_MLP_HIDDEN 64
+#define WN_MLP_PARAMS (WN_MLP_IN * WN_MLP_HIDDEN + WN_MLP_HIDDEN + WN_MLP_HIDDEN * WN_MLP_HIDDEN + WN_MLP_HIDDEN + WN_MLP_HIDDEN + 1)
+/* Where WN_SCHED_BINNED takes the depth of each near pair from. */
+enum {
+    WN_BIN_PREDICTOR = 0, /* the MLP (falls back to WN_BIN_NONE without a predictor) */
+    WN_BIN_HEURISTIC = 1, /* ceil(log2(B / max(eps, distance from the query to the chord))) */
+    WN_BIN_MEASURED = 2,  /* depths measured by a first, discarded near pass (upper bound) */
+    WN_BIN_NONE = 3       /* no reordering (the unbinned queue) */
 };
 
 /* Per-call overrides and diagnostics (all fields optional: 0/NULL = default). */
@@ -147,6 +165,8 @@ typedef struct {
     wn_profile* profile;     /* NULL, or a profile that records kernel durations            */
     unsigned long long* stats; /* NULL, or device [WN_STATS_COUNT] counters the batched
                                   schedules ADD to (zero them first): see WN_STAT_*          */
+    const wn_predictor* predictor; /* WN_SCHED_BINNED with WN_BIN_PREDICTOR                  */
+    int32_t bin_source;      /* WN_BIN_* (WN_SCHED_BINNED only)                             */
 } wn_query_opts;
 
 /* Work counters of the batched schedules (wn_query_opts.stats). */
@@ -214,6 +234,69 @@ wn_status wn_profile_create(int32_t capacity, wn_profile** out);
  * profile for reuse. */
 wn_status wn_profile_collect(wn_profile* p, int64_t* launches, double* total_ms);
 void wn_profile_destroy(wn_profile* p);
+
+/* Training options (0 = default in brackets) and report. */
+typedef struct {
+    int32_t epochs;       /* [8] passes over the samples                                   */
+    int32_t batch;        /* [4096] samples per AdamW step                                 */
+    float lr;             /* [2e-3] AdamW learning rate                                    */
+    float weight_decay;   /* [1e-4] decoupled weight decay                                 */
+    float huber_delta;    /* [1.0] Huber loss threshold                                    */
+    float holdout;        /* [0.1] fraction of samples kept out of training for the report */
+    int32_t seed;         /* shuffling seed                                                */
+    int64_t max_samples;  /* [0 = all] cap on the near pairs used                          */
+} wn_train_opts;
+
+typedef struct {
+    int64_t samples;        /* near pairs collected (root ellipse test failed)            */
+    int64_t train_samples;
+    int32_t steps;
+    float final_train_loss; /* mean Huber loss of the last epoch                          */
+    float holdout_mae;      /* mean |predicted - measured depth| on the holdout            */
+    float baseline_mae;     /* same, predicting the training mean depth (no network)       */
+    float heuristic_mae;    /* same, predicting the analytic heuristic                     */
+    float mean_depth;       /* training mean depth                                         */
+} wn_train_report;
+
+/* Create a predictor with weights drawn from a seeded He-uniform
+ * initialisation (host, deterministic) and uploaded to the current device. */
+wn_status wn_predictor_create(int32_t seed, wn_predictor** out);
+void wn_predictor_destroy(wn_predictor* p);
+
+/* Collect every near pair of `points` against `faces` (batched far pass),
+ * measure its depth with the near pass itself (labels), build the features,
+ * standardise them, and train the MLP on the GPU (forward, backward, AdamW
+ * kernels).  Synchronous.  `opts` and `report` may be NULL. */
+wn_status wn_predictor_train(wn_predictor* p, const wn_faces* faces, const wn_points* points,
+                             const wn_train_opts* opts, wn_train_report* report, void* stream);
+
+/* FP32 master parameters (host [WN_MLP_PARAMS], layout W1[64][16], b1[64],
+ * W2[64][64], b2[64], w3[64], b3) and the feature standardisation (host
+ * [2 * WN_MLP_IN]: means then standard deviations).  set_* also refreshes
+ * the BF16 copy. */
+wn_status wn_predictor_get_params(const wn_predictor* p, float* params, float* feature_norm);
+wn_status wn_predictor_set_params(wn_predictor* p, const float* params, const float* feature_norm);
+
+/* Mean Huber loss and its gradient with respect to the FP32 master
+ * parameters over n standardised feature rows (device [n][16]) and labels
+ * (device [n]); forward in BF16-rounded weights as in inference.  Host
+ * outputs; synchronous.  (Gradient checks.) */
+wn_status wn_predictor_loss_grad(const wn_predictor* p, const float* features, const float* labels, int64_t n,
+                                 float huber_delta, float* loss, float* grad, void* stream);
+
+/* Predicted depth for n standardised feature rows (device in/out). */
+wn_status wn_predictor_predict(const wn_predictor* p, const float* features, int64_t n, float* out, void* stream);
+
+/* Raw (unstandardised) features of given (point, segment) pairs: pair k is
+ * point pair_point[k] of `points` against segment pair_segment[k] (global
+ * index, as lifted for periodic faces) -> device [n][16].  pair_point,
+ * pair_segment: device int32 [n].  Features: query in the ellipse frame
+ * (2, in units of B/2), semi-axes B/2 and sqrt((B/2)^2 - (L/2)^2), degree,
+ * min/max weight, chord length L, distance to the control-point box, the two
+ * end-point distances, (d1+d2)/B, log2(B/max(eps, box distance)), B, L/2, the
+ * side of the chord. */
+wn_status wn_pair_features(const wn_faces* faces, const wn_points* points, const int32_t* pair_point,
+                           const int32_t* pair_segment, int64_t n, float* out, void* stream);
 
 /* Summary of a created handle (host copy of sizes). */
 typedef struct {

@@ -1,7 +1,7 @@
 // Host side of the winding-number library: validation, per-segment bounds,
 // device packing and query scheduling behind the C ABI of include/wn.h.
-#include "../../include/wn.h"
-#include "wn_internal.h"
+#include "wn_host_internal.h"
+#include "wn_learn.h"
 #include "wn_topology.h"
 
 #include <math.h>
@@ -14,30 +14,13 @@
 
 using namespace wn;
 
-struct wn_faces {
-    int device = 0;
-    void* dmem = nullptr;
-    int64_t dbytes = 0;
-    Segs sg{};
-    FaceTab ft_plan{};   // planar faces, largest first
-    FaceTab ft_per{};    // periodic faces, largest first
-    PerTab pt{};
-    int32_t num_faces = 0, num_loops = 0, num_segments = 0;
-    int32_t num_planar = 0, num_periodic = 0;
-    int32_t max_spf = 0, max_depth = 0;
-    double eps = 1e-10, eps2 = 1e-20;
-    int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
-    int cu_count = 0;
-    std::vector<int32_t> h_seg_begin;
-    std::vector<int32_t> h_dom;
-    std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
-};
-
-struct wn_profile {
-    std::vector<hipEvent_t> ev;  // 2 per slot
-    std::vector<int> kind;
-    int used = 0;
-};
+namespace wn {
+wn_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return WN_OK;
+    if (e == hipErrorOutOfMemory) return WN_E_NOMEM;
+    return WN_E_DEVICE;
+}
+}  // namespace wn
 
 namespace {
 
@@ -63,11 +46,6 @@ constexpr int kBinom[kCoef][kCoef] = {{1, 0, 0, 0, 0, 0}, {1, 1, 0, 0, 0, 0},  {
 
 bool finite_small(double x) { return isfinite(x) && fabs(x) < kCoordLimit; }
 
-wn_status hip_status(hipError_t e) {
-    if (e == hipSuccess) return WN_OK;
-    if (e == hipErrorOutOfMemory) return WN_E_NOMEM;
-    return WN_E_DEVICE;
-}
 
 // Lemma 1 / App. A.1 bound for one segment (no validation).
 double segment_bound(const double* u, const double* v, const double* w, int n) {
@@ -213,6 +191,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     std::vector<double> p0x(S), p0y(S), pnx(S), pny(S), hb2(S), Bv(S), eta(S);
     std::vector<double> coef((size_t)S * kCoef * 4, 0.0);
     std::vector<uint8_t> deg(S), rat(S), segper(S, 0);
+    std::vector<double> box((size_t)S * 4);
+    std::vector<float> wrange((size_t)S * 2);
     int32_t maxd = 0;
     for (int32_t f = 0; f < F; ++f) {
         const double e = 8.0 * 1.1102230246251565e-16 * (1.0 + face_scale[f]);
@@ -240,6 +220,23 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
             deg[s] = (uint8_t)n;
             rat[s] = is_rat ? 1 : 0;
             segper[s] = dom[f] != WN_DOMAIN_PLANE ? 1 : 0;
+            double* bx = &box[4 * (size_t)s];
+            bx[0] = bx[1] = u[0];
+            bx[2] = bx[3] = v[0];
+            float wl = 1.f, wh = 1.f;
+            if (is_rat) wl = wh = (float)w[0];
+            for (int i = 0; i <= n; ++i) {
+                bx[0] = std::min(bx[0], u[i]);
+                bx[1] = std::max(bx[1], u[i]);
+                bx[2] = std::min(bx[2], v[i]);
+                bx[3] = std::max(bx[3], v[i]);
+                if (is_rat) {
+                    wl = std::min(wl, (float)w[i]);
+                    wh = std::max(wh, (float)w[i]);
+                }
+            }
+            wrange[2 * (size_t)s] = wl;
+            wrange[2 * (size_t)s + 1] = wh;
             for (int j = 0; j <= n; ++j) {
                 const int i = n - j;
                 const double wi = is_rat ? w[i] : 1.0;
@@ -293,6 +290,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     const size_t o_hb2 = add(hb2.data(), S * 8), o_B = add(Bv.data(), S * 8), o_eta = add(eta.data(), S * 8);
     const size_t o_coef = add(coef.data(), coef.size() * 8);
     const size_t o_deg = add(deg.data(), S), o_rat = add(rat.data(), S), o_sper = add(segper.data(), S);
+    const size_t o_box = add(box.data(), box.size() * 8), o_wr = add(wrange.data(), wrange.size() * 4);
     const size_t o_sb = add(h->h_seg_begin.data(), ((size_t)F + 1) * 4);
     const size_t o_op = add(ord_plan.data(), ord_plan.size() * 4), o_oq = add(ord_per.data(), ord_per.size() * 4);
     // periodic tables (filled after the lift)
@@ -330,6 +328,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->sg.coef = (const double*)(base + o_coef);
     h->sg.deg = (const uint8_t*)(base + o_deg);
     h->sg.rat = (const uint8_t*)(base + o_rat);
+    h->sg.box = (const double*)(base + o_box);
+    h->sg.wrange = (const float*)(base + o_wr);
     const int32_t* d_sb = (const int32_t*)(base + o_sb);
     h->ft_plan = FaceTab{d_sb, (const int32_t*)(base + o_op), (int32_t)ord_plan.size()};
     h->ft_per = FaceTab{d_sb, (const int32_t*)(base + o_oq), (int32_t)ord_per.size()};
@@ -530,7 +530,7 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     if (q.queries_per_wg != 0 && q.queries_per_wg != 64 && q.queries_per_wg != 128 && q.queries_per_wg != 256)
         return WN_E_INVALID;
     if (q.queue_policy < 0 || q.queue_policy > 2 || q.near_capacity < 0) return WN_E_INVALID;
-    if (prec == WN_PREC_MIXED || sched == WN_SCHED_BINNED) return WN_E_UNSUPPORTED;
+    if (prec == WN_PREC_MIXED) return WN_E_UNSUPPORTED;
     if (q.depth_log && sched != WN_SCHED_PLAIN) return WN_E_UNSUPPORTED;
     const int64_t N = p->num_points;
     const int32_t F = h->num_faces;
@@ -550,32 +550,16 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     const bool periodic = h->num_periodic > 0;
     hipError_t e = hipSuccess;
 
-    // scratch: item tables, counters, near queue (+ copy translations), temporaries
     const bool plain = sched == WN_SCHED_PLAIN;
-    const int64_t max_items = N / 64 + F + 1;
+    const bool binned = sched == WN_SCHED_BINNED && q.bin_source != WN_BIN_NONE &&
+                        !(q.bin_source == WN_BIN_PREDICTOR && !q.predictor);
+    if (q.bin_source < 0 || q.bin_source > WN_BIN_NONE) return WN_E_INVALID;
     int64_t cap = q.near_capacity > 0 ? q.near_capacity : 8 * N + 65536;
     cap = std::min<int64_t>(cap, (int64_t)1 << 34);
     if (plain) cap = 0;  // periodic faces of the plain schedule recurse in line
-    size_t total = 0;
-    auto take = [&](size_t bytes) {
-        const size_t off = total;
-        total += (bytes + 255) & ~(size_t)255;
-        return off;
-    };
-    const size_t o_io = take(((size_t)F + 1) * 4), o_im = take((size_t)max_items * 8), o_ct = take(16);
-    const size_t o_nq = take((size_t)cap * 8), o_sh = take(periodic ? (size_t)cap * 16 : 0);
-    const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
-    void* scratch = nullptr;
-    e = hipMallocAsync(&scratch, total, st);
+    Scratch sc;
+    e = scratch_alloc(h, N, cap, binned, binned && q.bin_source == WN_BIN_MEASURED, out_w, out_lab, rule, sc, st);
     if (e != hipSuccess) return hip_status(e);
-    char* b = (char*)scratch;
-    int32_t* item_offs = (int32_t*)(b + o_io);
-    int2* item_map = (int2*)(b + o_im);
-    uint32_t* counters = (uint32_t*)(b + o_ct);
-    NearQueue nq{(uint2*)(b + o_nq), periodic ? (double2*)(b + o_sh) : nullptr, (unsigned long long*)(counters + 2),
-                 (uint64_t)cap};
-    Out out{out_w ? out_w : (double*)(b + o_w), out_lab ? out_lab : (uint8_t*)(b + o_l), nullptr, 0, rule};
-    bool zero_near = true;
 
     if (plain) {
         std::vector<int64_t> offs;
@@ -587,12 +571,13 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
             bool ok = e == hipSuccess && offs[0] == 0 && offs[F] == N;
             for (int32_t f = 0; ok && f < F; ++f) ok = offs[f + 1] >= offs[f];
             if (!ok) {
-                (void)hipFreeAsync(scratch, st);
+                scratch_free(sc, st);
                 return e != hipSuccess ? hip_status(e) : WN_E_INVALID;
             }
             ho = offs.data();
         }
-        const Out pout{out.w, out.lab, q.depth_log, h->max_spf, rule};
+        const Out pout{sc.out.w, sc.out.lab, q.depth_log, h->max_spf, rule};
+        bool zero_near = true;
         for (int32_t f = 0; f < F && e == hipSuccess; ++f) {
             const int64_t nf = ho[f + 1] - ho[f];
             if (nf == 0) continue;
@@ -603,65 +588,150 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
             } else {
                 // one-face item table, in-line recursion (queue capacity 0), finalize of its range
                 const FaceTab one{h->ft_per.seg_begin, h->ft_per.order + h->per_pos[f], 1};
-                e = launch_build_items(one, pts, 256, item_offs, item_map, max_items, counters, zero_near, st);
+                e = launch_build_items(one, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters, zero_near,
+                                       st);
                 zero_near = false;
                 if (e == hipSuccess)
-                    e = launch_far_periodic(h->sg, one, pts, item_offs, item_map, nullptr, (nf + 255) / 256, nq, out,
-                                            h->eps2, h->pt, st);
-                if (e == hipSuccess) e = launch_finalize(pts, out, ho[f], ho[f + 1], st);
+                    e = launch_far_periodic(h->sg, one, pts, sc.item_offs, sc.item_map, nullptr, (nf + 255) / 256,
+                                            sc.nq, sc.out, h->eps2, h->pt, st);
+                if (e == hipSuccess) e = launch_finalize(pts, sc.out, ho[f], ho[f + 1], st);
             }
         }
-        const hipError_t e2 = hipFreeAsync(scratch, st);
-        if (e == hipSuccess) e = e2;
+        scratch_free(sc, st);
         return hip_status(e);
     }
 
-    // batched: persistent far launches (planar, periodic), near queue, finalize
-    if (h->num_planar > 0) {
-        {
-            ProfScope ps(q.profile, WN_KERNEL_ITEMS, st);
-            e = launch_build_items(h->ft_plan, pts, qpw, item_offs, item_map, max_items, counters, zero_near, st);
-            zero_near = false;
+    // batched / binned: persistent far launches, (binning), near pass, finalize, redo
+    e = far_passes(h, pts, qpw, q.queue_policy, sc, q.profile, st);
+    NearQueue nq = sc.nq;
+    if (e == hipSuccess && binned) {
+        const wn_predictor* pr = q.predictor;
+        if (q.bin_source == WN_BIN_MEASURED) {
+            // first near pass into throw-away outputs, logging each entry's depth
+            const Out tmp{sc.w_tmp, sc.lab_tmp, nullptr, 0, rule};
+            e = near_pass(h, pts, sc.nq, tmp, nullptr, sc.depth, nullptr, st);
         }
         if (e == hipSuccess) {
-            const bool persistent = q.queue_policy != 2;
-            const int64_t grid = persistent ? (int64_t)h->cu_count * far_blocks_per_cu(false, qpw) : max_items;
-            ProfScope ps(q.profile, WN_KERNEL_FAR, st);
-            e = launch_far(false, qpw, h->sg, h->ft_plan, pts, item_offs, item_map, persistent ? counters : nullptr,
-                           -1, grid, nq, out, h->eps2, st);
+            ProfScope ps(q.profile, WN_KERNEL_BIN, st);
+            e = launch_binning(h->sg, pts, sc.nq, h->pt.seg_periodic, h->eps, q.bin_source,
+                               pr ? pr->d_wbf : nullptr, pr ? pr->d_norm : nullptr, sc.depth, sc.bins, sc.wg_hist,
+                               binning_grid(h), sc.qs2, sc.sh2, st);
         }
+        nq.qs = sc.qs2;
+        nq.shift = sc.sh2;
     }
-    if (e == hipSuccess && periodic) {
-        {
-            ProfScope ps(q.profile, WN_KERNEL_ITEMS, st);
-            e = launch_build_items(h->ft_per, pts, 256, item_offs, item_map, max_items, counters, zero_near, st);
-            zero_near = false;
-        }
-        if (e == hipSuccess) {
-            const bool persistent = q.queue_policy != 2;
-            const int64_t grid = persistent ? (int64_t)h->cu_count * far_periodic_blocks_per_cu() : max_items;
-            ProfScope ps(q.profile, WN_KERNEL_FAR_PERIODIC, st);
-            e = launch_far_periodic(h->sg, h->ft_per, pts, item_offs, item_map, persistent ? counters : nullptr, grid,
-                                    nq, out, h->eps2, h->pt, st);
-        }
-    }
-    if (e == hipSuccess) {
-        ProfScope ps(q.profile, WN_KERNEL_NEAR, st);
-        e = launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), Stats{q.stats},
-                        h->pt.seg_periodic, st);
-    }
+    if (e == hipSuccess) e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st);
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_FINALIZE, st);
-        e = launch_finalize(pts, out, 0, N, st);
+        e = launch_finalize(pts, sc.out, 0, N, st);
     }
     if (e == hipSuccess && h->num_planar > 0) {
         ProfScope ps(q.profile, WN_KERNEL_REDO, st);
-        e = launch_redo(h->sg, FaceTab{h->ft_plan.seg_begin, nullptr, F}, pts, out, h->eps2, st);
+        e = launch_redo(h->sg, FaceTab{h->ft_plan.seg_begin, nullptr, F}, pts, sc.out, h->eps2, st);
     }
-    const hipError_t e2 = hipFreeAsync(scratch, st);
-    if (e == hipSuccess) e = e2;
+    scratch_free(sc, st);
     return hip_status(e);
 }
+
+}  // extern "C"
+
+namespace wn {
+
+hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned, bool depth, double* out_w,
+                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st) {
+    const bool periodic = h->num_periodic > 0;
+    const int32_t F = h->num_faces;
+    sc.max_items = N / 64 + F + 1;
+    size_t total = 0;
+    auto take = [&](size_t bytes) {
+        const size_t off = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return off;
+    };
+    const int G = binning_grid(h);
+    const size_t o_io = take(((size_t)F + 1) * 4), o_im = take((size_t)sc.max_items * 8), o_ct = take(16);
+    const size_t o_nq = take((size_t)cap * 8), o_sh = take(periodic ? (size_t)cap * 16 : 0);
+    const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
+    const size_t o_q2 = take(binned ? (size_t)cap * 8 : 0), o_s2 = take(binned && periodic ? (size_t)cap * 16 : 0);
+    const size_t o_bn = take(binned ? (size_t)cap : 0), o_wh = take(binned ? (size_t)G * 32 * 4 : 0);
+    const size_t o_dp = take(depth ? (size_t)cap : 0);
+    const size_t o_wt = take(depth ? (size_t)N * 8 : 0), o_lt = take(depth ? (size_t)N : 0);
+    const hipError_t e = hipMallocAsync(&sc.base, total, st);
+    if (e != hipSuccess) return e;
+    char* b = (char*)sc.base;
+    sc.item_offs = (int32_t*)(b + o_io);
+    sc.item_map = (int2*)(b + o_im);
+    sc.counters = (uint32_t*)(b + o_ct);
+    sc.nq = NearQueue{(uint2*)(b + o_nq), periodic ? (double2*)(b + o_sh) : nullptr,
+                      (unsigned long long*)(sc.counters + 2), (uint64_t)cap};
+    sc.out = Out{out_w ? out_w : (double*)(b + o_w), out_lab ? out_lab : (uint8_t*)(b + o_l), nullptr, 0, rule};
+    if (binned) {
+        sc.qs2 = (uint2*)(b + o_q2);
+        sc.sh2 = periodic ? (double2*)(b + o_s2) : nullptr;
+        sc.bins = (uint8_t*)(b + o_bn);
+        sc.wg_hist = (uint32_t*)(b + o_wh);
+    }
+    if (depth) {
+        sc.depth = (uint8_t*)(b + o_dp);
+        sc.w_tmp = (double*)(b + o_wt);
+        sc.lab_tmp = (uint8_t*)(b + o_lt);
+    }
+    return hipSuccess;
+}
+
+void scratch_free(Scratch& sc, hipStream_t st) {
+    if (sc.base) (void)hipFreeAsync(sc.base, st);
+    sc.base = nullptr;
+}
+
+int binning_grid(const wn_faces* h) { return std::max(1, h->cu_count * 4); }
+
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, Scratch& sc, wn_profile* prof,
+                      hipStream_t st) {
+    hipError_t e = hipSuccess;
+    bool zero_near = true;
+    const bool persistent = policy != 2;
+    if (h->num_planar > 0) {
+        {
+            ProfScope ps(prof, WN_KERNEL_ITEMS, st);
+            e = launch_build_items(h->ft_plan, pts, qpw, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
+                                   zero_near, st);
+            zero_near = false;
+        }
+        if (e == hipSuccess) {
+            const int64_t grid = persistent ? (int64_t)h->cu_count * far_blocks_per_cu(false, qpw) : sc.max_items;
+            ProfScope ps(prof, WN_KERNEL_FAR, st);
+            e = launch_far(false, qpw, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
+                           persistent ? sc.counters : nullptr, -1, grid, sc.nq, sc.out, h->eps2, st);
+        }
+    }
+    if (e == hipSuccess && h->num_periodic > 0) {
+        {
+            ProfScope ps(prof, WN_KERNEL_ITEMS, st);
+            e = launch_build_items(h->ft_per, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
+                                   zero_near, st);
+            zero_near = false;
+        }
+        if (e == hipSuccess) {
+            const int64_t grid = persistent ? (int64_t)h->cu_count * far_periodic_blocks_per_cu() : sc.max_items;
+            ProfScope ps(prof, WN_KERNEL_FAR_PERIODIC, st);
+            e = launch_far_periodic(h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
+                                    persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, st);
+        }
+    }
+    return e;
+}
+
+hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
+                     uint8_t* entry_depth, wn_profile* prof, hipStream_t st) {
+    ProfScope ps(prof, WN_KERNEL_NEAR, st);
+    return launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), Stats{stats},
+                       h->pt.seg_periodic, entry_depth, st);
+}
+
+}  // namespace wn
+
+extern "C" {
 
 wn_status wn_query(const wn_faces* h, const wn_points* p, double* out_w, uint8_t* out_lab, void* stream) {
     return wn_query_ex(h, p, out_w, out_lab, nullptr, stream);

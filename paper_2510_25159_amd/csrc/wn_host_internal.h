@@ -1,0 +1,83 @@
+// Host-side internals shared by the library's host sources.
+#pragma once
+
+#include "../../include/wn.h"
+#include "wn_internal.h"
+
+#include <vector>
+
+struct wn_faces {
+    int device = 0;
+    void* dmem = nullptr;
+    int64_t dbytes = 0;
+    wn::Segs sg{};
+    wn::FaceTab ft_plan{};   // planar faces, largest first
+    wn::FaceTab ft_per{};    // periodic faces, largest first
+    wn::PerTab pt{};
+    int32_t num_faces = 0, num_loops = 0, num_segments = 0;
+    int32_t num_planar = 0, num_periodic = 0;
+    int32_t max_spf = 0, max_depth = 0;
+    double eps = 1e-10, eps2 = 1e-20;
+    int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
+    int cu_count = 0;
+    std::vector<int32_t> h_seg_begin;
+    std::vector<int32_t> h_dom;
+    std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
+};
+
+struct wn_profile {
+    std::vector<hipEvent_t> ev;  // 2 per slot
+    std::vector<int> kind;
+    int used = 0;
+};
+
+
+struct wn_predictor {
+    int device = 0;
+    float* d_master = nullptr;  // [P] FP32 master parameters
+    float* d_m = nullptr;       // [P] AdamW first moment
+    float* d_v = nullptr;       // [P] AdamW second moment
+    float* d_wbf = nullptr;     // [P] BF16-rounded parameters used by the kernels
+    float* d_norm = nullptr;    // [32] feature means, standard deviations
+    void* dmem = nullptr;
+    int step = 0;
+};
+
+namespace wn {
+
+// Per-call device scratch of the batched schedules.
+struct Scratch {
+    void* base = nullptr;
+    int32_t* item_offs = nullptr;
+    int2* item_map = nullptr;
+    uint32_t* counters = nullptr;
+    int64_t max_items = 0;
+    NearQueue nq{};
+    Out out{};
+    // binned schedule
+    uint2* qs2 = nullptr;
+    double2* sh2 = nullptr;
+    uint8_t* bins = nullptr;
+    uint32_t* wg_hist = nullptr;
+    uint8_t* depth = nullptr;
+    double* w_tmp = nullptr;
+    uint8_t* lab_tmp = nullptr;
+};
+
+// Allocate (stream-ordered) scratch for N points; outputs the caller did
+// not provide are allocated too.  binned adds the binning buffers.
+hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned, bool depth, double* out_w,
+                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st);
+void scratch_free(Scratch& sc, hipStream_t st);
+
+// Item build + persistent far passes (planar, periodic) filling sc.nq.
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, Scratch& sc, wn_profile* prof,
+                      hipStream_t st);
+// Near pass over nq; entry_depth optional.
+hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
+                     uint8_t* entry_depth, wn_profile* prof, hipStream_t st);
+int binning_grid(const wn_faces* h);
+
+wn_status hip_status(hipError_t e);
+
+}  // namespace wn

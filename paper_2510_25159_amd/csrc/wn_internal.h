@@ -39,6 +39,8 @@ struct Segs {
     const double* coef; // [S][kCoef][4]: slot j = (x, y, w, 0) of C(n, n-j) w_{n-j} P_{n-j}
     const uint8_t* deg; // [S] degree 1..5
     const uint8_t* rat; // [S] 1 if any weight != 1
+    const double* box;  // [S][4] control-point box umin, umax, vmin, vmax (lifted for periodic faces)
+    const float* wrange;// [S][2] min, max weight
 };
 
 struct FaceTab {
@@ -134,7 +136,7 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
                       const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       Stats stats, const uint8_t* seg_per, hipStream_t st);
+                       Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st);
 hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, hipStream_t st);
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, int qpw);

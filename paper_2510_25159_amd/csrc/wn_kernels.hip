@@ -276,6 +276,7 @@ struct NodeState {
     double a, ax, ay, ra, bx, by, rb;
     uint64_t pend, stored;
     int k;
+    int pmax;  // deepest level of this pair
     bool inside;
 };
 
@@ -296,6 +297,7 @@ __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_
     st.a = 0.0;
     st.k = 0;
     st.pend = st.stored = 0;
+    st.pmax = 0;
     st.inside = true;  // queued pairs failed the root ellipse test
 }
 
@@ -336,6 +338,7 @@ __device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, d
         st.by = my;
         st.rb = rm;
         st.k = k1;
+        st.pmax = k1 > st.pmax ? k1 : st.pmax;
         if (COUNT) nc.maxk = (uint32_t)k1 > nc.maxk ? (uint32_t)k1 : nc.maxk;
     } else {
         if (COUNT) {
@@ -393,7 +396,7 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 
 template <bool COUNT>
 __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats,
-                                              const uint8_t* seg_per) {
+                                              const uint8_t* seg_per, uint8_t* entry_depth) {
     __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
@@ -410,6 +413,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
     Turn T{1.0, 0.0, 0};
     bool onb = false, has = false;
     uint32_t q = 0;
+    unsigned long long cur = 0;  // queue index of this lane's pair
     NodeCount nc;
     for (;;) {
         const uint64_t idle = __ballot(!has);
@@ -418,6 +422,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
             if (!has && next + rank < c_end) {
                 const uint2 e = nq.qs[next + rank];
                 q = e.x;
+                cur = next + rank;
                 if ((int64_t)q < pts.n) {
                     double qx = pts.u[(int64_t)q * pts.stride], qy = pts.v[(int64_t)q * pts.stride];
                     if (nq.shift && seg_per[e.y]) {  // periodic copy: translate the query (App. C.1)
@@ -440,6 +445,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
         if (has && node_step<COUNT>(st, T, eps2, stk, onb, nc)) {
             if (onb) out.lab[q] = 2;
             else unsafeAtomicAdd(&out.w[q], turn_angle(T));
+            if (entry_depth) entry_depth[cur] = (uint8_t)(st.pmax < 255 ? st.pmax : 255);
             has = false;
         }
     }
@@ -568,14 +574,14 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
 }
 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       Stats stats, const uint8_t* seg_per, hipStream_t st) {
+                       Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     if (stats.c)
         hipLaunchKernelGGL(k_near<true>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
-                           seg_per);
+                           seg_per, entry_depth);
     else
         hipLaunchKernelGGL(k_near<false>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
-                           seg_per);
+                           seg_per, entry_depth);
     return hipGetLastError();
 }
 

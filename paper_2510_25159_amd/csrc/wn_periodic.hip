@@ -53,6 +53,17 @@ __global__ __launch_bounds__(256) void k_lift(LiftArgs a, Segs sg) {
         pnx[s] = a.cpu[c1] + ox;
         pny[s] = a.cpv[c1] + oy;
         const int n = (int)(c1 - c0);
+        double* box = const_cast<double*>(sg.box) + 4 * (size_t)s;
+        box[0] = INFINITY;
+        box[1] = -INFINITY;
+        box[2] = INFINITY;
+        box[3] = -INFINITY;
+        for (int64_t c = c0; c <= c1; ++c) {
+            box[0] = fmin(box[0], a.cpu[c] + ox);
+            box[1] = fmax(box[1], a.cpu[c] + ox);
+            box[2] = fmin(box[2], a.cpv[c] + oy);
+            box[3] = fmax(box[3], a.cpv[c] + oy);
+        }
         for (int j = 0; j <= n; ++j) {
             double* slot = coef + ((size_t)s * kCoef + j) * 4;
             slot[0] = a.cpu[c1 - j] * slot[2] + ox * slot[2];

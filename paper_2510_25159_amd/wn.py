@@ -25,9 +25,15 @@ EXPORTS = [
     "wn_default_options", "wn_default_query_opts", "wn_create_faces", "wn_query", "wn_query_ex",
     "wn_destroy_faces", "wn_status_string", "wn_segment_bound", "wn_get_faces_info",
     "wn_profile_create", "wn_profile_collect", "wn_profile_destroy",
+    "wn_predictor_create", "wn_predictor_destroy", "wn_predictor_train", "wn_predictor_get_params",
+    "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
 ]
+MLP_IN, MLP_HIDDEN = 16, 64
+MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+BIN_PREDICTOR, BIN_HEURISTIC, BIN_MEASURED, BIN_NONE = 0, 1, 2, 3
 KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO, KERNEL_FAR_PERIODIC = 0, 1, 2, 3, 4, 5
-KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo", 5: "k_far_periodic"}
+KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo", 5: "k_far_periodic",
+                6: "k_bin"}
 KERNEL_KINDS = 8
 STAT_NAMES = ["near_pairs", "splits", "leaves", "reevals", "near_flops", "max_depth"]
 STATS_COUNT = 8
@@ -55,7 +61,20 @@ class wn_points(ctypes.Structure):
 class wn_query_opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("queries_per_wg", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
-                ("near_capacity", ctypes.c_int64), ("depth_log", _P), ("profile", _P), ("stats", _P)]
+                ("near_capacity", ctypes.c_int64), ("depth_log", _P), ("profile", _P), ("stats", _P),
+                ("predictor", _P), ("bin_source", ctypes.c_int32)]
+
+
+class wn_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("weight_decay", ctypes.c_float), ("huber_delta", ctypes.c_float), ("holdout", ctypes.c_float),
+                ("seed", ctypes.c_int32), ("max_samples", ctypes.c_int64)]
+
+
+class wn_train_report(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int64), ("train_samples", ctypes.c_int64), ("steps", ctypes.c_int32),
+                ("final_train_loss", ctypes.c_float), ("holdout_mae", ctypes.c_float),
+                ("baseline_mae", ctypes.c_float), ("heuristic_mae", ctypes.c_float), ("mean_depth", ctypes.c_float)]
 
 
 class wn_faces_info(ctypes.Structure):
@@ -100,6 +119,22 @@ def lib():
         L.wn_profile_collect.restype = ctypes.c_int
         L.wn_profile_collect.argtypes = [_P, _P, _P]
         L.wn_profile_destroy.argtypes = [_P]
+        L.wn_predictor_create.restype = ctypes.c_int
+        L.wn_predictor_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_P)]
+        L.wn_predictor_destroy.argtypes = [_P]
+        L.wn_predictor_train.restype = ctypes.c_int
+        L.wn_predictor_train.argtypes = [_P, _P, ctypes.POINTER(wn_points), ctypes.POINTER(wn_train_opts),
+                                         ctypes.POINTER(wn_train_report), _P]
+        L.wn_predictor_get_params.restype = ctypes.c_int
+        L.wn_predictor_get_params.argtypes = [_P, _P, _P]
+        L.wn_predictor_set_params.restype = ctypes.c_int
+        L.wn_predictor_set_params.argtypes = [_P, _P, _P]
+        L.wn_predictor_loss_grad.restype = ctypes.c_int
+        L.wn_predictor_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_float, _P, _P, _P]
+        L.wn_predictor_predict.restype = ctypes.c_int
+        L.wn_predictor_predict.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
+        L.wn_pair_features.restype = ctypes.c_int
+        L.wn_pair_features.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.c_int64, _P, _P]
         L.wn_get_faces_info.restype = ctypes.c_int
         L.wn_get_faces_info.argtypes = [_P, ctypes.POINTER(wn_faces_info)]
         _lib = L
@@ -226,7 +261,7 @@ class FaceSet:
     def query(self, u, v, offsets, offsets_host=None, out_w=None, out_lab=None, *, stride: int = 1,
               schedule: Optional[int] = None, precision: Optional[int] = None, rule: Optional[int] = None,
               queries_per_wg: int = 0, queue_policy: int = 0, near_capacity: int = 0, depth_log=None,
-              profile: Optional[Profile] = None, stats=None, stream=None):
+              profile: Optional[Profile] = None, stats=None, predictor=None, bin_source: int = 0, stream=None):
         """Run the query on torch CUDA tensors (float64 u, v; int64 offsets).
 
         Returns (out_w, out_lab) torch tensors (allocated when not given)."""
@@ -257,8 +292,99 @@ class FaceSet:
         q.depth_log = None if depth_log is None else depth_log.data_ptr()
         q.profile = None if profile is None else profile.handle
         q.stats = None if stats is None else stats.data_ptr()
+        q.predictor = None if predictor is None else predictor.handle
+        q.bin_source = bin_source
         st = lib().wn_query_ex(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
                                _stream_ptr(stream))
         if st != WN_OK:
             raise WnError(st, "wn_query_ex")
         return out_w, out_lab
+
+
+def _points(u, v, offsets, stride=1, n=None):
+    n = u.numel() if n is None else n
+    return wn_points(n, u.data_ptr(), v.data_ptr(), stride, offsets.data_ptr(), None)
+
+
+class Predictor:
+    """Learned depth predictor (MLP 16-64-64-1, BF16 weights, trained on the GPU)."""
+
+    def __init__(self, seed: int = 0):
+        self._p = _P()
+        st = lib().wn_predictor_create(int(seed), ctypes.byref(self._p))
+        if st != WN_OK:
+            raise WnError(st, "wn_predictor_create")
+
+    @property
+    def handle(self):
+        return self._p
+
+    def close(self):
+        if self._p is not None and self._p.value:
+            lib().wn_predictor_destroy(self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train(self, faceset: "FaceSet", u, v, offsets, *, epochs=8, batch=4096, lr=2e-3, weight_decay=1e-4,
+              huber_delta=1.0, holdout=0.1, seed=0, max_samples=0, stream=None) -> dict:
+        o = wn_train_opts(epochs, batch, lr, weight_decay, huber_delta, holdout, seed, max_samples)
+        r = wn_train_report()
+        p = _points(u, v, offsets)
+        st = lib().wn_predictor_train(self._p, faceset._h, ctypes.byref(p), ctypes.byref(o), ctypes.byref(r),
+                                      _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_predictor_train")
+        return {k: getattr(r, k) for k, _ in wn_train_report._fields_}
+
+    def get_params(self):
+        prm = np.empty(MLP_PARAMS, dtype=np.float32)
+        norm = np.empty(2 * MLP_IN, dtype=np.float32)
+        st = lib().wn_predictor_get_params(self._p, _np_ptr(prm), _np_ptr(norm))
+        if st != WN_OK:
+            raise WnError(st, "wn_predictor_get_params")
+        return prm, norm
+
+    def set_params(self, params=None, norm=None):
+        prm = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        nm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        st = lib().wn_predictor_set_params(self._p, _np_ptr(prm), _np_ptr(nm))
+        if st != WN_OK:
+            raise WnError(st, "wn_predictor_set_params")
+
+    def loss_grad(self, X, Y, huber_delta=1.0, stream=None):
+        """X: torch cuda float32 [n,16] (standardised), Y: [n]; returns (loss, grad numpy)."""
+        loss = ctypes.c_float(0)
+        grad = np.empty(MLP_PARAMS, dtype=np.float32)
+        st = lib().wn_predictor_loss_grad(self._p, X.data_ptr(), Y.data_ptr(), X.shape[0], huber_delta,
+                                          ctypes.byref(loss), _np_ptr(grad), _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_predictor_loss_grad")
+        return loss.value, grad
+
+    def predict(self, X, stream=None):
+        import torch
+
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        st = lib().wn_predictor_predict(self._p, X.data_ptr(), X.shape[0], out.data_ptr(), _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_predictor_predict")
+        return out
+
+
+def pair_features(faceset: "FaceSet", u, v, offsets, pair_point, pair_segment, stream=None):
+    """Raw features [n,16] (torch cuda float32) of (point, global segment) pairs."""
+    import torch
+
+    n = pair_point.numel()
+    out = torch.empty((n, MLP_IN), dtype=torch.float32, device=u.device)
+    p = _points(u, v, offsets)
+    st = lib().wn_pair_features(faceset._h, ctypes.byref(p), pair_point.data_ptr(), pair_segment.data_ptr(), n,
+                                out.data_ptr(), _stream_ptr(stream))
+    if st != WN_OK:
+        raise WnError(st, "wn_pair_features")
+    return out

@@ -314,6 +314,37 @@ def config1(seed: int = SEED_C1):
 
 
 # --------------------------------------------------------------------------
+# Config 4: pairs of config 1's generator for the learned depth predictor
+# --------------------------------------------------------------------------
+def config4(split: str = "train", near_frac: float = 0.0):
+    """One 64-segment star face (config 1 generator) and its queries:
+    train = 78,125 points x 64 segments = 5M pairs (seed 40), eval = 156,250 x 64
+    = 10M pairs (seed 41).  ``near_frac`` > 0 places that fraction of the points
+    within 1e-3 of the curve (a stress variant outside the configuration)."""
+    seed, n = (SEED_C4_TRAIN, 78125) if split == "train" else (SEED_C4_EVAL, 156250)
+    faces = config1_faces(seed)
+    q = config1_queries(seed, n)
+    if near_frac > 0:
+        rng = np.random.default_rng(seed + 1000)
+        k = int(round(near_frac * n))
+        segs = [(np.column_stack([faces.cp_u[faces.seg_cp_offsets[s]:faces.seg_cp_offsets[s + 1]],
+                                  faces.cp_v[faces.seg_cp_offsets[s]:faces.seg_cp_offsets[s + 1]]]), None)
+                for s in range(faces.num_segments)]
+        lp = _Loop([c for c, _ in segs], [None] * len(segs))
+        si = rng.integers(0, len(segs), k)
+        t = rng.uniform(0, 1, k)
+        base = _eval_many([lp], np.zeros(k, dtype=np.int64), si, t)
+        rad = 1e-3 * np.sqrt(rng.uniform(0, 1, k))
+        phi = rng.uniform(0, 2 * np.pi, k)
+        u = q.u.copy()
+        v = q.v.copy()
+        u[:k] = base[:, 0] + rad * np.cos(phi)
+        v[:k] = base[:, 1] + rad * np.sin(phi)
+        q = Queries(u=u, v=v, face_point_offsets=q.face_point_offsets, near_mask=np.arange(n) < k)
+    return faces, q
+
+
+# --------------------------------------------------------------------------
 # Config 2: batched B-Rep-like planar faces
 # --------------------------------------------------------------------------
 def _loguniform_int(rng, lo, hi):
