@@ -298,6 +298,31 @@ wn_status wn_predictor_predict(const wn_predictor* p, const float* features, int
 wn_status wn_pair_features(const wn_faces* faces, const wn_points* points, const int32_t* pair_point,
                            const int32_t* pair_segment, int64_t n, float* out, void* stream);
 
+/* Plans: a preallocated batched query captured once into a HIP graph.  The
+ * caller owns the point buffers (`points`: device u, v with stride, device
+ * per-face offsets; points->num_points is the capacity) and the outputs
+ * (device, capacity entries), which must outlive the plan.  Before each
+ * launch the caller writes any number of points up to the capacity and their
+ * per-face offsets (offsets[num_faces] = live count): the kernels read the
+ * live count from the offsets.  The plan allocates its scratch once;
+ * launching allocates nothing.  Launches that overlap on one plan race (they
+ * share its scratch).  `q` selects the schedule (WN_SCHED_BATCHED or
+ * WN_SCHED_BINNED) and tiling; q->profile, q->stats and q->depth_log must be
+ * NULL.  The faces handle (and a predictor given in q) must outlive the plan. */
+typedef struct wn_plan wn_plan;
+wn_status wn_plan_create(const wn_faces* faces, const wn_points* points, double* out_winding, uint8_t* out_inside,
+                         const wn_query_opts* q, void* stream, wn_plan** out);
+/* Replay the captured graph on `stream` (asynchronous). */
+wn_status wn_plan_launch(wn_plan* p, void* stream);
+/* Autotuner: time every (points per workgroup in {64, 128, 256}) x (queue
+ * policy in {persistent, one workgroup per item}) on the plan's current
+ * buffers (`reps` runs each, HIP-event timed), keep the fastest and
+ * re-capture the graph.  Synchronous.  report (host, nullable, 8 doubles):
+ * average milliseconds in the order (64,p), (64,w), (128,p), (128,w),
+ * (256,p), (256,w), then the chosen points per workgroup and policy. */
+wn_status wn_plan_autotune(wn_plan* p, int32_t reps, void* stream, double* report);
+void wn_plan_destroy(wn_plan* p);
+
 /* Summary of a created handle (host copy of sizes). */
 typedef struct {
     int32_t num_faces, num_loops, num_segments;

@@ -259,6 +259,13 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         delete h;
         return WN_E_DEVICE;
     }
+    // resident workgroups per CU of the persistent kernels (queried once, so
+    // that a captured query issues no host queries)
+    h->bpc_far[0] = far_blocks_per_cu(false, 64);
+    h->bpc_far[1] = far_blocks_per_cu(false, 128);
+    h->bpc_far[2] = far_blocks_per_cu(false, 256);
+    h->bpc_far_per = far_periodic_blocks_per_cu();
+    h->bpc_near = near_blocks_per_cu();
 
     // faces ordered by segment count (largest first) for the work queues
     std::vector<int32_t> ord_plan, ord_per;
@@ -517,8 +524,14 @@ static int pick_qpw(int64_t n, int cu) {
     return 64;
 }
 
-wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint8_t* out_lab,
-                      const wn_query_opts* qo, void* stream) {
+}  // extern "C"
+
+namespace wn {
+
+// The query pipeline.  With `preset` scratch (a plan) nothing is allocated or
+// synchronised, so the call can be captured into a graph.
+wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8_t* out_lab, const wn_query_opts* qo,
+                     Scratch* preset, void* stream) {
     if (!h || !p) return WN_E_INVALID;
     wn_query_opts q;
     wn_default_query_opts(&q);
@@ -558,8 +571,16 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     cap = std::min<int64_t>(cap, (int64_t)1 << 34);
     if (plain) cap = 0;  // periodic faces of the plain schedule recurse in line
     Scratch sc;
-    e = scratch_alloc(h, N, cap, binned, binned && q.bin_source == WN_BIN_MEASURED, out_w, out_lab, rule, sc, st);
-    if (e != hipSuccess) return hip_status(e);
+    if (preset) {
+        if (plain || (binned && (!preset->qs2 || (q.bin_source == WN_BIN_MEASURED && !preset->depth))))
+            return WN_E_UNSUPPORTED;
+        sc = *preset;
+        sc.out = Out{out_w, out_lab, nullptr, 0, rule};
+    } else {
+        e = scratch_alloc(h, N, cap, binned, binned && q.bin_source == WN_BIN_MEASURED, out_w, out_lab, rule, sc,
+                          st, true);
+        if (e != hipSuccess) return hip_status(e);
+    }
 
     if (plain) {
         std::vector<int64_t> offs;
@@ -571,7 +592,7 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
             bool ok = e == hipSuccess && offs[0] == 0 && offs[F] == N;
             for (int32_t f = 0; ok && f < F; ++f) ok = offs[f + 1] >= offs[f];
             if (!ok) {
-                scratch_free(sc, st);
+                if (!preset) scratch_free(sc, st);
                 return e != hipSuccess ? hip_status(e) : WN_E_INVALID;
             }
             ho = offs.data();
@@ -594,10 +615,10 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
                 if (e == hipSuccess)
                     e = launch_far_periodic(h->sg, one, pts, sc.item_offs, sc.item_map, nullptr, (nf + 255) / 256,
                                             sc.nq, sc.out, h->eps2, h->pt, st);
-                if (e == hipSuccess) e = launch_finalize(pts, sc.out, ho[f], ho[f + 1], st);
+                if (e == hipSuccess) e = launch_finalize(pts, sc.out, ho[f], ho[f + 1], -1, st);
             }
         }
-        scratch_free(sc, st);
+        if (!preset) scratch_free(sc, st);
         return hip_status(e);
     }
 
@@ -623,14 +644,23 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
     if (e == hipSuccess) e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st);
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_FINALIZE, st);
-        e = launch_finalize(pts, sc.out, 0, N, st);
+        e = launch_finalize(pts, sc.out, 0, N, F, st);
     }
     if (e == hipSuccess && h->num_planar > 0) {
         ProfScope ps(q.profile, WN_KERNEL_REDO, st);
         e = launch_redo(h->sg, FaceTab{h->ft_plan.seg_begin, nullptr, F}, pts, sc.out, h->eps2, st);
     }
-    scratch_free(sc, st);
+    if (!preset) scratch_free(sc, st);
     return hip_status(e);
+}
+
+}  // namespace wn
+
+extern "C" {
+
+wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint8_t* out_lab,
+                      const wn_query_opts* qo, void* stream) {
+    return query_core(h, p, out_w, out_lab, qo, nullptr, stream);
 }
 
 }  // extern "C"
@@ -638,7 +668,7 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
 namespace wn {
 
 hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned, bool depth, double* out_w,
-                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st) {
+                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st, bool stream_ordered) {
     const bool periodic = h->num_periodic > 0;
     const int32_t F = h->num_faces;
     sc.max_items = N / 64 + F + 1;
@@ -656,7 +686,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
     const size_t o_bn = take(binned ? (size_t)cap : 0), o_wh = take(binned ? (size_t)G * 32 * 4 : 0);
     const size_t o_dp = take(depth ? (size_t)cap : 0);
     const size_t o_wt = take(depth ? (size_t)N * 8 : 0), o_lt = take(depth ? (size_t)N : 0);
-    const hipError_t e = hipMallocAsync(&sc.base, total, st);
+    const hipError_t e = stream_ordered ? hipMallocAsync(&sc.base, total, st) : hipMalloc(&sc.base, total);
     if (e != hipSuccess) return e;
     char* b = (char*)sc.base;
     sc.item_offs = (int32_t*)(b + o_io);
@@ -684,7 +714,7 @@ void scratch_free(Scratch& sc, hipStream_t st) {
     sc.base = nullptr;
 }
 
-int binning_grid(const wn_faces* h) { return std::max(1, h->cu_count * 4); }
+int binning_grid(const wn_faces* h) { return std::min(1024, std::max(1, h->cu_count * 4)); }
 
 hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, Scratch& sc, wn_profile* prof,
                       hipStream_t st) {
@@ -699,7 +729,8 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
             zero_near = false;
         }
         if (e == hipSuccess) {
-            const int64_t grid = persistent ? (int64_t)h->cu_count * far_blocks_per_cu(false, qpw) : sc.max_items;
+            const int bpc = qpw == 64 ? h->bpc_far[0] : (qpw == 128 ? h->bpc_far[1] : h->bpc_far[2]);
+            const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR, st);
             e = launch_far(false, qpw, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
                            persistent ? sc.counters : nullptr, -1, grid, sc.nq, sc.out, h->eps2, st);
@@ -713,7 +744,7 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
             zero_near = false;
         }
         if (e == hipSuccess) {
-            const int64_t grid = persistent ? (int64_t)h->cu_count * far_periodic_blocks_per_cu() : sc.max_items;
+            const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_far_per : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR_PERIODIC, st);
             e = launch_far_periodic(h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
                                     persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, st);
@@ -725,7 +756,7 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
                      uint8_t* entry_depth, wn_profile* prof, hipStream_t st) {
     ProfScope ps(prof, WN_KERNEL_NEAR, st);
-    return launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * near_blocks_per_cu(), Stats{stats},
+    return launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * h->bpc_near, Stats{stats},
                        h->pt.seg_periodic, entry_depth, st);
 }
 

@@ -20,6 +20,8 @@ struct wn_faces {
     double eps = 1e-10, eps2 = 1e-20;
     int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
     int cu_count = 0;
+    int bpc_far[3] = {1, 1, 1};  // resident workgroups per CU, k_far batched, 64/128/256 points per workgroup
+    int bpc_far_per = 1, bpc_near = 1;
     std::vector<int32_t> h_seg_begin;
     std::vector<int32_t> h_dom;
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
@@ -67,7 +69,7 @@ struct Scratch {
 // Allocate (stream-ordered) scratch for N points; outputs the caller did
 // not provide are allocated too.  binned adds the binning buffers.
 hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned, bool depth, double* out_w,
-                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st);
+                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st, bool stream_ordered);
 void scratch_free(Scratch& sc, hipStream_t st);
 
 // Item build + persistent far passes (planar, periodic) filling sc.nq.
@@ -79,5 +81,7 @@ hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out
 int binning_grid(const wn_faces* h);
 
 wn_status hip_status(hipError_t e);
+wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8_t* out_lab, const wn_query_opts* q,
+                     Scratch* preset, void* stream);
 
 }  // namespace wn

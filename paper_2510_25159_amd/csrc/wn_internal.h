@@ -137,7 +137,7 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
                        Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st);
-hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, hipStream_t st);
+hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, int32_t nf, hipStream_t st);
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, int qpw);
 int near_blocks_per_cu();

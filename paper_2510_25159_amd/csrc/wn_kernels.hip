@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, O
     const int wave = threadIdx.x >> 6;
     double2* stk = s_stack + wave * kStackSlots * kWave + lane;
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (i >= pts.n || out.lab[i] != kRedo) return;
+    if (i >= pts.n || i >= pts.offs[ft.num_faces] || out.lab[i] != kRedo) return;
     // face of point i: last f with offs[f] <= i
     int lo = 0, hi = ft.num_faces - 1;
     while (lo < hi) {
@@ -508,9 +508,12 @@ __global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, O
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out, int64_t q0, int64_t q1) {
+// Points are [q0, q1), further bounded by offs[nf] when nf >= 0 (the live
+// point count of a replayed graph).
+__global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out, int64_t q0, int64_t q1, int32_t nf) {
     const int64_t i = q0 + (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (i >= q1 || i >= pts.n) return;
+    if (nf >= 0 && i >= pts.offs[nf]) return;
     const uint8_t f = out.lab[i];
     double w = out.w[i];
     uint8_t lab;
@@ -585,10 +588,10 @@ hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, hipStream_t st) {
+hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, int32_t nf, hipStream_t st) {
     if (q1 <= q0) return hipSuccess;
     const int64_t g = (q1 - q0 + kWG - 1) / kWG;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWG), 0, st, pts, out, q0, q1);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWG), 0, st, pts, out, q0, q1, nf);
     return hipGetLastError();
 }
 

@@ -295,23 +295,29 @@ __global__ __launch_bounds__(256) void k_bin_count(Segs sg, Points pts, NearQueu
 }
 
 // wg_hist[g][b] -> start offset of (g, b) in bin-major order (in place).
-__global__ __launch_bounds__(64) void k_bin_scan(uint32_t* wg_hist, int G) {
-    __shared__ uint64_t s_tot[kBins];
-    const int b = threadIdx.x;
-    if (b < kBins) {
-        uint64_t run = 0;
-        for (int g = 0; g < G; ++g) {
-            const uint32_t c = wg_hist[(size_t)g * kBins + b];
-            wg_hist[(size_t)g * kBins + b] = (uint32_t)run;
-            run += c;
+// One workgroup, thread g owns workgroup g's counts (G <= 1024); per bin a
+// block-wide exclusive scan over g.
+__global__ __launch_bounds__(1024) void k_bin_scan(uint32_t* wg_hist, int G) {
+    __shared__ uint32_t s_v[1024];
+    __shared__ uint32_t s_base;
+    const int g = threadIdx.x;
+    if (g == 0) s_base = 0;
+    for (int b = 0; b < kBins; ++b) {
+        const uint32_t c = g < G ? wg_hist[(size_t)g * kBins + b] : 0u;
+        s_v[g] = c;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t t = g >= off ? s_v[g - off] : 0u;
+            __syncthreads();
+            s_v[g] += t;
+            __syncthreads();
         }
-        s_tot[b] = run;
-    }
-    __syncthreads();
-    if (b < kBins) {
-        uint64_t base = 0;
-        for (int k = 0; k < b; ++k) base += s_tot[k];
-        for (int g = 0; g < G; ++g) wg_hist[(size_t)g * kBins + b] += (uint32_t)base;
+        const uint32_t incl = s_v[g];
+        const uint32_t base = s_base;
+        if (g < G) wg_hist[(size_t)g * kBins + b] = base + incl - c;
+        __syncthreads();
+        if (g == 1023) s_base = base + incl;
+        __syncthreads();
     }
 }
 
@@ -382,7 +388,7 @@ hipError_t launch_binning(const Segs& sg, const Points& pts, NearQueue nq, const
                           uint32_t* wg_hist, int G, uint2* qs_out, double2* sh_out, hipStream_t st) {
     hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, sg, pts, nq, seg_per, eps, mode, w, norm, measured,
                        bins, wg_hist);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(64), 0, st, wg_hist, G);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, wg_hist, G);
     hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(256), 0, st, nq, bins, wg_hist, qs_out, sh_out);
     return hipGetLastError();
 }

@@ -165,7 +165,7 @@ wn_status wn_predictor_train(wn_predictor* pr, const wn_faces* h, const wn_point
 
     // 1. near pairs of the training points and their measured depths
     Scratch sc;
-    hipError_t e = scratch_alloc(h, N, cap, false, false, nullptr, nullptr, h->rule, sc, st);
+    hipError_t e = scratch_alloc(h, N, cap, false, false, nullptr, nullptr, h->rule, sc, st, true);
     if (e != hipSuccess) return hip_status(e);
     uint8_t* d_depth = nullptr;
     e = hipMallocAsync((void**)&d_depth, (size_t)cap, st);

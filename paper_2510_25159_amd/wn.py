@@ -27,6 +27,7 @@ EXPORTS = [
     "wn_profile_create", "wn_profile_collect", "wn_profile_destroy",
     "wn_predictor_create", "wn_predictor_destroy", "wn_predictor_train", "wn_predictor_get_params",
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
+    "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy",
 ]
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -135,6 +136,14 @@ def lib():
         L.wn_predictor_predict.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
         L.wn_pair_features.restype = ctypes.c_int
         L.wn_pair_features.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.c_int64, _P, _P]
+        L.wn_plan_create.restype = ctypes.c_int
+        L.wn_plan_create.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.POINTER(wn_query_opts), _P,
+                                     ctypes.POINTER(_P)]
+        L.wn_plan_launch.restype = ctypes.c_int
+        L.wn_plan_launch.argtypes = [_P, _P]
+        L.wn_plan_autotune.restype = ctypes.c_int
+        L.wn_plan_autotune.argtypes = [_P, ctypes.c_int32, _P, _P]
+        L.wn_plan_destroy.argtypes = [_P]
         L.wn_get_faces_info.restype = ctypes.c_int
         L.wn_get_faces_info.argtypes = [_P, ctypes.POINTER(wn_faces_info)]
         _lib = L
@@ -388,3 +397,50 @@ def pair_features(faceset: "FaceSet", u, v, offsets, pair_point, pair_segment, s
     if st != WN_OK:
         raise WnError(st, "wn_pair_features")
     return out
+
+
+class Plan:
+    """A batched query captured once into a HIP graph over caller-owned torch
+    buffers (capacity = u.numel()); write points/offsets, then launch()."""
+
+    def __init__(self, faceset: "FaceSet", u, v, offsets, out_w, out_lab, *, schedule: int = SCHED_BATCHED,
+                 queries_per_wg: int = 0, queue_policy: int = 0, predictor=None, bin_source: int = 0, stream=None):
+        self._keep = (faceset, u, v, offsets, out_w, out_lab, predictor)
+        self._h = _P()
+        p = _points(u, v, offsets)
+        q = wn_query_opts()
+        lib().wn_default_query_opts(ctypes.byref(q))
+        q.schedule = schedule
+        q.queries_per_wg = queries_per_wg
+        q.queue_policy = queue_policy
+        q.predictor = None if predictor is None else predictor.handle
+        q.bin_source = bin_source
+        st = lib().wn_plan_create(faceset._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
+                                  _stream_ptr(stream), ctypes.byref(self._h))
+        if st != WN_OK:
+            raise WnError(st, "wn_plan_create")
+
+    def launch(self, stream=None):
+        st = lib().wn_plan_launch(self._h, _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_plan_launch")
+
+    def autotune(self, reps: int = 3, stream=None) -> dict:
+        rep = np.zeros(8, dtype=np.float64)
+        st = lib().wn_plan_autotune(self._h, reps, _stream_ptr(stream), _np_ptr(rep))
+        if st != WN_OK:
+            raise WnError(st, "wn_plan_autotune")
+        names = ["64/persistent", "64/per-item", "128/persistent", "128/per-item", "256/persistent", "256/per-item"]
+        return {"ms": dict(zip(names, rep[:6].tolist())), "queries_per_wg": int(rep[6]),
+                "queue_policy": int(rep[7])}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().wn_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
