@@ -38,6 +38,98 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _dev_queries(torch, q):
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(q.u).to(dev), torch.from_numpy(q.v).to(dev),
+            torch.from_numpy(q.face_point_offsets).to(dev))
+
+
+def _time_query(torch, fs, tens, offs_host, reps, **kw):
+    from paper_2510_25159_amd import wn
+
+    prof = wn.Profile(64 * (reps + 1))
+    fs.query(*tens, offs_host, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fs.query(*tens, offs_host, profile=prof, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    return ms, {k: t_ / max(n, 1) for k, (n, t_) in prof.collect().items()}
+
+
+def section_config1(args):
+    """One planar face, 64 cubic segments, 65,536 uniform points."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    faces, q = W.config1()
+    fs = wn.FaceSet(faces)
+    tens = _dev_queries(torch, q)
+    pairs = faces.num_segments * q.num_points
+    out = {"pairs": pairs, "points": q.num_points}
+    for name, sched in (("plain", 0), ("batched", 1)):
+        ms, k = _time_query(torch, fs, tens, q.face_point_offsets, 50, schedule=sched)
+        out[name] = {"ms_per_step": ms, "evals_per_s": pairs / (ms / 1e3), "queries_per_s": q.num_points / (ms / 1e3),
+                     "kernel_ms": k}
+    kf = out["plain"]["kernel_ms"].get("k_far", float("nan"))
+    out["plain"]["far_roofline_frac"] = FLOPS_PER_PAIR * pairs / (kf / 1e3) / PEAK_FP64_VALU
+    return out
+
+
+def section_config3(args):
+    """512 periodic faces (cylinder / torus), 2^20 points."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    faces, q = W.config3()
+    fs = wn.FaceSet(faces)
+    tens = _dev_queries(torch, q)
+    out = {"faces": faces.num_faces, "segments": faces.num_segments, "points": q.num_points}
+    for name, sched in (("plain", 0), ("batched", 1)):
+        ms, k = _time_query(torch, fs, tens, q.face_point_offsets, 10 if sched else 3, schedule=sched)
+        out[name] = {"ms_per_step": ms, "queries_per_s": q.num_points / (ms / 1e3), "kernel_ms": k}
+    return out
+
+
+def section_config4(args):
+    """Learned depth predictor: train on 5M pairs (seed 40), evaluate 10M pairs (seed 41)."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    out = {}
+    for variant, near in (("uniform", 0.0), ("near30", 0.3)):
+        ft, qt = W.config4("train", near_frac=near)
+        fe, qe = W.config4("eval", near_frac=near)
+        pr = wn.Predictor(seed=7)
+        t = time.perf_counter()
+        rep = pr.train(wn.FaceSet(ft), *_dev_queries(torch, qt), epochs=60, lr=3e-3, seed=1)
+        rep["train_s"] = time.perf_counter() - t
+        fs = wn.FaceSet(fe)
+        tens = _dev_queries(torch, qe)
+        res = {"train": rep}
+        for name, sched, src in (("unbinned", 1, 3), ("mlp_binned", 2, 0), ("heuristic_binned", 2, 1),
+                                 ("measured_binned", 2, 2)):
+            ms, k = _time_query(torch, fs, tens, qe.face_point_offsets, 20, schedule=sched, predictor=pr,
+                                bin_source=src)
+            res[name] = {"ms_per_step": ms, "k_near_ms": k.get("k_near"), "k_bin_ms": k.get("k_bin")}
+        out[variant] = res
+    return out
+
+
+def section_config5(args):
+    """Serving loop: Poisson arrivals, resident faces, graph replays."""
+    from paper_2510_25159_amd import serving
+
+    return serving.run(duration=args.serving_duration)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +142,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--qpw", type=int, default=0)
     ap.add_argument("--policy", type=int, default=0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the config 1/3/4/5 sections")
+    ap.add_argument("--serving-duration", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -168,6 +262,17 @@ def main():
         maxerr = float(np.max(np.abs(w_b[idx][far] - w_o[far])))
         log(f"oracle sample: {ns} points in {tcpu:.1f}s on {cores} threads; mismatches {mism}, max err {maxerr:.2e}")
 
+    sections = {}
+    if not args.no_extra:
+        for name, fn in (("config1", section_config1), ("config3", section_config3),
+                         ("config4", section_config4), ("config5", section_config5)):
+            t = time.time()
+            try:
+                sections[name] = fn(args)
+            except Exception as exc:  # report, keep the headline line
+                sections[name] = {"error": repr(exc)}
+            log(f"{name}: {time.time() - t:.1f}s {json.dumps(sections[name])[:400]}")
+
     rec = {
         "metric": METRIC,
         "value": value,
@@ -196,6 +301,7 @@ def main():
         "roofline": roofline,
         "rooflines": rooflines,
         "cpu_baseline": cpu,
+        "configs": sections,
     }
     print(json.dumps(rec), flush=True)
 
