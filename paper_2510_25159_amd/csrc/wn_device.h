@@ -38,7 +38,44 @@ __device__ __forceinline__ void turn_norm(Turn& t) {
     t.zi = ldexp(t.zi, -e);
 }
 
-__device__ __forceinline__ double turn_angle(const Turn& t) { return atan2(t.zi, t.zr) + kTwoPi * (double)t.K; }
+// Maclaurin coefficients of arctan: arctan(t) = t + t s sum_k c_k s^k with
+// s = t^2, c_k = (-1)^(k+1) / (2k + 3).  Read from memory (scalar loads) at
+// each use, so that loops calling arg_of() do not hold the table in vector
+// registers.
+static __device__ double g_atan_series[21] = {
+    -1.0 / 3,  1.0 / 5,  -1.0 / 7,  1.0 / 9,  -1.0 / 11, 1.0 / 13, -1.0 / 15,
+    1.0 / 17,  -1.0 / 19, 1.0 / 21, -1.0 / 23, 1.0 / 25, -1.0 / 27, 1.0 / 29,
+    -1.0 / 31, 1.0 / 33, -1.0 / 35, 1.0 / 37, -1.0 / 39, 1.0 / 41, -1.0 / 43};
+
+// arg(x + iy) in [-pi, pi] (atan2(y, x), signed zeros of y respected).
+// Octant reduction: with n = min(|x|,|y|), d = max(|x|,|y|), arctan(n/d) is
+// taken directly when n/d <= tan(pi/8), else as pi/4 + arctan((n-d)/(n+d));
+// either way |t| <= tan(pi/8), s <= 0.1716, and the series above cut after
+// s^20 leaves a truncation error below 1e-18 relative.
+__device__ __forceinline__ double arg_of(double x, double y) {
+    const double ax = fabs(x), ay = fabs(y);
+    const bool swap = ay > ax;
+    const double n = swap ? ax : ay, d = swap ? ay : ax;
+    if (!(d > 0.0)) return 0.0;
+    const bool big = n > 0.41421356237309503 * d;
+    const double num = big ? n - d : n, den = big ? n + d : d;
+    double r = __builtin_amdgcn_rcp(den);  // two Newton steps to full precision
+    r = fma(fma(-den, r, 1.0), r, r);
+    r = fma(fma(-den, r, 1.0), r, r);
+    const double t = num * r, s = t * t;
+    const double* c = g_atan_series;
+    asm volatile("" : "+s"(c));  // opaque: the table is loaded here, not folded or hoisted
+    double g = c[20];
+#pragma unroll
+    for (int k = 19; k >= 0; --k) g = fma(g, s, c[k]);
+    double a = fma(t * s, g, t);
+    if (big) a += 0.78539816339744830962;  // pi/4
+    if (swap) a = 1.57079632679489661923 - a;
+    if (__double2hiint(x) < 0) a = 3.14159265358979323846 - a;
+    return __double2hiint(y) < 0 ? -a : a;
+}
+
+__device__ __forceinline__ double turn_angle(const Turn& t) { return arg_of(t.zr, t.zi) + kTwoPi * (double)t.K; }
 
 // ---------------------------------------------------------------------------
 // ellipse test (Lemma 1 / sub-segment bound), square-root free

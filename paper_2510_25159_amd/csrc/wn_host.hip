@@ -249,6 +249,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
             }
         }
     }
+    std::vector<uint8_t> join(S, 0);
+    for (int32_t s = 1; s < S; ++s) join[s] = (p0x[s] == pnx[s - 1] && p0y[s] == pny[s - 1]) ? 1 : 0;
     h->max_depth = maxd;
     if (maxd > opt.stack_cap) {
         delete h;
@@ -298,6 +300,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     const size_t o_coef = add(coef.data(), coef.size() * 8);
     const size_t o_deg = add(deg.data(), S), o_rat = add(rat.data(), S), o_sper = add(segper.data(), S);
     const size_t o_box = add(box.data(), box.size() * 8), o_wr = add(wrange.data(), wrange.size() * 4);
+    const size_t o_join = add(join.data(), S);
     const size_t o_sb = add(h->h_seg_begin.data(), ((size_t)F + 1) * 4);
     const size_t o_op = add(ord_plan.data(), ord_plan.size() * 4), o_oq = add(ord_per.data(), ord_per.size() * 4);
     // periodic tables (filled after the lift)
@@ -337,6 +340,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->sg.rat = (const uint8_t*)(base + o_rat);
     h->sg.box = (const double*)(base + o_box);
     h->sg.wrange = (const float*)(base + o_wr);
+    h->sg.join = (const uint8_t*)(base + o_join);
     const int32_t* d_sb = (const int32_t*)(base + o_sb);
     h->ft_plan = FaceTab{d_sb, (const int32_t*)(base + o_op), (int32_t)ord_plan.size()};
     h->ft_per = FaceTab{d_sb, (const int32_t*)(base + o_oq), (int32_t)ord_per.size()};

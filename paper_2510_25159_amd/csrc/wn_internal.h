@@ -16,6 +16,7 @@ constexpr int kStackSlots = 8;      // LDS ring slots per lane for pending right
 constexpr int kDepthCap = 52;       // dyadic parameters a + 2^-k stay exact in FP64
 constexpr int kSegChunk = kWG;      // segments staged in LDS per chunk
 constexpr int kNearBuf = 256;       // per-wave LDS buffer of near pairs before one queue append
+constexpr int kRefillMin = 16;      // near pass: idle lanes of a wave before they take new pairs
 // Relative inflation of the ellipse axis: the far decision is taken only when
 // it survives rounding (Lemma 1 boundary "<=" counts as inside, so inflating
 // the bound only sends borderline pairs to the recursion).
@@ -39,6 +40,7 @@ struct Segs {
     const double* coef; // [S][kCoef][4]: slot j = (x, y, w, 0) of C(n, n-j) w_{n-j} P_{n-j}
     const uint8_t* deg; // [S] degree 1..5
     const uint8_t* rat; // [S] 1 if any weight != 1
+    const uint8_t* join;// [S] 1 when gamma(0) equals the previous segment's gamma(1) bit for bit
     const double* box;  // [S][4] control-point box umin, umax, vmin, vmax (lifted for periodic faces)
     const float* wrange;// [S][2] min, max weight
 };

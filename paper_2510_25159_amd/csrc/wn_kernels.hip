@@ -122,6 +122,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
     constexpr int GS = kWavesPerWG / GQ;
     constexpr int QPW = kWave * GQ;
     __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
+    __shared__ uint8_t s_join[kSegChunk];
     __shared__ double2 s_stack[INLINE ? kWavesPerWG * kStackSlots * kWave : 1];
     __shared__ double s_ang[kWavesPerWG][kWave];
     __shared__ int s_flag[kWavesPerWG][kWave];
@@ -171,9 +172,12 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         Turn T{1.0, 0.0, 0};
         bool onb = false;
         const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
-        int cnt = 0;
         int nfill = 0;      // entries in this wave's near-pair buffer (wave-uniform)
         bool lost = false;  // a near pair of this lane's query did not fit in the queue
+        // End point of the previous segment of this wave, relative to the
+        // query: reused as the next start point when the two are the same
+        // point bit for bit (consecutive segments of a loop).
+        double pbx = 0.0, pby = 0.0, prb = 0.0;
         for (int c0 = s0; c0 < s1; c0 += kSegChunk) {
             __syncthreads();
             const int sj = c0 + tid;
@@ -183,45 +187,73 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                 s_pnx[tid] = sg.pnx[sj];
                 s_pny[tid] = sg.pny[sj];
                 s_hb2[tid] = sg.hb2[sj];
+                s_join[tid] = sg.join[sj];
             }
             __syncthreads();
             const int cn = min(kSegChunk, s1 - c0);
-            for (int j = gs; j < cn; j += GS) {
-                const double ax = s_p0x[j] - qx, ay = s_p0y[j] - qy;
-                const double bx = s_pnx[j] - qx, by = s_pny[j] - qy;
-                const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
-                const bool work = valid && !onb;
-                if (work && (ra < eps2 || rb < eps2)) onb = true;
-                const bool far = outside_ellipse(ra, rb, s_hb2[j]);
-                if (far) turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
-                bool need = work && !onb && !far;
-                int depth = 0;
-                if constexpr (!INLINE) {
-                    const uint64_t m = __ballot(need);
-                    if (m) {
-                        const int cntm = __popcll(m);
-                        if (nfill + cntm > kNearBuf) {
-                            lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
-                            nfill = 0;
+            // GS waves split the chunk into contiguous ranges
+            const int jb = (cn * gs) / GS, je = (cn * (gs + 1)) / GS;
+            for (int j0 = jb; j0 < je; j0 += kWave) {
+                const int jn = min(kWave, je - j0);
+                // bit i: segment j0 + i starts where segment j0 + i - 1 ended
+                uint64_t jm = __ballot(lane < jn && s_join[j0 + lane] != 0);
+                if (j0 == jb && (GS > 1 || c0 == s0)) jm &= ~1ull;
+                for (int g0 = 0; g0 < jn; g0 += 8) {
+                    const int ge = min(g0 + 8, jn);
+                    for (int jj = g0; jj < ge; ++jj) {
+                        const int j = j0 + jj;
+                        const bool work = valid && !onb;
+                        double ax, ay, ra;
+                        if ((jm >> jj) & 1ull) {
+                            ax = pbx;  // already tested against eps as an end point
+                            ay = pby;
+                            ra = prb;
+                        } else {
+                            ax = s_p0x[j] - qx;
+                            ay = s_p0y[j] - qy;
+                            ra = ax * ax + ay * ay;
+                            if (work && ra < eps2) onb = true;
                         }
-                        const int rank = __popcll(m & ((1ull << lane) - 1ull));
-                        if (need) {
-                            s_nbuf[wave][nfill + rank] = make_uint2((uint32_t)qi, (uint32_t)(c0 + j));
-                            need = false;
+                        const double bx = s_pnx[j] - qx, by = s_pny[j] - qy;
+                        const double rb = bx * bx + by * by;
+                        if (work && rb < eps2) onb = true;
+                        pbx = bx;
+                        pby = by;
+                        prb = rb;
+                        const bool far = outside_ellipse(ra, rb, s_hb2[j]);
+                        if (far) turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
+                        bool need = work && !onb && !far;
+                        int depth = 0;
+                        if constexpr (!INLINE) {
+                            const uint64_t m = __ballot(need);
+                            if (m) {
+                                const int cntm = __popcll(m);
+                                if (nfill + cntm > kNearBuf) {
+                                    lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
+                                    nfill = 0;
+                                }
+                                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                                if (need) {
+                                    s_nbuf[wave][nfill + rank] = make_uint2((uint32_t)qi, (uint32_t)(c0 + j));
+                                    need = false;
+                                }
+                                nfill += cntm;
+                            }
                         }
-                        nfill += cntm;
+                        if (INLINE && need) {
+                            const int s = c0 + j;
+                            Coef c;
+                            load_coef(sg, s, c);
+                            depth = near_pair(T, c, sg.B[s], sg.eta[s], s_pnx[j], s_pny[j], qx, qy, ax, ay, ra, bx,
+                                              by, rb, eps2, stk, onb);
+                        }
+                        if (INLINE && out.depth && active)
+                            out.depth[qi * (int64_t)out.depth_stride + (c0 + j - s0)] = (uint8_t)depth;
                     }
+                    // rescale after at most 8 factors: each has modulus |a||b| in
+                    // [2^-100, 2^103] (|coordinates| < 1e15, |a|, |b| >= eps >= 1e-15)
+                    turn_norm(T);
                 }
-                if (INLINE && need) {
-                    const int s = c0 + j;
-                    Coef c;
-                    load_coef(sg, s, c);
-                    depth = near_pair(T, c, sg.B[s], sg.eta[s], s_pnx[j], s_pny[j], qx, qy, ax, ay, ra, bx, by, rb,
-                                      eps2, stk, onb);
-                }
-                if (INLINE && out.depth && active)
-                    out.depth[qi * (int64_t)out.depth_stride + (c0 + j - s0)] = (uint8_t)depth;
-                if ((++cnt & 3) == 0) turn_norm(T);
             }
         }
         if constexpr (!INLINE) lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
@@ -271,28 +303,32 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
 // loop trip, so lanes with short and long recursions interleave.
 // ---------------------------------------------------------------------------
 struct NodeState {
-    Coef c;
-    double B, eta, pnx, pny, qx, qy;
+    Coef c;  // translated by -q: evaluates gamma(t) - q directly
+    double B, eta;
     double a, ax, ay, ra, bx, by, rb;
     uint64_t pend, stored;
     int k;
-    int pmax;  // deepest level of this pair
+    int pmax;      // deepest level of this pair
+    uint32_t seg;  // segment (its end point is reloaded in the rare evicted t = 1 case)
     bool inside;
 };
 
 __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_t s, double qx, double qy) {
     load_coef(sg, s, st.c);
+    // sum_i C(n,i) w_i (P_i - q) B_i(t) / sum_i C(n,i) w_i B_i(t) = gamma(t) - q
+#pragma unroll
+    for (int j = 0; j < kCoef; ++j) {
+        st.c.x[j] = fma(-st.c.w[j], qx, st.c.x[j]);
+        st.c.y[j] = fma(-st.c.w[j], qy, st.c.y[j]);
+    }
     st.B = sg.B[s];
     st.eta = sg.eta[s];
-    st.pnx = sg.pnx[s];
-    st.pny = sg.pny[s];
-    st.qx = qx;
-    st.qy = qy;
+    st.seg = s;
     st.ax = sg.p0x[s] - qx;
     st.ay = sg.p0y[s] - qy;
     st.ra = st.ax * st.ax + st.ay * st.ay;
-    st.bx = st.pnx - qx;
-    st.by = st.pny - qy;
+    st.bx = sg.pnx[s] - qx;
+    st.by = sg.pny[s] - qy;
     st.rb = st.bx * st.bx + st.by * st.by;
     st.a = 0.0;
     st.k = 0;
@@ -306,11 +342,48 @@ struct NodeCount {
     uint64_t flops = 0;
 };
 
-// One node of Alg. 1.  Returns true when the pair is finished.  COUNT
-// selects the instrumented variant (work counters).
+// One step of Alg. 1 on the current interval: when it passed the ellipse
+// test (a leaf) its chord factor is taken and the next pending interval is
+// popped and tested; then, when the current interval failed the test, it is
+// halved and its left half tested.  A step therefore takes at most one leaf
+// and one split, so lanes whose recursions alternate between the two finish
+// in fewer steps.  Returns true when the pair is finished.  COUNT selects
+// the instrumented variant (work counters).
 template <bool COUNT>
 __device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, double2* stk, bool& onb,
-                                          NodeCount& nc) {
+                                          NodeCount& nc, const Segs& sg, double qx, double qy) {
+    if (!st.inside) {
+        if (COUNT) {
+            ++nc.leaf;
+            nc.flops += 11;
+        }
+        turn_mul(T, st.ax * st.bx + st.ay * st.by, st.ax * st.by - st.ay * st.bx);
+        if (st.pend == 0) return true;
+        const int kk = 63 - __clzll(st.pend);
+        st.pend &= ~(1ull << kk);
+        st.a += ldexp(1.0, -st.k);
+        st.ax = st.bx;
+        st.ay = st.by;
+        st.ra = st.rb;
+        if (st.stored & (1ull << kk)) {
+            const double2 p = stk[(kk & (kStackSlots - 1)) * kWave];
+            st.bx = p.x;
+            st.by = p.y;
+        } else {
+            const double t = st.a + ldexp(1.0, -kk);
+            if (t == 1.0) {
+                st.bx = sg.pnx[st.seg] - qx;
+                st.by = sg.pny[st.seg] - qy;
+            } else {
+                bez_eval(st.c, t, st.bx, st.by);
+                if (COUNT) ++nc.reeval;
+            }
+        }
+        st.stored &= ~(1ull << kk);
+        st.rb = st.bx * st.bx + st.by * st.by;
+        st.k = kk;
+        st.inside = !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k));
+    }
     if (st.inside) {
         if (COUNT) {
             ++nc.split;
@@ -327,8 +400,6 @@ __device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, d
         st.pend |= 1ull << k1;
         double mx, my;
         bez_eval(st.c, st.a + ldexp(1.0, -k1), mx, my);
-        mx -= st.qx;
-        my -= st.qy;
         const double rm = mx * mx + my * my;
         if (rm < eps2) {
             onb = true;
@@ -340,41 +411,8 @@ __device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, d
         st.k = k1;
         st.pmax = k1 > st.pmax ? k1 : st.pmax;
         if (COUNT) nc.maxk = (uint32_t)k1 > nc.maxk ? (uint32_t)k1 : nc.maxk;
-    } else {
-        if (COUNT) {
-            ++nc.leaf;
-            nc.flops += 11;
-        }
-        turn_mul(T, st.ax * st.bx + st.ay * st.by, st.ax * st.by - st.ay * st.bx);
-        if (st.pend == 0) return true;
-        turn_norm(T);
-        const int kk = 63 - __clzll(st.pend);
-        st.pend &= ~(1ull << kk);
-        st.a += ldexp(1.0, -st.k);
-        st.ax = st.bx;
-        st.ay = st.by;
-        st.ra = st.rb;
-        if (st.stored & (1ull << kk)) {
-            const double2 p = stk[(kk & (kStackSlots - 1)) * kWave];
-            st.bx = p.x;
-            st.by = p.y;
-        } else {
-            const double t = st.a + ldexp(1.0, -kk);
-            if (t == 1.0) {
-                st.bx = st.pnx;
-                st.by = st.pny;
-            } else {
-                bez_eval(st.c, t, st.bx, st.by);
-                if (COUNT) ++nc.reeval;
-            }
-            st.bx -= st.qx;
-            st.by -= st.qy;
-        }
-        st.stored &= ~(1ull << kk);
-        st.rb = st.bx * st.bx + st.by * st.by;
-        st.k = kk;
+        st.inside = !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k));
     }
-    st.inside = !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k));
     return false;
 }
 
@@ -394,10 +432,23 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
+// Angles of the first `count` buffered products (one lane each), added to
+// the query's winding sum.  Called with the whole wave active.
+__device__ __forceinline__ void drain_turns(const double2* fz, const int2* fq, int count, int lane, double* w) {
+    if (lane < count) {
+        const double2 z = fz[lane];
+        const int2 qk = fq[lane];
+        unsafeAtomicAdd(&w[qk.x], turn_angle(Turn{z.x, z.y, qk.y}));
+    }
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats,
                                               const uint8_t* seg_per, uint8_t* entry_depth) {
     __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    __shared__ double2 s_fz[kWavesPerWG][kWave];  // finished pairs: product z
+    __shared__ int2 s_fq[kWavesPerWG][kWave];     // finished pairs: query, turn count
+    int nfin = 0;                                 // entries in this wave's buffer (wave-uniform)
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     double2* stk = s_stack + wave * kStackSlots * kWave + lane;
@@ -413,18 +464,29 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
     Turn T{1.0, 0.0, 0};
     bool onb = false, has = false;
     uint32_t q = 0;
+    double qx = 0.0, qy = 0.0;   // this lane's query (translated for periodic copies)
     unsigned long long cur = 0;  // queue index of this lane's pair
     NodeCount nc;
-    for (;;) {
+    // window of the next 64 queue entries, one per lane, loaded one refill ahead
+    uint2 win = make_uint2(0xffffffffu, 0u);
+    if (next + lane < c_end) win = nq.qs[next + lane];
+    for (uint32_t it = 1;; ++it) {
+        // each step multiplies T by at most one factor: rescale every 8 steps
+        if ((it & 7) == 0) turn_norm(T);
         const uint64_t idle = __ballot(!has);
-        if (idle && next < c_end) {
-            const unsigned long long rank = (unsigned long long)__popcll(idle & ((1ull << lane) - 1ull));
+        // refill idle lanes once kRefillMin of them are idle (each refill
+        // waits for the gathers of the new pairs' data)
+        if (idle && next < c_end && (__popcll(idle) >= kRefillMin || idle == ~0ull)) {
+            const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+            uint2 e;  // all lanes active here: entry next + rank comes from lane rank of the window
+            e.x = (uint32_t)__shfl((int)win.x, rank);
+            e.y = (uint32_t)__shfl((int)win.y, rank);
             if (!has && next + rank < c_end) {
-                const uint2 e = nq.qs[next + rank];
                 q = e.x;
                 cur = next + rank;
                 if ((int64_t)q < pts.n) {
-                    double qx = pts.u[(int64_t)q * pts.stride], qy = pts.v[(int64_t)q * pts.stride];
+                    qx = pts.u[(int64_t)q * pts.stride];
+                    qy = pts.v[(int64_t)q * pts.stride];
                     if (nq.shift && seg_per[e.y]) {  // periodic copy: translate the query (App. C.1)
                         const double2 sh = nq.shift[next + rank];
                         qx -= sh.x;
@@ -437,18 +499,37 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
                 }
             }
             next += (unsigned long long)__popcll(idle);
+            if (next + lane < c_end) win = nq.qs[next + lane];
         }
         if (!__any(has)) {
             if (next >= c_end) break;
             continue;
         }
-        if (has && node_step<COUNT>(st, T, eps2, stk, onb, nc)) {
+        bool fin = false;
+        if (has) fin = node_step<COUNT>(st, T, eps2, stk, onb, nc, sg, qx, qy);
+        if (fin) {
             if (onb) out.lab[q] = 2;
-            else unsafeAtomicAdd(&out.w[q], turn_angle(T));
-            if (entry_depth) entry_depth[cur] = (uint8_t)(st.pmax < 255 ? st.pmax : 255);
+            if (COUNT && entry_depth) entry_depth[cur] = (uint8_t)(st.pmax < 255 ? st.pmax : 255);
             has = false;
         }
+        // finished pairs wait in the wave's buffer; their angles are taken
+        // 64 at a time with every lane busy
+        const uint64_t fm = __ballot(fin && !onb);
+        if (fm) {
+            const int cnt = __popcll(fm);
+            if (nfin + cnt > kWave) {
+                drain_turns(s_fz[wave], s_fq[wave], nfin, lane, out.w);
+                nfin = 0;
+            }
+            if (fin && !onb) {
+                const int slot = nfin + __popcll(fm & ((1ull << lane) - 1ull));
+                s_fz[wave][slot] = make_double2(T.zr, T.zi);
+                s_fq[wave][slot] = make_int2((int)q, T.K);
+            }
+            nfin += cnt;
+        }
     }
+    drain_turns(s_fz[wave], s_fq[wave], nfin, lane, out.w);
     if (COUNT && stats.c) {
         const unsigned long long sp = wave_sum((unsigned long long)nc.split);
         const unsigned long long lf = wave_sum((unsigned long long)nc.leaf);
@@ -579,7 +660,7 @@ hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
                        Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
-    if (stats.c)
+    if (stats.c || entry_depth)
         hipLaunchKernelGGL(k_near<true>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
                            seg_per, entry_depth);
     else
