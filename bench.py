@@ -32,10 +32,50 @@ METRIC = "point×segment winding evals/s & queries/s, plain vs batched form, 0 m
 FLOPS_PER_PAIR = 22
 PEAK_FP64_VALU = 78.6e12   # MI355X vector FP64, FLOP/s
 PEAK_HBM = 8.0e12          # B/s
+# HBM traffic per launch measured with rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE, each scaled by a plain copy's reading); valid only while the
+# library sources are the ones the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_config2.txt")
+LIB_SOURCES = os.path.join(ROOT, "paper_2510_25159_amd", "csrc")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    """sha256 over the library's kernel and host sources (sorted by name)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(LIB_SOURCES)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(LIB_SOURCES, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic() -> dict:
+    """{kernel: HBM bytes per launch} from the committed counter summary, or
+    {} when it is missing or was taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return {}
+    kv = {}
+    for ln in lines:
+        if "=" in ln and not ln.startswith((" ", "#", "$")):
+            k, v = ln.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_hash():
+        return {}
+    out = {}
+    for k, v in kv.items():
+        if k.startswith("traffic_bytes_per_launch "):
+            out[k.split()[1]] = float(v)
+    return out
 
 
 def _dev_queries(torch, q):
@@ -144,6 +184,8 @@ def main():
     ap.add_argument("--policy", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true", help="skip the config 1/3/4/5 sections")
     ap.add_argument("--serving-duration", type=float, default=10.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -179,6 +221,15 @@ def main():
         fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=schedule, queries_per_wg=args.qpw,
                  queue_policy=args.policy, profile=profile, stream=stream)
 
+    if args.copy_calibration_mib > 0:
+        # a plain copy of known size: reads and writes exactly copy_calibration_mib MiB
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # warmup
     for _ in range(args.warmup):
         step(args.schedule)
@@ -235,6 +286,9 @@ def main():
                                "unit": "TFLOP/s", "frac": a / PEAK_FP64_VALU, "traffic": None, "avg_launch_ms": ms,
                                "work": f"{st['near_pairs']} near pairs, {st['splits']} splits x (6n+15) + "
                                        f"{st['leaves']} leaves x 11 = {st['near_flops']} flops"}
+    traffic = measured_traffic()
+    for k, r in rooflines.items():
+        r["traffic"] = traffic.get(k)
     dom = max(rooflines, key=lambda k: rooflines[k]["avg_launch_ms"])
     roofline = dict(rooflines[dom], kernel=dom)
 

@@ -91,6 +91,41 @@ __device__ __forceinline__ double half_axis2(double B, double eta, int k) {
 }
 
 // ---------------------------------------------------------------------------
+// Signed crossings with the ray {(x, 0): x > 0} from the query (points
+// relative to the query).  For a polygon that avoids the query, the sum of
+// the principal angles its edges subtend is 2 pi times the sum of these
+// crossings.  Ties are broken by one symbolic displacement of the query,
+// q + (-e^2, e) with e -> 0+: a vertex on the ray's line counts as below it,
+// and a zero orientation takes the sign of the e and e^2 terms.  Every
+// caller evaluates the same expressions on the same doubles, so the
+// decisions agree wherever two edges share a vertex.
+// ---------------------------------------------------------------------------
+// a x b, with a zero replaced by the signed zero of the displaced query's
+// orientation (b_x - a_x, then b_y - a_y).
+__device__ __forceinline__ double cross_sos(double ax, double ay, double bx, double by) {
+    const double o = fma(ax, by, -(ay * bx));
+    if (o != 0.0) return o;
+    const double d = bx != ax ? bx - ax : by - ay;
+    return copysign(0.0, d);
+}
+
+// +1 when a -> b crosses the ray upward, -1 downward, else 0.
+__device__ __forceinline__ int ray_cross(double ax, double ay, double bx, double by) {
+    const double o = cross_sos(ax, ay, bx, by);
+    const bool neg = __double2hiint(o) < 0;  // sign bit: -0 counts as negative
+    const bool up = ay <= 0.0 && by > 0.0 && !neg;
+    const bool dn = ay > 0.0 && by <= 0.0 && neg;
+    return up ? 1 : (dn ? -1 : 0);
+}
+
+// Chord factor of a near pair for the angle accumulator: (a . b, a x b) with
+// the same tie rule as ray_cross, so that a query on the chord gets +-pi on
+// the side that ray_cross assumes.
+__device__ __forceinline__ void chord_factor(Turn& T, double ax, double ay, double bx, double by) {
+    turn_mul(T, fma(ax, bx, ay * by), cross_sos(ax, ay, bx, by));
+}
+
+// ---------------------------------------------------------------------------
 // curve evaluation
 // ---------------------------------------------------------------------------
 struct Coef {
@@ -140,11 +175,19 @@ __device__ __forceinline__ void bez_eval(const Coef& c, double t, double& X, dou
 // near pair: Alg. 1 on an explicit stack.  The root [0,1] is known to be
 // inside its ellipse and not on the boundary.  Points are kept relative to
 // the query.  `stk` is this lane's slot 0 in LDS (slot stride kWave).
+//
+// The pair's angle is the sum of the leaves' chord angles.  It is returned
+// as an integer N: angle = (chord angle of the segment, given to the
+// accumulator by the caller through chord_factor) + 2 pi N, where
+// N = sum over leaves of ray_cross - ray_cross(chord).  This is exact: the
+// leaves' chords followed by the reversed segment chord form a closed
+// polygon that avoids the query, whose angle sum is 2 pi times its crossings.
 // Returns the deepest level reached; sets onb on an eps hit.
 // ---------------------------------------------------------------------------
-__device__ int near_pair(Turn& T, const Coef& c, double B, double eta, double pnx, double pny, double qx, double qy,
+__device__ int near_pair(int& N, const Coef& c, double B, double eta, double pnx, double pny, double qx, double qy,
                          double ax, double ay, double ra, double bx, double by, double rb, double eps2,
                          double2* stk, bool& onb) {
+    int n = -ray_cross(ax, ay, bx, by);
     double a = 0.0;  // left end of the current node, exact dyadic
     int k = 0;       // level: node = [a, a + 2^-k]
     uint64_t pend = 0, stored = 0;
@@ -177,9 +220,11 @@ __device__ int near_pair(Turn& T, const Coef& c, double B, double eta, double pn
             k = k1;
             maxk = k1 > maxk ? k1 : maxk;
         } else {
-            turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
-            if (pend == 0) return maxk;
-            turn_norm(T);
+            n += ray_cross(ax, ay, bx, by);
+            if (pend == 0) {
+                N += n;
+                return maxk;
+            }
             const int kk = 63 - __clzll(pend);
             pend &= ~(1ull << kk);
             a += ldexp(1.0, -k);
@@ -209,15 +254,15 @@ __device__ int near_pair(Turn& T, const Coef& c, double B, double eta, double pn
     }
 }
 
-// Near pair with all segment data read from global memory.
-__device__ __forceinline__ int near_from_global(Turn& T, const Segs& sg, uint32_t s, double qx, double qy,
+// Near pair with all segment data read from global memory (integer part only).
+__device__ __forceinline__ int near_from_global(int& N, const Segs& sg, uint32_t s, double qx, double qy,
                                                 double eps2, double2* stk, bool& onb) {
     const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
     const double pnx = sg.pnx[s], pny = sg.pny[s];
     const double bx = pnx - qx, by = pny - qy;
     Coef c;
     load_coef(sg, s, c);
-    return near_pair(T, c, sg.B[s], sg.eta[s], pnx, pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
+    return near_pair(N, c, sg.B[s], sg.eta[s], pnx, pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
                      eps2, stk, onb);
 }
 

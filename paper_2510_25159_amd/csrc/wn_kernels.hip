@@ -170,6 +170,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         const bool valid = active && fabs(qx) < kCoordLimit && fabs(qy) < kCoordLimit;
         if (!valid) qx = qy = 0.0;
         Turn T{1.0, 0.0, 0};
+        int xc = 0;  // integer part of in-line near pairs (2 pi units)
         bool onb = false;
         const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
         int nfill = 0;      // entries in this wave's near-pair buffer (wave-uniform)
@@ -223,6 +224,8 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         const bool far = outside_ellipse(ra, rb, s_hb2[j]);
                         if (far) turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
                         bool need = work && !onb && !far;
+                        // near pair: its chord angle here, the integer rest from the recursion
+                        if (need) chord_factor(T, ax, ay, bx, by);
                         int depth = 0;
                         if constexpr (!INLINE) {
                             const uint64_t m = __ballot(need);
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                             const int s = c0 + j;
                             Coef c;
                             load_coef(sg, s, c);
-                            depth = near_pair(T, c, sg.B[s], sg.eta[s], s_pnx[j], s_pny[j], qx, qy, ax, ay, ra, bx,
+                            depth = near_pair(xc, c, sg.B[s], sg.eta[s], s_pnx[j], s_pny[j], qx, qy, ax, ay, ra, bx,
                                               by, rb, eps2, stk, onb);
                         }
                         if (INLINE && out.depth && active)
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         }
         if constexpr (!INLINE) lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
         // combine the GS partial sums of each query group
-        double ang = turn_angle(T);
+        double ang = turn_angle(T) + kTwoPi * (double)xc;
         if constexpr (GS > 1) {
             s_ang[wave][lane] = ang;
             s_flag[wave][lane] = (onb ? 1 : 0) | (lost ? 2 : 0);
@@ -308,6 +311,7 @@ struct NodeState {
     double a, ax, ay, ra, bx, by, rb;
     uint64_t pend, stored;
     int k;
+    int n;         // leaves' ray crossings minus the segment chord's (see near_pair)
     int pmax;      // deepest level of this pair
     uint32_t seg;  // segment (its end point is reloaded in the rare evicted t = 1 case)
     bool inside;
@@ -330,6 +334,7 @@ __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_
     st.bx = sg.pnx[s] - qx;
     st.by = sg.pny[s] - qy;
     st.rb = st.bx * st.bx + st.by * st.by;
+    st.n = -ray_cross(st.ax, st.ay, st.bx, st.by);
     st.a = 0.0;
     st.k = 0;
     st.pend = st.stored = 0;
@@ -350,14 +355,14 @@ struct NodeCount {
 // in fewer steps.  Returns true when the pair is finished.  COUNT selects
 // the instrumented variant (work counters).
 template <bool COUNT>
-__device__ __forceinline__ bool node_step(NodeState& st, Turn& T, double eps2, double2* stk, bool& onb,
-                                          NodeCount& nc, const Segs& sg, double qx, double qy) {
+__device__ __forceinline__ bool node_step(NodeState& st, double eps2, double2* stk, bool& onb, NodeCount& nc,
+                                          const Segs& sg, double qx, double qy) {
     if (!st.inside) {
         if (COUNT) {
             ++nc.leaf;
             nc.flops += 11;
         }
-        turn_mul(T, st.ax * st.bx + st.ay * st.by, st.ax * st.by - st.ay * st.bx);
+        st.n += ray_cross(st.ax, st.ay, st.bx, st.by);
         if (st.pend == 0) return true;
         const int kk = 63 - __clzll(st.pend);
         st.pend &= ~(1ull << kk);
@@ -432,23 +437,10 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
-// Angles of the first `count` buffered products (one lane each), added to
-// the query's winding sum.  Called with the whole wave active.
-__device__ __forceinline__ void drain_turns(const double2* fz, const int2* fq, int count, int lane, double* w) {
-    if (lane < count) {
-        const double2 z = fz[lane];
-        const int2 qk = fq[lane];
-        unsafeAtomicAdd(&w[qk.x], turn_angle(Turn{z.x, z.y, qk.y}));
-    }
-}
-
 template <bool COUNT>
 __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats,
                                               const uint8_t* seg_per, uint8_t* entry_depth) {
     __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
-    __shared__ double2 s_fz[kWavesPerWG][kWave];  // finished pairs: product z
-    __shared__ int2 s_fq[kWavesPerWG][kWave];     // finished pairs: query, turn count
-    int nfin = 0;                                 // entries in this wave's buffer (wave-uniform)
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     double2* stk = s_stack + wave * kStackSlots * kWave + lane;
@@ -461,7 +453,6 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
     const unsigned long long c_end = c_begin + per < n ? c_begin + per : n;
     unsigned long long next = c_begin;  // wave-uniform
     NodeState st;
-    Turn T{1.0, 0.0, 0};
     bool onb = false, has = false;
     uint32_t q = 0;
     double qx = 0.0, qy = 0.0;   // this lane's query (translated for periodic copies)
@@ -470,9 +461,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
     // window of the next 64 queue entries, one per lane, loaded one refill ahead
     uint2 win = make_uint2(0xffffffffu, 0u);
     if (next + lane < c_end) win = nq.qs[next + lane];
-    for (uint32_t it = 1;; ++it) {
-        // each step multiplies T by at most one factor: rescale every 8 steps
-        if ((it & 7) == 0) turn_norm(T);
+    for (;;) {
         const uint64_t idle = __ballot(!has);
         // refill idle lanes once kRefillMin of them are idle (each refill
         // waits for the gathers of the new pairs' data)
@@ -493,7 +482,6 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
                         qy -= sh.y;
                     }
                     node_init(st, sg, e.y, qx, qy);
-                    T = Turn{1.0, 0.0, 0};
                     onb = false;
                     has = true;
                 }
@@ -505,31 +493,15 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
             if (next >= c_end) break;
             continue;
         }
-        bool fin = false;
-        if (has) fin = node_step<COUNT>(st, T, eps2, stk, onb, nc, sg, qx, qy);
-        if (fin) {
+        if (has && node_step<COUNT>(st, eps2, stk, onb, nc, sg, qx, qy)) {
+            // the pair's angle is its chord angle (already in the far pass's
+            // sum) plus 2 pi n; most pairs have n = 0 and write nothing
             if (onb) out.lab[q] = 2;
+            else if (st.n != 0) unsafeAtomicAdd(&out.w[q], kTwoPi * (double)st.n);
             if (COUNT && entry_depth) entry_depth[cur] = (uint8_t)(st.pmax < 255 ? st.pmax : 255);
             has = false;
         }
-        // finished pairs wait in the wave's buffer; their angles are taken
-        // 64 at a time with every lane busy
-        const uint64_t fm = __ballot(fin && !onb);
-        if (fm) {
-            const int cnt = __popcll(fm);
-            if (nfin + cnt > kWave) {
-                drain_turns(s_fz[wave], s_fq[wave], nfin, lane, out.w);
-                nfin = 0;
-            }
-            if (fin && !onb) {
-                const int slot = nfin + __popcll(fm & ((1ull << lane) - 1ull));
-                s_fz[wave][slot] = make_double2(T.zr, T.zi);
-                s_fq[wave][slot] = make_int2((int)q, T.K);
-            }
-            nfin += cnt;
-        }
     }
-    drain_turns(s_fz[wave], s_fq[wave], nfin, lane, out.w);
     if (COUNT && stats.c) {
         const unsigned long long sp = wave_sum((unsigned long long)nc.split);
         const unsigned long long lf = wave_sum((unsigned long long)nc.leaf);
@@ -565,6 +537,7 @@ __global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, O
     }
     const double qx = pts.u[i * pts.stride], qy = pts.v[i * pts.stride];
     Turn T{1.0, 0.0, 0};
+    int xc = 0;
     bool onb = false;
     int cnt = 0;
     for (int s = ft.seg_begin[lo]; s < ft.seg_begin[lo + 1] && !onb; ++s) {
@@ -575,15 +548,19 @@ __global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, O
             onb = true;
             break;
         }
-        if (outside_ellipse(ra, rb, sg.hb2[s])) turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
-        else (void)near_from_global(T, sg, (uint32_t)s, qx, qy, eps2, stk, onb);
+        if (outside_ellipse(ra, rb, sg.hb2[s])) {
+            turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
+        } else {
+            chord_factor(T, ax, ay, bx, by);
+            (void)near_from_global(xc, sg, (uint32_t)s, qx, qy, eps2, stk, onb);
+        }
         if ((++cnt & 3) == 0) turn_norm(T);
     }
     if (onb) {
         out.w[i] = __builtin_nan("");
         out.lab[i] = 2;
     } else {
-        const double w = turn_angle(T) / kTwoPi;
+        const double w = (turn_angle(T) + kTwoPi * (double)xc) / kTwoPi;
         out.w[i] = w;
         out.lab[i] = classify(w, out.rule);
     }

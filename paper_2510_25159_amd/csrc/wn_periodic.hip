@@ -139,6 +139,7 @@ struct PerLane {
     int64_t qi;
     bool valid, onb;
     Turn T;
+    int xc;  // integer part of near pairs recursed in line (2 pi units)
     int nfill;
     int cnt;
 };
@@ -164,7 +165,7 @@ __device__ void flush_near_per(const uint2* buf, const double2* sbuf, int nfill,
             const uint2 ent = buf[e];
             if ((int64_t)ent.x == P.qi && !P.onb) {
                 const double2 sh = sbuf[e];
-                (void)near_from_global(P.T, sg, ent.y, P.qx - sh.x, P.qy - sh.y, eps2, stk, P.onb);
+                (void)near_from_global(P.xc, sg, ent.y, P.qx - sh.x, P.qy - sh.y, eps2, stk, P.onb);
             }
         }
     }
@@ -186,6 +187,7 @@ __device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double
         const bool far = outside_ellipse(ra, rb, sg.hb2[s]);
         if (work && far) turn_mul(P.T, ax * bx + ay * by, ax * by - ay * bx);
         const bool need = work && !P.onb && !far;
+        if (need) chord_factor(P.T, ax, ay, bx, by);  // the near pass adds the integer rest
         const uint64_t m = __ballot(need);
         if (m) {
             const int cntm = __popcll(m);
@@ -271,6 +273,7 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
         if (!P.valid) P.qx = P.qy = 0.0;
         P.onb = false;
         P.T = Turn{1.0, 0.0, 0};
+        P.xc = 0;
         P.nfill = 0;
         P.cnt = 0;
         const PFace pf = pt.face[f];
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
         }
         flush_near_per(s_nbuf[wave], s_nsh[wave], P.nfill, nq, lane, P, sg, eps2, stk);
         if (active) {
-            out.w[P.qi] = turn_angle(P.T);
+            out.w[P.qi] = turn_angle(P.T) + kTwoPi * (double)P.xc;
             out.lab[P.qi] = !P.valid ? 3 : (P.onb ? 2 : 0);
         }
     }

@@ -156,3 +156,46 @@ def test_config2_full_sampled(torch_cuda, oracle_lib):
     # every label is a valid code and no point is left unwritten
     assert set(np.unique(lab)).issubset({0, 1, 2})
     assert np.isfinite(w[lab != 2]).all()
+
+
+def _lens(p0, c1, c2, pn, d1, d2, w=None):
+    """Closed loop of two cubics p0 -> pn (controls c1, c2) and back (controls d1, d2)."""
+    a = np.array([p0, c1, c2, pn], dtype=np.float64)
+    b = np.array([pn, d1, d2, p0], dtype=np.float64)
+    return [(a, w), (b, None if w is None else w[::-1].copy())]
+
+
+def test_queries_on_chords_and_ray_ties(torch_cuda, oracle_lib):
+    """Queries exactly on the chord of a near segment (horizontal, vertical,
+    diagonal chords), on the chords' lines outside the segments, and level
+    with vertices: every tie the near-pair bookkeeping breaks must give the
+    oracle's winding number."""
+    lens_h = _lens((-1, 0), (-0.5, 0.3), (0.5, 0.3), (1, 0), (0.5, -0.3), (-0.5, -0.3))
+    lens_v = _lens((0, -1), (-0.3, -0.5), (-0.3, 0.5), (0, 1), (0.3, 0.5), (0.3, -0.5))
+    lens_d = _lens((-1, -1), (-1, 0), (0, 1), (1, 1), (1, 0), (0, -1))
+    lens_r = _lens((-1, 0), (-0.5, 0.3), (0.5, 0.3), (1, 0), (0.5, -0.3), (-0.5, -0.3),
+                   w=np.array([1.0, 2.0, 0.5, 1.0]))
+    # one bulge closed by a line: the queries sit between the cubic and its chord
+    half = [(np.array([[-1, 0], [-0.5, 0.3], [0.5, 0.3], [1, 0]], dtype=np.float64), None),
+            (np.array([[1, 0], [-1, 0]], dtype=np.float64), None)]
+    diamond = [(np.array([[1, 0], [0.7, 0.7], [0, 1]], dtype=np.float64), None),
+               (np.array([[0, 1], [-0.7, 0.7], [-1, 0]], dtype=np.float64), None),
+               (np.array([[-1, 0], [-0.7, -0.7], [0, -1]], dtype=np.float64), None),
+               (np.array([[0, -1], [0.7, -0.7], [1, 0]], dtype=np.float64), None)]
+    faces = W.faces_from_loops([[lens_h], [lens_v], [lens_d], [lens_r], [half], [diamond],
+                                [lens_h, diamond]])
+    on_h = [[0, 0], [0.5, 0], [-0.5, 0], [0.25, 0], [0, 0.1], [0, -0.1], [2, 0], [-2, 0], [0.75, 0]]
+    on_v = [[y, x] for x, y in on_h]
+    on_d = [[0, 0], [0.5, 0.5], [-0.25, -0.25], [2, 2], [-3, -3], [0.5, -0.5]]
+    pts = [np.array(on_h, float), np.array(on_v, float), np.array(on_d, float), np.array(on_h, float),
+           np.array([[0, 0.05], [0.5, 0.01], [0, 0.1], [-0.5, 0.1], [0.25, 0.2], [0, 0.3], [0.9, 0.01], [2, 0]],
+                    float),
+           np.array(on_h + [[0.5, 0.5], [-0.5, -0.5]], float),
+           np.array(on_h, float)]
+    q = W.queries_for_faces(pts)
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    assert np.all(n_o == 0)  # every query is well away from the curves
+    for sched in (0, 1):
+        w, lab = run_wn(faces, q, schedule=sched)
+        st = compare(w, lab, w_o, n_o)
+        assert st["compared"] == q.num_points
