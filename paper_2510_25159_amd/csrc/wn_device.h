@@ -82,7 +82,7 @@ __device__ __forceinline__ double turn_angle(const Turn& t) { return arg_of(t.zr
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool outside_ellipse(double ra, double rb, double hb2) {
     const double R = fma(-0.5, ra + rb, hb2);
-    return (R < 0.0) || (ra * rb > R * R);
+    return (R < 0.0) | (ra * rb > R * R);  // no short circuit: no branch
 }
 
 __device__ __forceinline__ double half_axis2(double B, double eta, int k) {
@@ -100,29 +100,53 @@ __device__ __forceinline__ double half_axis2(double B, double eta, int k) {
 // caller evaluates the same expressions on the same doubles, so the
 // decisions agree wherever two edges share a vertex.
 // ---------------------------------------------------------------------------
-// a x b, with a zero replaced by the signed zero of the displaced query's
-// orientation (b_x - a_x, then b_y - a_y).
-__device__ __forceinline__ double cross_sos(double ax, double ay, double bx, double by) {
-    const double o = fma(ax, by, -(ay * bx));
-    if (o != 0.0) return o;
-    const double d = bx != ax ? bx - ax : by - ay;
-    return copysign(0.0, d);
+// a x b as every caller computes it.
+__device__ __forceinline__ double cross_raw(double ax, double ay, double bx, double by) {
+    return fma(ax, by, -(ay * bx));
 }
 
-// +1 when a -> b crosses the ray upward, -1 downward, else 0.
+// Sign of the displaced query's orientation of a -> b: that of a x b, and
+// for an exact zero that of b_x - a_x, then of b_y - a_y (a == b: positive).
+__device__ __forceinline__ bool cross_neg(double ax, double ay, double bx, double by) {
+    const double o = cross_raw(ax, ay, bx, by);
+    const bool dx = bx != ax;
+    const bool tie = (dx & (bx < ax)) | (!dx & (by < ay));
+    return (o < 0.0) | ((o == 0.0) & tie);
+}
+
+// Crossing of an edge from a (a_low: a_y <= 0) to b (b_low: b_y <= 0) with
+// orientation sign neg: +1 upward, -1 downward, else 0.
+__device__ __forceinline__ int ray_cross_n(bool a_low, bool b_low, bool neg) {
+    return (a_low & !b_low & !neg) ? 1 : ((!a_low & b_low & neg) ? -1 : 0);
+}
+
 __device__ __forceinline__ int ray_cross(double ax, double ay, double bx, double by) {
-    const double o = cross_sos(ax, ay, bx, by);
-    const bool neg = __double2hiint(o) < 0;  // sign bit: -0 counts as negative
-    const bool up = ay <= 0.0 && by > 0.0 && !neg;
-    const bool dn = ay > 0.0 && by <= 0.0 && neg;
-    return up ? 1 : (dn ? -1 : 0);
+    return ray_cross_n(ay <= 0.0, by <= 0.0, cross_neg(ax, ay, bx, by));
 }
 
-// Chord factor of a near pair for the angle accumulator: (a . b, a x b) with
-// the same tie rule as ray_cross, so that a query on the chord gets +-pi on
-// the side that ray_cross assumes.
+// Angle factor (a . b, a x b) of the edge a -> b for the accumulator, with
+// an exact zero cross product replaced by the signed zero of cross_neg, so
+// that a query on the edge gets +-pi on the side that ray_cross assumes.
+__device__ __forceinline__ void edge_factor(Turn& T, double ax, double ay, double bx, double by) {
+    double o = cross_raw(ax, ay, bx, by);
+    if (o == 0.0) o = cross_neg(ax, ay, bx, by) ? -0.0 : 0.0;
+    turn_mul(T, fma(ax, bx, ay * by), o);
+}
+
+// Chord factor of a near pair whose integer rest comes from near_pair.
 __device__ __forceinline__ void chord_factor(Turn& T, double ax, double ay, double bx, double by) {
-    turn_mul(T, fma(ax, bx, ay * by), cross_sos(ax, ay, bx, by));
+    edge_factor(T, ax, ay, bx, by);
+}
+
+// Close a chain of edges that runs from c to e: the chain's angle sum is
+// the principal angle from c to e plus 2 pi (its crossings + those of the
+// closing edge e -> c).  The first term goes to the accumulator, the
+// closing edge's crossing to N; the closing edge's orientation is the
+// negation of c -> e's, so the two terms agree on ties.
+__device__ __forceinline__ void close_chain(Turn& T, int& N, double cx, double cy, double ex, double ey) {
+    edge_factor(T, cx, cy, ex, ey);
+    N += ray_cross_n(ey <= 0.0, cy <= 0.0, !cross_neg(cx, cy, ex, ey));
+    turn_norm(T);
 }
 
 // ---------------------------------------------------------------------------
@@ -147,28 +171,32 @@ __device__ __forceinline__ void load_coef(const Segs& sg, int s, Coef& c) {
     c.rat = sg.rat[s] != 0;
 }
 
-// gamma(t) = sum_i C(n,i) w_i P_i t^i (1-t)^(n-i) / sum_i C(n,i) w_i t^i (1-t)^(n-i).
-// Slot j holds index i = n - j, so Horner in t runs j = 0..n with (1-t)^j.
+// Reciprocal to full precision: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+
+// gamma(t) = sum_k C(n,k) w_k P_k t^k (1-t)^(n-k) / sum_k C(n,k) w_k t^k (1-t)^(n-k).
+// Slot k holds the k-th term's coefficient (zero for k > n).  Dividing both
+// sums by (1-t)^n leaves polynomials in u = t / (1-t), so one Horner pass
+// over all kCoef slots serves every degree without a branch; polynomial
+// segments carry w_k = 1 (denominator (1+u)^n).  With positive weights the
+// absolute error stays a few units in the last place of the control points'
+// size for any u (0 < t < 1).
 __device__ __forceinline__ void bez_eval(const Coef& c, double t, double& X, double& Y) {
-    const double s = 1.0 - t;
-    double ax = c.x[0], ay = c.y[0], aw = c.w[0], sp = 1.0;
+    const double u = t * recip(1.0 - t);
+    double px = c.x[kCoef - 1], py = c.y[kCoef - 1], pw = c.w[kCoef - 1];
 #pragma unroll
-    for (int j = 1; j < kCoef; ++j) {
-        if (j <= c.n) {
-            sp *= s;
-            ax = fma(ax, t, c.x[j] * sp);
-            ay = fma(ay, t, c.y[j] * sp);
-            aw = fma(aw, t, c.w[j] * sp);
-        }
+    for (int k = kCoef - 2; k >= 0; --k) {
+        px = fma(px, u, c.x[k]);
+        py = fma(py, u, c.y[k]);
+        pw = fma(pw, u, c.w[k]);
     }
-    if (c.rat) {
-        const double r = 1.0 / aw;
-        X = ax * r;
-        Y = ay * r;
-    } else {
-        X = ax;
-        Y = ay;
-    }
+    const double r = recip(pw);
+    X = px * r;
+    Y = py * r;
 }
 
 // ---------------------------------------------------------------------------

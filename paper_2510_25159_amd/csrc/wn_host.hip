@@ -237,11 +237,10 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
             }
             wrange[2 * (size_t)s] = wl;
             wrange[2 * (size_t)s + 1] = wh;
-            for (int j = 0; j <= n; ++j) {
-                const int i = n - j;
+            for (int i = 0; i <= n; ++i) {  // slot i: C(n,i) w_i (P_i, 1); slots above n stay zero
                 const double wi = is_rat ? w[i] : 1.0;
                 const double c = (double)kBinom[n][i] * wi;
-                double* slot = &coef[((size_t)s * kCoef + j) * 4];
+                double* slot = &coef[((size_t)s * kCoef + i) * 4];
                 slot[0] = c * u[i];
                 slot[1] = c * v[i];
                 slot[2] = c;

@@ -175,10 +175,17 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
         int nfill = 0;      // entries in this wave's near-pair buffer (wave-uniform)
         bool lost = false;  // a near pair of this lane's query did not fit in the queue
-        // End point of the previous segment of this wave, relative to the
-        // query: reused as the next start point when the two are the same
-        // point bit for bit (consecutive segments of a loop).
-        double pbx = 0.0, pby = 0.0, prb = 0.0;
+        // Chains: runs of consecutive segments of this wave in which each
+        // segment starts where the previous one ended (bit for bit).  A
+        // chain's chord angles sum to the angle from its start to its end
+        // plus 2 pi times the ray crossings of its chords and of the closing
+        // edge, so a pair costs a crossing test instead of an angle factor;
+        // near pairs keep their chord in the chain and get the integer rest
+        // from the recursion.
+        double csx = 0.0, csy = 0.0;             // start of the open chain, relative to the query
+        double pbx = 0.0, pby = 0.0, prb = 0.0;  // end of the previous segment, relative
+        bool pb_low = false;                     // pby <= 0 (below or on the ray's line)
+        bool open = false;                       // wave-uniform
         for (int c0 = s0; c0 < s1; c0 += kSegChunk) {
             __syncthreads();
             const int sj = c0 + tid;
@@ -195,37 +202,41 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
             // GS waves split the chunk into contiguous ranges
             const int jb = (cn * gs) / GS, je = (cn * (gs + 1)) / GS;
             for (int j0 = jb; j0 < je; j0 += kWave) {
-                const int jn = min(kWave, je - j0);
+                const int jn = __builtin_amdgcn_readfirstlane(min(kWave, je - j0));
                 // bit i: segment j0 + i starts where segment j0 + i - 1 ended
-                uint64_t jm = __ballot(lane < jn && s_join[j0 + lane] != 0);
-                if (j0 == jb && (GS > 1 || c0 == s0)) jm &= ~1ull;
-                for (int g0 = 0; g0 < jn; g0 += 8) {
-                    const int ge = min(g0 + 8, jn);
-                    for (int jj = g0; jj < ge; ++jj) {
+                const uint64_t jm = __ballot(lane < jn && s_join[j0 + lane] != 0);
+                int jj = 0;
+                while (jj < jn) {
+                    if (!(open & ((jm >> jj) & 1ull))) {  // a chain starts at segment j0 + jj
+                        if (open) close_chain(T, xc, csx, csy, pbx, pby);
+                        pbx = s_p0x[j0 + jj] - qx;
+                        pby = s_p0y[j0 + jj] - qy;
+                        prb = pbx * pbx + pby * pby;
+                        onb |= valid & (prb < eps2);
+                        pb_low = pby <= 0.0;
+                        csx = pbx;
+                        csy = pby;
+                        open = true;
+                    }
+                    // the run jj .. re - 1 continues the chain without a break
+                    const uint64_t brk = jj + 1 < 64 ? ~(jm >> (jj + 1)) : ~0ull;
+                    const int re = min(jn, jj + 1 + (int)__builtin_ctzll(brk | (1ull << 63)));
+                    for (; jj < re; ++jj) {
                         const int j = j0 + jj;
-                        const bool work = valid && !onb;
-                        double ax, ay, ra;
-                        if ((jm >> jj) & 1ull) {
-                            ax = pbx;  // already tested against eps as an end point
-                            ay = pby;
-                            ra = prb;
-                        } else {
-                            ax = s_p0x[j] - qx;
-                            ay = s_p0y[j] - qy;
-                            ra = ax * ax + ay * ay;
-                            if (work && ra < eps2) onb = true;
-                        }
+                        // a = the previous segment's end point (already tested against eps);
+                        // flags combine with & and | (no short circuit, no branch)
+                        const double ax = pbx, ay = pby, ra = prb;
+                        const bool a_low = pb_low;
                         const double bx = s_pnx[j] - qx, by = s_pny[j] - qy;
                         const double rb = bx * bx + by * by;
-                        if (work && rb < eps2) onb = true;
+                        onb |= valid & (rb < eps2);
+                        const bool b_low = by <= 0.0;
+                        xc += ray_cross_n(a_low, b_low, cross_neg(ax, ay, bx, by));  // = ray_cross(a, b)
                         pbx = bx;
                         pby = by;
                         prb = rb;
-                        const bool far = outside_ellipse(ra, rb, s_hb2[j]);
-                        if (far) turn_mul(T, ax * bx + ay * by, ax * by - ay * bx);
-                        bool need = work && !onb && !far;
-                        // near pair: its chord angle here, the integer rest from the recursion
-                        if (need) chord_factor(T, ax, ay, bx, by);
+                        pb_low = b_low;
+                        bool need = valid & !onb & !outside_ellipse(ra, rb, s_hb2[j]);
                         int depth = 0;
                         if constexpr (!INLINE) {
                             const uint64_t m = __ballot(need);
@@ -253,12 +264,14 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         if (INLINE && out.depth && active)
                             out.depth[qi * (int64_t)out.depth_stride + (c0 + j - s0)] = (uint8_t)depth;
                     }
-                    // rescale after at most 8 factors: each has modulus |a||b| in
-                    // [2^-100, 2^103] (|coordinates| < 1e15, |a|, |b| >= eps >= 1e-15)
-                    turn_norm(T);
                 }
             }
+            if (GS > 1 && open) {  // this wave's next range is not adjacent
+                close_chain(T, xc, csx, csy, pbx, pby);
+                open = false;
+            }
         }
+        if (open) close_chain(T, xc, csx, csy, pbx, pby);
         if constexpr (!INLINE) lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
         // combine the GS partial sums of each query group
         double ang = turn_angle(T) + kTwoPi * (double)xc;

@@ -64,10 +64,10 @@ __global__ __launch_bounds__(256) void k_lift(LiftArgs a, Segs sg) {
             box[2] = fmin(box[2], a.cpv[c] + oy);
             box[3] = fmax(box[3], a.cpv[c] + oy);
         }
-        for (int j = 0; j <= n; ++j) {
+        for (int j = 0; j <= n; ++j) {  // slot j: control point j
             double* slot = coef + ((size_t)s * kCoef + j) * 4;
-            slot[0] = a.cpu[c1 - j] * slot[2] + ox * slot[2];
-            slot[1] = a.cpv[c1 - j] * slot[2] + oy * slot[2];
+            slot[0] = a.cpu[c0 + j] * slot[2] + ox * slot[2];
+            slot[1] = a.cpv[c0 + j] * slot[2] + oy * slot[2];
         }
     }
     PLoop L{};
