@@ -223,11 +223,12 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                     const int re = min(jn, jj + 1 + (int)__builtin_ctzll(brk | (1ull << 63)));
                     for (; jj < re; ++jj) {
                         const int j = j0 + jj;
+                        const double cpx = s_pnx[j], cpy = s_pny[j], chb = s_hb2[j];
                         // a = the previous segment's end point (already tested against eps);
                         // flags combine with & and | (no short circuit, no branch)
                         const double ax = pbx, ay = pby, ra = prb;
                         const bool a_low = pb_low;
-                        const double bx = s_pnx[j] - qx, by = s_pny[j] - qy;
+                        const double bx = cpx - qx, by = cpy - qy;
                         const double rb = bx * bx + by * by;
                         onb |= valid & (rb < eps2);
                         const bool b_low = by <= 0.0;
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         pby = by;
                         prb = rb;
                         pb_low = b_low;
-                        bool need = valid & !onb & !outside_ellipse(ra, rb, s_hb2[j]);
+                        bool need = valid & !onb & !outside_ellipse(ra, rb, chb);
                         int depth = 0;
                         if constexpr (!INLINE) {
                             const uint64_t m = __ballot(need);
@@ -258,8 +259,8 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                             const int s = c0 + j;
                             Coef c;
                             load_coef(sg, s, c);
-                            depth = near_pair(xc, c, sg.B[s], sg.eta[s], s_pnx[j], s_pny[j], qx, qy, ax, ay, ra, bx,
-                                              by, rb, eps2, stk, onb);
+                            depth = near_pair(xc, c, sg.B[s], sg.eta[s], cpx, cpy, qx, qy, ax, ay, ra, bx, by, rb,
+                                              eps2, stk, onb);
                         }
                         if (INLINE && out.depth && active)
                             out.depth[qi * (int64_t)out.depth_stride + (c0 + j - s0)] = (uint8_t)depth;
@@ -369,69 +370,77 @@ struct NodeCount {
 // the instrumented variant (work counters).
 template <bool COUNT>
 __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double2* stk, bool& onb, NodeCount& nc,
-                                          const Segs& sg, double qx, double qy) {
-    if (!st.inside) {
-        if (COUNT) {
-            ++nc.leaf;
-            nc.flops += 11;
-        }
-        st.n += ray_cross(st.ax, st.ay, st.bx, st.by);
-        if (st.pend == 0) return true;
-        const int kk = 63 - __clzll(st.pend);
-        st.pend &= ~(1ull << kk);
-        st.a += ldexp(1.0, -st.k);
-        st.ax = st.bx;
-        st.ay = st.by;
-        st.ra = st.rb;
-        if (st.stored & (1ull << kk)) {
-            const double2 p = stk[(kk & (kStackSlots - 1)) * kWave];
-            st.bx = p.x;
-            st.by = p.y;
+                                          const Segs& sg, double qx, double qy, bool has) {
+    // State changes are selects rather than branches, so lanes on the two
+    // paths do not make the compiler copy the whole state at each branch;
+    // only the memory accesses and the curve evaluation sit under branches.
+    // 1. leaf: the chord's ray crossing, then pop the deepest pending interval
+    const bool leaf = has & !st.inside;
+    const int x = ray_cross(st.ax, st.ay, st.bx, st.by);
+    st.n += leaf ? x : 0;
+    bool fin = leaf & (st.pend == 0);
+    const bool pop = leaf & (st.pend != 0);
+    const int kk = 63 - __clzll(st.pend | 1ull);
+    const uint64_t kbit = 1ull << kk;
+    const bool kept = (st.stored & kbit) != 0;
+    double2 p = make_double2(0.0, 0.0);
+    if (pop & kept) p = stk[(kk & (kStackSlots - 1)) * kWave];
+    if (pop & !kept) {  // end point evicted from the ring: evaluate again
+        const double t = st.a + ldexp(1.0, -st.k) + ldexp(1.0, -kk);
+        if (t == 1.0) {
+            p.x = sg.pnx[st.seg] - qx;
+            p.y = sg.pny[st.seg] - qy;
         } else {
-            const double t = st.a + ldexp(1.0, -kk);
-            if (t == 1.0) {
-                st.bx = sg.pnx[st.seg] - qx;
-                st.by = sg.pny[st.seg] - qy;
-            } else {
-                bez_eval(st.c, t, st.bx, st.by);
-                if (COUNT) ++nc.reeval;
-            }
+            bez_eval(st.c, t, p.x, p.y);
         }
-        st.stored &= ~(1ull << kk);
-        st.rb = st.bx * st.bx + st.by * st.by;
-        st.k = kk;
-        st.inside = !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k));
+        if (COUNT) ++nc.reeval;
     }
-    if (st.inside) {
+    if (COUNT && leaf) {
+        ++nc.leaf;
+        nc.flops += 11;
+    }
+    st.a = pop ? st.a + ldexp(1.0, -st.k) : st.a;
+    st.pend = pop ? (st.pend & ~kbit) : st.pend;
+    st.stored = pop ? (st.stored & ~kbit) : st.stored;
+    st.k = pop ? kk : st.k;
+    st.ax = pop ? st.bx : st.ax;
+    st.ay = pop ? st.by : st.ay;
+    st.ra = pop ? st.rb : st.ra;
+    st.bx = pop ? p.x : st.bx;
+    st.by = pop ? p.y : st.by;
+    st.rb = pop ? fma(p.x, p.x, p.y * p.y) : st.rb;
+    st.inside = pop ? !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k)) : st.inside;
+    // 2. split: halve the current interval, continue with its left half
+    const bool split = has & !fin & st.inside;
+    const bool capped = split & (st.k >= kDepthCap);  // cannot happen for a validated eps
+    const bool sp = split & !capped;
+    const int k1 = st.k + 1;
+    double mx = 0.0, my = 0.0;
+    if (sp) {
+        stk[(k1 & (kStackSlots - 1)) * kWave] = make_double2(st.bx, st.by);
+        bez_eval(st.c, st.a + ldexp(1.0, -k1), mx, my);
         if (COUNT) {
             ++nc.split;
             nc.flops += 6 * st.c.n + 15;
+            nc.maxk = (uint32_t)k1 > nc.maxk ? (uint32_t)k1 : nc.maxk;
         }
-        if (st.k >= kDepthCap) {
-            onb = true;
-            return true;
-        }
-        const int k1 = st.k + 1;
-        stk[(k1 & (kStackSlots - 1)) * kWave] = make_double2(st.bx, st.by);
-        if (k1 >= kStackSlots) st.stored &= ~(1ull << (k1 - kStackSlots));
-        st.stored |= 1ull << k1;
-        st.pend |= 1ull << k1;
-        double mx, my;
-        bez_eval(st.c, st.a + ldexp(1.0, -k1), mx, my);
-        const double rm = mx * mx + my * my;
-        if (rm < eps2) {
-            onb = true;
-            return true;
-        }
-        st.bx = mx;
-        st.by = my;
-        st.rb = rm;
-        st.k = k1;
-        st.pmax = k1 > st.pmax ? k1 : st.pmax;
-        if (COUNT) nc.maxk = (uint32_t)k1 > nc.maxk ? (uint32_t)k1 : nc.maxk;
-        st.inside = !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k));
     }
-    return false;
+    const double rm = fma(mx, mx, my * my);
+    const bool hit = sp & (rm < eps2);
+    onb |= capped | hit;
+    fin |= capped | hit;
+    const bool adv = sp & !hit;
+    const uint64_t k1bit = 1ull << k1;
+    const uint64_t evict = k1 >= kStackSlots ? (1ull << (k1 - kStackSlots)) : 0ull;
+    st.stored = adv ? ((st.stored & ~evict) | k1bit) : st.stored;
+    st.pend = adv ? (st.pend | k1bit) : st.pend;
+    st.bx = adv ? mx : st.bx;
+    st.by = adv ? my : st.by;
+    st.rb = adv ? rm : st.rb;
+    st.k = adv ? k1 : st.k;
+    st.pmax = (adv & (k1 > st.pmax)) ? k1 : st.pmax;
+    st.inside = adv ? !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k)) : st.inside;
+    return fin;
 }
 
 template <typename T_>
@@ -506,7 +515,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
             if (next >= c_end) break;
             continue;
         }
-        if (has && node_step<COUNT>(st, eps2, stk, onb, nc, sg, qx, qy)) {
+        if (node_step<COUNT>(st, eps2, stk, onb, nc, sg, qx, qy, has)) {
             // the pair's angle is its chord angle (already in the far pass's
             // sum) plus 2 pi n; most pairs have n = 0 and write nothing
             if (onb) out.lab[q] = 2;
