@@ -177,6 +177,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--faces", type=int, default=2000, help="faces of the batched set (default: the full set)")
     ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--mixed-steps", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=6000000, help="points of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=int, default=1)
@@ -248,6 +249,23 @@ def main():
     log(f"batched: {ms_step:.3f} ms/step, {value:.3e} evals/s; kernels {kern}")
     w_b = out_w.cpu().numpy()
     lab_b = out_l.cpu().numpy()
+
+    # batched schedule with the FP32 far-field admission (same results, see the header)
+    def step_mixed(profile=None):
+        fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, precision=1,
+                 queries_per_wg=args.qpw, queue_policy=args.policy, profile=profile, stream=stream)
+
+    step_mixed()
+    torch.cuda.synchronize()
+    pm = wn.Profile(capacity=8 * args.mixed_steps + 64)
+    tm1 = time.perf_counter()
+    for _ in range(args.mixed_steps):
+        step_mixed(pm)
+    torch.cuda.synchronize()
+    ms_mixed = (time.perf_counter() - tm1) * 1e3 / max(args.mixed_steps, 1)
+    kern_mixed = {k: t_ / max(n, 1) for k, (n, t_) in pm.collect().items()}
+    mixed_same = bool(np.array_equal(out_l.cpu().numpy(), lab_b))
+    log(f"batched mixed: {ms_mixed:.3f} ms/step; kernels {kern_mixed}; labels equal to FP64: {mixed_same}")
 
     # plain schedule beside it (one launch per face, in-line recursion)
     step(0)
@@ -349,6 +367,8 @@ def main():
         "plain": {"ms_per_step": ms_plain, "evals_per_s": pairs / (ms_plain / 1e3),
                   "queries_per_s": N / (ms_plain / 1e3), "labels_equal_batched": plain_agree},
         "speedup_batched_vs_plain": ms_plain / ms_step,
+        "batched_mixed": {"ms_per_step": ms_mixed, "evals_per_s": pairs / (ms_mixed / 1e3), "kernel_ms": kern_mixed,
+                          "labels_equal_fp64": mixed_same},
         "mismatches": mism,
         "kernels": kernels,
         "work": st,

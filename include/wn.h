@@ -51,11 +51,14 @@ typedef enum {
     WN_DOMAIN_TORUS = 2       /* periodic in u and v (bi-periodic)             */
 } wn_domain;
 
-/* Arithmetic of the far-field pair test (the recursion is always FP64). */
+/* Arithmetic of the root ellipse test of planar faces (Alg. 1; the
+   recursion, the angle and crossing sums and periodic faces are always FP64).
+   MIXED admits a pair as far when FP32 distances exceed the ellipse's axis by
+   a relative 2^-20 margin, which certifies the FP64 decision, and falls back
+   to the FP64 test otherwise: its results equal FP64's bit for bit. */
 typedef enum {
     WN_PREC_FP64 = 0,  /* every step in FP64                                    */
-    WN_PREC_MIXED = 1  /* FP32 filtered far-field predicates, FP64 where the
-                          filter cannot certify the decision                     */
+    WN_PREC_MIXED = 1  /* FP32 certified far-field admission, FP64 fallback      */
 } wn_precision;
 
 /* Rounding of omega to a label (Sec. 4.1: "classify based on this value"). */

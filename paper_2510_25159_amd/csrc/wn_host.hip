@@ -262,9 +262,11 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     }
     // resident workgroups per CU of the persistent kernels (queried once, so
     // that a captured query issues no host queries)
-    h->bpc_far[0] = far_blocks_per_cu(false, 64);
-    h->bpc_far[1] = far_blocks_per_cu(false, 128);
-    h->bpc_far[2] = far_blocks_per_cu(false, 256);
+    for (int m = 0; m < 2; ++m) {
+        h->bpc_far[m][0] = far_blocks_per_cu(false, m == 1, 64);
+        h->bpc_far[m][1] = far_blocks_per_cu(false, m == 1, 128);
+        h->bpc_far[m][2] = far_blocks_per_cu(false, m == 1, 256);
+    }
     h->bpc_far_per = far_periodic_blocks_per_cu();
     h->bpc_near = near_blocks_per_cu();
 
@@ -546,7 +548,6 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     if (q.queries_per_wg != 0 && q.queries_per_wg != 64 && q.queries_per_wg != 128 && q.queries_per_wg != 256)
         return WN_E_INVALID;
     if (q.queue_policy < 0 || q.queue_policy > 2 || q.near_capacity < 0) return WN_E_INVALID;
-    if (prec == WN_PREC_MIXED) return WN_E_UNSUPPORTED;
     if (q.depth_log && sched != WN_SCHED_PLAIN) return WN_E_UNSUPPORTED;
     const int64_t N = p->num_points;
     const int32_t F = h->num_faces;
@@ -607,8 +608,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
             if (nf == 0) continue;
             ProfScope ps(q.profile, WN_KERNEL_FAR, st);
             if (h->h_dom[f] == WN_DOMAIN_PLANE) {
-                e = launch_far(true, qpw, h->sg, h->ft_plan, pts, nullptr, nullptr, nullptr, f, (nf + qpw - 1) / qpw,
-                               NearQueue{}, pout, h->eps2, st);
+                e = launch_far(true, prec == WN_PREC_MIXED, qpw, h->sg, h->ft_plan, pts, nullptr, nullptr, nullptr, f,
+                               (nf + qpw - 1) / qpw, NearQueue{}, pout, h->eps2, st);
             } else {
                 // one-face item table, in-line recursion (queue capacity 0), finalize of its range
                 const FaceTab one{h->ft_per.seg_begin, h->ft_per.order + h->per_pos[f], 1};
@@ -626,7 +627,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     }
 
     // batched / binned: persistent far launches, (binning), near pass, finalize, redo
-    e = far_passes(h, pts, qpw, q.queue_policy, sc, q.profile, st);
+    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, sc, q.profile, st);
     NearQueue nq = sc.nq;
     if (e == hipSuccess && binned) {
         const wn_predictor* pr = q.predictor;
@@ -719,8 +720,8 @@ void scratch_free(Scratch& sc, hipStream_t st) {
 
 int binning_grid(const wn_faces* h) { return std::min(1024, std::max(1, h->cu_count * 4)); }
 
-hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, Scratch& sc, wn_profile* prof,
-                      hipStream_t st) {
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, Scratch& sc,
+                      wn_profile* prof, hipStream_t st) {
     hipError_t e = hipSuccess;
     bool zero_near = true;
     const bool persistent = policy != 2;
@@ -732,10 +733,11 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
             zero_near = false;
         }
         if (e == hipSuccess) {
-            const int bpc = qpw == 64 ? h->bpc_far[0] : (qpw == 128 ? h->bpc_far[1] : h->bpc_far[2]);
+            const int* bp = h->bpc_far[mixed ? 1 : 0];
+            const int bpc = qpw == 64 ? bp[0] : (qpw == 128 ? bp[1] : bp[2]);
             const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR, st);
-            e = launch_far(false, qpw, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
+            e = launch_far(false, mixed, qpw, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
                            persistent ? sc.counters : nullptr, -1, grid, sc.nq, sc.out, h->eps2, st);
         }
     }

@@ -20,7 +20,7 @@ struct wn_faces {
     double eps = 1e-10, eps2 = 1e-20;
     int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
     int cu_count = 0;
-    int bpc_far[3] = {1, 1, 1};  // resident workgroups per CU, k_far batched, 64/128/256 points per workgroup
+    int bpc_far[2][3] = {{1, 1, 1}, {1, 1, 1}};  // resident workgroups per CU, k_far batched: [FP64, MIXED][64/128/256 points per workgroup]
     int bpc_far_per = 1, bpc_near = 1;
     std::vector<int32_t> h_seg_begin;
     std::vector<int32_t> h_dom;
@@ -73,7 +73,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
 void scratch_free(Scratch& sc, hipStream_t st);
 
 // Item build + persistent far passes (planar, periodic) filling sc.nq.
-hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, Scratch& sc, wn_profile* prof,
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, Scratch& sc, wn_profile* prof,
                       hipStream_t st);
 // Near pass over nq; entry_depth optional.
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,

@@ -17,6 +17,7 @@ constexpr int kDepthCap = 52;       // dyadic parameters a + 2^-k stay exact in 
 constexpr int kSegChunk = kWG;      // segments staged in LDS per chunk
 constexpr int kNearBuf = 256;       // per-wave LDS buffer of near pairs before one queue append
 constexpr int kRefillMin = 16;      // near pass: idle lanes of a wave before they take new pairs
+constexpr float kMixedMargin = 0x1p-20f; // precision MIXED: relative FP32 admission margin
 // Relative inflation of the ellipse axis: the far decision is taken only when
 // it survives rounding (Lemma 1 boundary "<=" counts as inside, so inflating
 // the bound only sends borderline pairs to the recursion).
@@ -134,14 +135,14 @@ struct Out {
 namespace wn {
 hipError_t launch_build_items(const FaceTab& ft, const Points& pts, int qpw, int32_t* item_offs, int2* item_map,
                               int64_t map_cap, uint32_t* counters, bool zero_near, hipStream_t st);
-hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
+hipError_t launch_far(bool inline_near, bool mixed, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
                       const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
                        Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st);
 hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, int32_t nf, hipStream_t st);
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st);
-int far_blocks_per_cu(bool inline_near, int qpw);
+int far_blocks_per_cu(bool inline_near, bool mixed, int qpw);
 int near_blocks_per_cu();
 hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);
 hipError_t launch_far_periodic(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, in
 // Item source: item_counter != nullptr -> persistent loop popping items;
 // else item = blockIdx.x.  single_face >= 0 -> items are the tiles of that face.
 // ---------------------------------------------------------------------------
-template <bool INLINE, int GQ>
+template <bool INLINE, int GQ, bool MIXED>
 __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
                                              const int2* item_map, uint32_t* item_counter, int32_t single_face,
                                              NearQueue nq, Out out, double eps2) {
@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
     constexpr int QPW = kWave * GQ;
     __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
     __shared__ uint8_t s_join[kSegChunk];
+    __shared__ float s_bef[MIXED ? kSegChunk : 1];  // FP32 upper bound of the root ellipse's axis
     __shared__ double2 s_stack[INLINE ? kWavesPerWG * kStackSlots * kWave : 1];
     __shared__ double s_ang[kWavesPerWG][kWave];
     __shared__ int s_flag[kWavesPerWG][kWave];
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         double csx = 0.0, csy = 0.0;             // start of the open chain, relative to the query
         double pbx = 0.0, pby = 0.0, prb = 0.0;  // end of the previous segment, relative
         bool pb_low = false;                     // pby <= 0 (below or on the ray's line)
+        float pdf = 0.f;                         // |pb| in FP32 (precision MIXED)
         bool open = false;                       // wave-uniform
         for (int c0 = s0; c0 < s1; c0 += kSegChunk) {
             __syncthreads();
@@ -196,6 +198,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                 s_pny[tid] = sg.pny[sj];
                 s_hb2[tid] = sg.hb2[sj];
                 s_join[tid] = sg.join[sj];
+                if constexpr (MIXED) s_bef[tid] = __double2float_ru(sqrt(2.0 * s_hb2[tid]));
             }
             __syncthreads();
             const int cn = min(kSegChunk, s1 - c0);
@@ -214,6 +217,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         prb = pbx * pbx + pby * pby;
                         onb |= valid & (prb < eps2);
                         pb_low = pby <= 0.0;
+                        if constexpr (MIXED) pdf = sqrtf(fmaf((float)pbx, (float)pbx, (float)pby * (float)pby));
                         csx = pbx;
                         csy = pby;
                         open = true;
@@ -237,7 +241,22 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         pby = by;
                         prb = rb;
                         pb_low = b_low;
-                        bool need = valid & !onb & !outside_ellipse(ra, rb, chb);
+                        bool near;
+                        if constexpr (MIXED) {
+                            // FP32 admission: d1 + d2 beyond the axis by a relative 2^-20
+                            // margin (far above the FP32 rounding of the two distances)
+                            // proves the pair far; the FP64 test runs only when some lane
+                            // is not admitted
+                            const float bxf = (float)bx, byf = (float)by;
+                            const float d2f = sqrtf(fmaf(bxf, bxf, byf * byf));
+                            const bool admit = (pdf + d2f) * (1.0f - kMixedMargin) > s_bef[j] * (1.0f + kMixedMargin);
+                            pdf = d2f;
+                            near = false;
+                            if (__ballot(!admit) != 0ull) near = !admit & !outside_ellipse(ra, rb, chb);
+                        } else {
+                            near = !outside_ellipse(ra, rb, chb);
+                        }
+                        bool need = valid & !onb & near;
                         int depth = 0;
                         if constexpr (!INLINE) {
                             const uint64_t m = __ballot(need);
@@ -623,37 +642,41 @@ hipError_t launch_build_items(const FaceTab& ft, const Points& pts, int qpw, int
     return hipGetLastError();
 }
 
-template <bool INLINE>
+template <bool INLINE, bool MIXED>
 static hipError_t launch_far_q(int qpw, dim3 grid, hipStream_t st, const Segs& sg, const FaceTab& ft,
                                const Points& pts, const int32_t* item_offs, const int2* item_map,
                                uint32_t* item_counter, int32_t single_face, NearQueue nq, Out out, double eps2) {
     switch (qpw) {
         case 64:
-            hipLaunchKernelGGL((k_far<INLINE, 1>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+            hipLaunchKernelGGL((k_far<INLINE, 1, MIXED>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
                                item_counter, single_face, nq, out, eps2);
             break;
         case 128:
-            hipLaunchKernelGGL((k_far<INLINE, 2>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+            hipLaunchKernelGGL((k_far<INLINE, 2, MIXED>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
                                item_counter, single_face, nq, out, eps2);
             break;
         default:
-            hipLaunchKernelGGL((k_far<INLINE, 4>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+            hipLaunchKernelGGL((k_far<INLINE, 4, MIXED>), grid, dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
                                item_counter, single_face, nq, out, eps2);
             break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_far(bool inline_near, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
+hipError_t launch_far(bool inline_near, bool mixed, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
                       const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     const dim3 g((unsigned)grid);
     if (inline_near)
-        return launch_far_q<true>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter, single_face, nq, out,
-                                  eps2);
-    return launch_far_q<false>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter, single_face, nq, out,
-                               eps2);
+        return mixed ? launch_far_q<true, true>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter,
+                                                single_face, nq, out, eps2)
+                     : launch_far_q<true, false>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter,
+                                                 single_face, nq, out, eps2);
+    return mixed ? launch_far_q<false, true>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter, single_face,
+                                             nq, out, eps2)
+                 : launch_far_q<false, false>(qpw, g, st, sg, ft, pts, item_offs, item_map, item_counter,
+                                              single_face, nq, out, eps2);
 }
 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
@@ -688,18 +711,18 @@ int near_blocks_per_cu() {
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-int far_blocks_per_cu(bool inline_near, int qpw) {
+template <bool INLINE, bool MIXED>
+static hipError_t far_occupancy(int* nb, int qpw) {
+    return qpw == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_far<INLINE, 1, MIXED>, kWG, 0)
+           : qpw == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_far<INLINE, 2, MIXED>, kWG, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_far<INLINE, 4, MIXED>, kWG, 0);
+}
+
+int far_blocks_per_cu(bool inline_near, bool mixed, int qpw) {
     int nb = 0;
     hipError_t e;
-    if (inline_near) {
-        e = qpw == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<true, 1>, kWG, 0)
-            : qpw == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<true, 2>, kWG, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<true, 4>, kWG, 0);
-    } else {
-        e = qpw == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<false, 1>, kWG, 0)
-            : qpw == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<false, 2>, kWG, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far<false, 4>, kWG, 0);
-    }
+    if (inline_near) e = mixed ? far_occupancy<true, true>(&nb, qpw) : far_occupancy<true, false>(&nb, qpw);
+    else e = mixed ? far_occupancy<false, true>(&nb, qpw) : far_occupancy<false, false>(&nb, qpw);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

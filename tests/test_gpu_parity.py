@@ -61,6 +61,24 @@ def test_config2_subset_parity(torch_cuda, c2_small, schedule, policy):
     assert st["compared"] > 0.99 * q.num_points
 
 
+FP32_TOL = 1e-5  # |omega_gpu - omega_oracle| bound for the mixed-precision path
+
+
+@pytest.mark.parametrize("schedule,qpw", [(0, 256), (1, 64), (1, 256), (2, 0)])
+def test_mixed_precision(torch_cuda, c2_small, schedule, qpw):
+    """FP32 admission with the FP64 fallback: within the FP32 bound of the
+    oracle, and (by construction) equal to the FP64 path bit for bit."""
+    f, q, w_o, n_o = c2_small
+    print(f"config2[0:24] mixed schedule={schedule} qpw={qpw}", flush=True)
+    kw = dict(schedule=schedule, queries_per_wg=qpw, bin_source=1 if schedule == 2 else 0)
+    w32, lab32 = run_wn(f, q, precision=1, **kw)
+    compare(w32, lab32, w_o, n_o, tol=FP32_TOL)
+    w64, lab64 = run_wn(f, q, precision=0, **kw)
+    assert np.array_equal(lab32, lab64)
+    ok = np.isfinite(w64)
+    assert np.array_equal(np.isfinite(w32), ok) and np.array_equal(w32[ok], w64[ok])
+
+
 def test_near_queue_overflow_falls_back_in_line(torch_cuda, c2_small):
     f, q, w_o, n_o = c2_small
     w, lab = run_wn(f, q, schedule=1, near_capacity=1000)
