@@ -107,11 +107,24 @@ __device__ __forceinline__ double cross_raw(double ax, double ay, double bx, dou
 
 // Sign of the displaced query's orientation of a -> b: that of a x b, and
 // for an exact zero that of b_x - a_x, then of b_y - a_y (a == b: positive).
+__device__ __forceinline__ bool cross_tie_neg(double ax, double ay, double bx, double by) {
+    const bool dx = bx != ax;
+    return (dx & (bx < ax)) | (!dx & (by < ay));
+}
 __device__ __forceinline__ bool cross_neg(double ax, double ay, double bx, double by) {
     const double o = cross_raw(ax, ay, bx, by);
-    const bool dx = bx != ax;
-    const bool tie = (dx & (bx < ax)) | (!dx & (by < ay));
-    return (o < 0.0) | ((o == 0.0) & tie);
+    return (o < 0.0) | ((o == 0.0) & cross_tie_neg(ax, ay, bx, by));
+}
+// The same for a wave in uniform control flow: the tie is only evaluated
+// when some lane has an exact zero (the empty asm keeps that a branch).
+__device__ __forceinline__ bool cross_neg_wave(double ax, double ay, double bx, double by) {
+    const double o = cross_raw(ax, ay, bx, by);
+    bool neg = o < 0.0;
+    if (__builtin_amdgcn_ballot_w64(o == 0.0) != 0ull) {
+        asm volatile("");
+        neg |= (o == 0.0) & cross_tie_neg(ax, ay, bx, by);
+    }
+    return neg;
 }
 
 // Crossing of an edge from a (a_low: a_y <= 0) to b (b_low: b_y <= 0) with

@@ -175,7 +175,9 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         bool onb = false;
         const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
         int nfill = 0;      // entries in this wave's near-pair buffer (wave-uniform)
-        bool lost = false;  // a near pair of this lane's query did not fit in the queue
+        // a near pair of this lane's query did not fit in the queue (an int, not
+        // a bool: lane masks updated inside divergent code cost scalar merges)
+        int lost = 0;
         // Chains: runs of consecutive segments of this wave in which each
         // segment starts where the previous one ended (bit for bit).  A
         // chain's chord angles sum to the angle from its start to its end
@@ -225,6 +227,44 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                     // the run jj .. re - 1 continues the chain without a break
                     const uint64_t brk = jj + 1 < 64 ? ~(jm >> (jj + 1)) : ~0ull;
                     const int re = min(jn, jj + 1 + (int)__builtin_ctzll(brk | (1ull << 63)));
+                    if constexpr (!INLINE && !MIXED) {
+                        // two segments per trip: their arithmetic is independent apart
+                        // from the shared end point, which gives each wave two chains
+                        // of dependent instructions to interleave
+                        auto append = [&](bool need, int j) {
+                            const uint64_t m = __builtin_amdgcn_ballot_w64(need);
+                            if (m) {
+                                const int cntm = __popcll(m);
+                                if (nfill + cntm > kNearBuf) {
+                                    lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
+                                    nfill = 0;
+                                }
+                                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                                if (need) s_nbuf[wave][nfill + rank] = make_uint2((uint32_t)qi, (uint32_t)(c0 + j));
+                                nfill += cntm;
+                            }
+                        };
+                        for (; jj + 1 < re; jj += 2) {
+                            const int j = j0 + jj;
+                            const double bx0 = s_pnx[j] - qx, by0 = s_pny[j] - qy;
+                            const double bx1 = s_pnx[j + 1] - qx, by1 = s_pny[j + 1] - qy;
+                            const double rb0 = bx0 * bx0 + by0 * by0, rb1 = bx1 * bx1 + by1 * by1;
+                            onb |= valid & ((rb0 < eps2) | (rb1 < eps2));
+                            const bool b0_low = by0 <= 0.0, b1_low = by1 <= 0.0;
+                            xc += ray_cross_n(pb_low, b0_low, cross_neg_wave(pbx, pby, bx0, by0)) +
+                                  ray_cross_n(b0_low, b1_low, cross_neg_wave(bx0, by0, bx1, by1));
+                            const bool near0 = !outside_ellipse(prb, rb0, s_hb2[j]);
+                            const bool near1 = !outside_ellipse(rb0, rb1, s_hb2[j + 1]);
+                            // (an eps hit at j + 1 also drops pair j: the query is on the boundary)
+                            const bool live = valid & !onb;
+                            pbx = bx1;
+                            pby = by1;
+                            prb = rb1;
+                            pb_low = b1_low;
+                            append(live & near0, j);
+                            append(live & near1, j + 1);
+                        }
+                    }
                     for (; jj < re; ++jj) {
                         const int j = j0 + jj;
                         const double cpx = s_pnx[j], cpy = s_pny[j], chb = s_hb2[j];
@@ -236,7 +276,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         const double rb = bx * bx + by * by;
                         onb |= valid & (rb < eps2);
                         const bool b_low = by <= 0.0;
-                        xc += ray_cross_n(a_low, b_low, cross_neg(ax, ay, bx, by));  // = ray_cross(a, b)
+                        xc += ray_cross_n(a_low, b_low, cross_neg_wave(ax, ay, bx, by));  // = ray_cross(a, b)
                         pbx = bx;
                         pby = by;
                         prb = rb;
@@ -259,11 +299,11 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         bool need = valid & !onb & near;
                         int depth = 0;
                         if constexpr (!INLINE) {
-                            const uint64_t m = __ballot(need);
+                            const uint64_t m = __builtin_amdgcn_ballot_w64(need);
                             if (m) {
                                 const int cntm = __popcll(m);
                                 if (nfill + cntm > kNearBuf) {
-                                    lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
+                                    lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
                                     nfill = 0;
                                 }
                                 const int rank = __popcll(m & ((1ull << lane) - 1ull));
@@ -292,7 +332,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
             }
         }
         if (open) close_chain(T, xc, csx, csy, pbx, pby);
-        if constexpr (!INLINE) lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi);
+        if constexpr (!INLINE) lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
         // combine the GS partial sums of each query group
         double ang = turn_angle(T) + kTwoPi * (double)xc;
         if constexpr (GS > 1) {
@@ -304,7 +344,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                 for (int g = 1; g < GS; ++g) {
                     ang += s_ang[wave + g][lane];
                     onb = onb || (s_flag[wave + g][lane] & 1);
-                    lost = lost || (s_flag[wave + g][lane] & 2);
+                    lost |= (s_flag[wave + g][lane] & 2) ? 1 : 0;
                 }
             }
         }
@@ -338,16 +378,22 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
 // chunk (wave-local counter, no global atomics).  One node of Alg. 1 per
 // loop trip, so lanes with short and long recursions interleave.
 // ---------------------------------------------------------------------------
+// Pending intervals of the near pass: LDS ring of kNearSlots slots per lane,
+// each holding the two end points of a deferred interval (32 B).
+constexpr int kNearSlots = 4;
+static_assert(kNearSlots == 4, "the eviction mask assumes four slots (levels of one residue mod 4)");
+
+// Near-pair state.  The current interval [a, a + 2^-k] is always one that
+// failed its ellipse test (the root is queued for exactly that reason).
 struct NodeState {
     Coef c;  // translated by -q: evaluates gamma(t) - q directly
     double B, eta;
-    double a, ax, ay, ra, bx, by, rb;
-    uint64_t pend, stored;
+    double a, ax, ay, ra, bx, by, rb;  // current interval: left end, end points relative to q, |.|^2
+    uint64_t pend, stored;             // levels with a deferred right sibling / whose slot still holds it
     int k;
-    int n;         // leaves' ray crossings minus the segment chord's (see near_pair)
+    int n;         // far children's ray crossings minus the segment chord's (see near_pair)
     int pmax;      // deepest level of this pair
-    uint32_t seg;  // segment (its end point is reloaded in the rare evicted t = 1 case)
-    bool inside;
+    uint32_t seg;  // segment (its end point is reloaded when an evicted interval ends at t = 1)
 };
 
 __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_t s, double qx, double qy) {
@@ -372,7 +418,6 @@ __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_
     st.k = 0;
     st.pend = st.stored = 0;
     st.pmax = 0;
-    st.inside = true;  // queued pairs failed the root ellipse test
 }
 
 struct NodeCount {
@@ -380,85 +425,94 @@ struct NodeCount {
     uint64_t flops = 0;
 };
 
-// One step of Alg. 1 on the current interval: when it passed the ellipse
-// test (a leaf) its chord factor is taken and the next pending interval is
-// popped and tested; then, when the current interval failed the test, it is
-// halved and its left half tested.  A step therefore takes at most one leaf
-// and one split, so lanes whose recursions alternate between the two finish
-// in fewer steps.  Returns true when the pair is finished.  COUNT selects
-// the instrumented variant (work counters).
+// One split of Alg. 1: the current interval is halved at its midpoint and
+// BOTH halves are tested.  A half that passes is a leaf: its chord's ray
+// crossing is taken at once (the sum does not depend on the order).  A half
+// that fails becomes the current interval; when both fail, the right one is
+// deferred.  When neither fails, the deepest deferred interval resumes (it
+// failed its test when its parent was split).  Every step is therefore one
+// curve evaluation: a pair costs as many steps as Alg. 1 has split nodes,
+// and the set of tested nodes, splits and leaves is exactly Alg. 1's.
+// State changes are selects; the memory accesses and the evaluations sit
+// under branches.  Returns true when the pair is finished.
 template <bool COUNT>
-__device__ __forceinline__ bool node_step(NodeState& st, double eps2, double2* stk, bool& onb, NodeCount& nc,
+__device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* stk, bool& onb, NodeCount& nc,
                                           const Segs& sg, double qx, double qy, bool has) {
-    // State changes are selects rather than branches, so lanes on the two
-    // paths do not make the compiler copy the whole state at each branch;
-    // only the memory accesses and the curve evaluation sit under branches.
-    // 1. leaf: the chord's ray crossing, then pop the deepest pending interval
-    const bool leaf = has & !st.inside;
-    const int x = ray_cross(st.ax, st.ay, st.bx, st.by);
-    st.n += leaf ? x : 0;
-    bool fin = leaf & (st.pend == 0);
-    const bool pop = leaf & (st.pend != 0);
-    const int kk = 63 - __clzll(st.pend | 1ull);
-    const uint64_t kbit = 1ull << kk;
-    const bool kept = (st.stored & kbit) != 0;
-    double2 p = make_double2(0.0, 0.0);
-    if (pop & kept) p = stk[(kk & (kStackSlots - 1)) * kWave];
-    if (pop & !kept) {  // end point evicted from the ring: evaluate again
-        const double t = st.a + ldexp(1.0, -st.k) + ldexp(1.0, -kk);
-        if (t == 1.0) {
-            p.x = sg.pnx[st.seg] - qx;
-            p.y = sg.pny[st.seg] - qy;
-        } else {
-            bez_eval(st.c, t, p.x, p.y);
-        }
-        if (COUNT) ++nc.reeval;
-    }
-    if (COUNT && leaf) {
-        ++nc.leaf;
-        nc.flops += 11;
-    }
-    st.a = pop ? st.a + ldexp(1.0, -st.k) : st.a;
-    st.pend = pop ? (st.pend & ~kbit) : st.pend;
-    st.stored = pop ? (st.stored & ~kbit) : st.stored;
-    st.k = pop ? kk : st.k;
-    st.ax = pop ? st.bx : st.ax;
-    st.ay = pop ? st.by : st.ay;
-    st.ra = pop ? st.rb : st.ra;
-    st.bx = pop ? p.x : st.bx;
-    st.by = pop ? p.y : st.by;
-    st.rb = pop ? fma(p.x, p.x, p.y * p.y) : st.rb;
-    st.inside = pop ? !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k)) : st.inside;
-    // 2. split: halve the current interval, continue with its left half
-    const bool split = has & !fin & st.inside;
-    const bool capped = split & (st.k >= kDepthCap);  // cannot happen for a validated eps
-    const bool sp = split & !capped;
+    const bool capped = has & (st.k >= kDepthCap);  // cannot happen for a validated eps
+    const bool sp = has & !capped;
     const int k1 = st.k + 1;
+    const double h = ldexp(1.0, -k1);
+    const double tm = st.a + h;
     double mx = 0.0, my = 0.0;
-    if (sp) {
-        stk[(k1 & (kStackSlots - 1)) * kWave] = make_double2(st.bx, st.by);
-        bez_eval(st.c, st.a + ldexp(1.0, -k1), mx, my);
-        if (COUNT) {
-            ++nc.split;
-            nc.flops += 6 * st.c.n + 15;
-            nc.maxk = (uint32_t)k1 > nc.maxk ? (uint32_t)k1 : nc.maxk;
-        }
-    }
+    if (sp) bez_eval(st.c, tm, mx, my);
     const double rm = fma(mx, mx, my * my);
     const bool hit = sp & (rm < eps2);
     onb |= capped | hit;
-    fin |= capped | hit;
-    const bool adv = sp & !hit;
+    bool fin = capped | hit;
+    const bool go = sp & !hit;
+    // the two halves [a, m] and [m, b] at level k + 1
+    const double hb = half_axis2(st.B, st.eta, k1);
+    const bool lfar = outside_ellipse(st.ra, rm, hb);
+    const bool rfar = outside_ellipse(rm, st.rb, hb);
+    const int xl = ray_cross(st.ax, st.ay, mx, my);
+    const int xr = ray_cross(mx, my, st.bx, st.by);
+    st.n += go ? ((lfar ? xl : 0) + (rfar ? xr : 0)) : 0;
+    if (COUNT && go) {
+        ++nc.split;
+        nc.flops += 6 * st.c.n + 15 + 11 * ((lfar ? 1 : 0) + (rfar ? 1 : 0));
+        nc.leaf += (lfar ? 1 : 0) + (rfar ? 1 : 0);
+        nc.maxk = (uint32_t)k1 > nc.maxk ? (uint32_t)k1 : nc.maxk;
+    }
+    const bool both = go & !lfar & !rfar;  // defer the right half, continue left
+    const bool left = go & !lfar;          // continue with the left half
+    const bool right = go & lfar & !rfar;  // continue with the right half
+    const bool none = go & lfar & rfar;    // resume the deepest deferred interval
     const uint64_t k1bit = 1ull << k1;
-    const uint64_t evict = k1 >= kStackSlots ? (1ull << (k1 - kStackSlots)) : 0ull;
-    st.stored = adv ? ((st.stored & ~evict) | k1bit) : st.stored;
-    st.pend = adv ? (st.pend | k1bit) : st.pend;
-    st.bx = adv ? mx : st.bx;
-    st.by = adv ? my : st.by;
-    st.rb = adv ? rm : st.rb;
-    st.k = adv ? k1 : st.k;
-    st.pmax = (adv & (k1 > st.pmax)) ? k1 : st.pmax;
-    st.inside = adv ? !outside_ellipse(st.ra, st.rb, half_axis2(st.B, st.eta, st.k)) : st.inside;
+    if (both) stk[(k1 & (kNearSlots - 1)) * kWave] = make_double4(mx, my, st.bx, st.by);
+    // the slot's previous occupant, at any level of the same residue, is evicted
+    const uint64_t evict = 0x1111111111111111ull << (k1 & (kNearSlots - 1));
+    st.stored = both ? ((st.stored & ~evict) | k1bit) : st.stored;
+    st.pend = both ? (st.pend | k1bit) : st.pend;
+    st.pmax = (go & (k1 > st.pmax)) ? k1 : st.pmax;
+    // continue left: b <- m;  continue right: a <- m
+    st.bx = left ? mx : st.bx;
+    st.by = left ? my : st.by;
+    st.rb = left ? rm : st.rb;
+    st.a = right ? tm : st.a;
+    st.ax = right ? mx : st.ax;
+    st.ay = right ? my : st.ay;
+    st.ra = right ? rm : st.ra;
+    st.k = (left | right) ? k1 : st.k;
+    fin |= none & (st.pend == 0);
+    const bool pop = none & (st.pend != 0);
+    const int kk = 63 - __clzll(st.pend | 1ull);
+    const uint64_t kbit = 1ull << kk;
+    const bool kept = (st.stored & kbit) != 0;
+    // deferred interval [a', a' + 2^-kk]: a' = (a rounded down to 2^-(kk-1)) + 2^-kk
+    const double ap = ldexp(floor(ldexp(st.a, kk - 1)), 1 - kk) + ldexp(1.0, -kk);
+    double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (pop & kept) p = stk[(kk & (kNearSlots - 1)) * kWave];
+    if (pop & !kept) {  // slot reused by a deeper interval: evaluate both ends again
+        bez_eval(st.c, ap, p.x, p.y);
+        const double te = ap + ldexp(1.0, -kk);
+        if (te == 1.0) {
+            p.z = sg.pnx[st.seg] - qx;
+            p.w = sg.pny[st.seg] - qy;
+        } else {
+            bez_eval(st.c, te, p.z, p.w);
+        }
+        if (COUNT) nc.reeval += 2;
+    }
+    st.pend = pop ? (st.pend & ~kbit) : st.pend;
+    st.stored = pop ? (st.stored & ~kbit) : st.stored;
+    st.a = pop ? ap : st.a;
+    st.k = pop ? kk : st.k;
+    st.ax = pop ? p.x : st.ax;
+    st.ay = pop ? p.y : st.ay;
+    st.ra = pop ? fma(p.x, p.x, p.y * p.y) : st.ra;
+    st.bx = pop ? p.z : st.bx;
+    st.by = pop ? p.w : st.by;
+    st.rb = pop ? fma(p.z, p.z, p.w * p.w) : st.rb;
     return fin;
 }
 
@@ -481,10 +535,10 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 template <bool COUNT>
 __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats,
                                               const uint8_t* seg_per, uint8_t* entry_depth) {
-    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
-    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    double4* stk = s_stack + wave * kNearSlots * kWave + lane;
     unsigned long long n = *nq.count;
     n = n < nq.cap ? n : nq.cap;
     const unsigned long long nw = (unsigned long long)gridDim.x * kWavesPerWG;
