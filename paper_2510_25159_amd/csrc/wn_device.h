@@ -213,13 +213,34 @@ __device__ __forceinline__ void bez_eval(const Coef& c, double t, double& X, dou
 }
 
 // ---------------------------------------------------------------------------
-// near pair: Alg. 1 on an explicit stack.  The root [0,1] is known to be
+// Deferred intervals live in an LDS ring of kNearSlots slots per lane
+// (slot = level mod kNearSlots, 32 B: both end points).  Storing at a level
+// evicts whatever the slot held, at any level of the same residue.
+// ---------------------------------------------------------------------------
+static_assert(kNearSlots == 4, "the eviction mask assumes four slots");
+__device__ __forceinline__ uint64_t slot_evict_mask(int level) {
+    return 0x1111111111111111ull << (level & (kNearSlots - 1));
+}
+
+// Left end of the interval deferred at level kk while the current interval
+// (left end a) lies in its left sibling: (a rounded down to 2^-(kk-1)) + 2^-kk.
+__device__ __forceinline__ double deferred_left(double a, int kk) {
+    return ldexp(floor(ldexp(a, kk - 1)), 1 - kk) + ldexp(1.0, -kk);
+}
+
+// ---------------------------------------------------------------------------
+// near pair: Alg. 1 with an explicit stack.  The root [0,1] is known to be
 // inside its ellipse and not on the boundary.  Points are kept relative to
-// the query.  `stk` is this lane's slot 0 in LDS (slot stride kWave).
+// the query; `stk` is this lane's slot 0 in LDS (slot stride kWave).
+//
+// Each step halves the current interval and tests both halves: a half that
+// passes is a leaf (its chord's crossing is taken at once), a half that fails
+// becomes the current interval, the right one deferred when both fail.  The
+// tested nodes, splits and leaves are exactly Alg. 1's.
 //
 // The pair's angle is the sum of the leaves' chord angles.  It is returned
 // as an integer N: angle = (chord angle of the segment, given to the
-// accumulator by the caller through chord_factor) + 2 pi N, where
+// accumulator by the caller through chord_factor or a chain) + 2 pi N, where
 // N = sum over leaves of ray_cross - ray_cross(chord).  This is exact: the
 // leaves' chords followed by the reversed segment chord form a closed
 // polygon that avoids the query, whose angle sum is 2 pi times its crossings.
@@ -227,77 +248,90 @@ __device__ __forceinline__ void bez_eval(const Coef& c, double t, double& X, dou
 // ---------------------------------------------------------------------------
 __device__ int near_pair(int& N, const Coef& c, double B, double eta, double pnx, double pny, double qx, double qy,
                          double ax, double ay, double ra, double bx, double by, double rb, double eps2,
-                         double2* stk, bool& onb) {
+                         double4* stk, bool& onb) {
     int n = -ray_cross(ax, ay, bx, by);
-    double a = 0.0;  // left end of the current node, exact dyadic
-    int k = 0;       // level: node = [a, a + 2^-k]
+    double a = 0.0;  // current interval [a, a + 2^-k], exact dyadic
+    int k = 0;
     uint64_t pend = 0, stored = 0;
     int maxk = 0;
-    bool inside = true;
     for (;;) {
-        if (inside) {
-            if (k >= kDepthCap) {
-                onb = true;  // cannot happen for a validated eps (depth bound <= cap)
-                return maxk;
-            }
-            const int k1 = k + 1;
-            const int slot = k1 & (kStackSlots - 1);
-            stk[slot * kWave] = make_double2(bx, by);
-            if (k1 >= kStackSlots) stored &= ~(1ull << (k1 - kStackSlots));
-            stored |= 1ull << k1;
-            pend |= 1ull << k1;
-            double mx, my;
-            bez_eval(c, a + ldexp(1.0, -k1), mx, my);
-            mx -= qx;
-            my -= qy;
-            const double rm = mx * mx + my * my;
-            if (rm < eps2) {
-                onb = true;
-                return k1;
+        if (k >= kDepthCap) {
+            onb = true;  // cannot happen for a validated eps (depth bound <= cap)
+            return maxk;
+        }
+        const int k1 = k + 1;
+        const double tm = a + ldexp(1.0, -k1);
+        double mx, my;
+        bez_eval(c, tm, mx, my);
+        mx -= qx;
+        my -= qy;
+        const double rm = mx * mx + my * my;
+        if (rm < eps2) {
+            onb = true;
+            return k1;
+        }
+        maxk = k1 > maxk ? k1 : maxk;
+        const double hb = half_axis2(B, eta, k1);
+        const bool lfar = outside_ellipse(ra, rm, hb);
+        const bool rfar = outside_ellipse(rm, rb, hb);
+        if (lfar) n += ray_cross(ax, ay, mx, my);
+        if (rfar) n += ray_cross(mx, my, bx, by);
+        if (!lfar) {  // continue left; defer the right half when it failed too
+            if (!rfar) {
+                stk[(k1 & (kNearSlots - 1)) * kWave] = make_double4(mx, my, bx, by);
+                stored = (stored & ~slot_evict_mask(k1)) | (1ull << k1);
+                pend |= 1ull << k1;
             }
             bx = mx;
             by = my;
             rb = rm;
             k = k1;
-            maxk = k1 > maxk ? k1 : maxk;
-        } else {
-            n += ray_cross(ax, ay, bx, by);
+        } else if (!rfar) {  // continue right
+            a = tm;
+            ax = mx;
+            ay = my;
+            ra = rm;
+            k = k1;
+        } else {  // both halves are leaves: resume the deepest deferred interval
             if (pend == 0) {
                 N += n;
                 return maxk;
             }
             const int kk = 63 - __clzll(pend);
-            pend &= ~(1ull << kk);
-            a += ldexp(1.0, -k);
-            ax = bx;
-            ay = by;
-            ra = rb;
-            if (stored & (1ull << kk)) {
-                const double2 p = stk[(kk & (kStackSlots - 1)) * kWave];
-                bx = p.x;
-                by = p.y;
-            } else {
-                const double t = a + ldexp(1.0, -kk);
-                if (t == 1.0) {
+            const uint64_t kbit = 1ull << kk;
+            pend &= ~kbit;
+            a = deferred_left(a, kk);
+            if (stored & kbit) {
+                const double4 p = stk[(kk & (kNearSlots - 1)) * kWave];
+                ax = p.x;
+                ay = p.y;
+                bx = p.z;
+                by = p.w;
+            } else {  // evicted: evaluate both ends again (same parameters, same values)
+                bez_eval(c, a, ax, ay);
+                ax -= qx;
+                ay -= qy;
+                const double te = a + ldexp(1.0, -kk);
+                if (te == 1.0) {
                     bx = pnx;
                     by = pny;
                 } else {
-                    bez_eval(c, t, bx, by);
+                    bez_eval(c, te, bx, by);
                 }
                 bx -= qx;
                 by -= qy;
             }
-            stored &= ~(1ull << kk);
+            stored &= ~kbit;
+            ra = ax * ax + ay * ay;
             rb = bx * bx + by * by;
             k = kk;
         }
-        inside = !outside_ellipse(ra, rb, half_axis2(B, eta, k));
     }
 }
 
 // Near pair with all segment data read from global memory (integer part only).
 __device__ __forceinline__ int near_from_global(int& N, const Segs& sg, uint32_t s, double qx, double qy,
-                                                double eps2, double2* stk, bool& onb) {
+                                                double eps2, double4* stk, bool& onb) {
     const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
     const double pnx = sg.pnx[s], pny = sg.pny[s];
     const double bx = pnx - qx, by = pny - qy;

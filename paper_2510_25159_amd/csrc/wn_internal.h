@@ -12,7 +12,7 @@ constexpr int kCoef = kMaxDeg + 1;  // coefficient slots per segment
 constexpr int kWave = 64;
 constexpr int kWG = 256;            // threads per workgroup of the pair kernels
 constexpr int kWavesPerWG = kWG / kWave;
-constexpr int kStackSlots = 8;      // LDS ring slots per lane for pending right end points
+constexpr int kNearSlots = 4;       // LDS ring slots per lane for deferred intervals (two end points each)
 constexpr int kDepthCap = 52;       // dyadic parameters a + 2^-k stay exact in FP64
 constexpr int kSegChunk = kWG;      // segments staged in LDS per chunk
 constexpr int kNearBuf = 256;       // per-wave LDS buffer of near pairs before one queue append

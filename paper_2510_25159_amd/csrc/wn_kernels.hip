@@ -14,22 +14,25 @@
 //    (uniform-address LDS reads broadcast to the wave).  The ellipse test is
 //    evaluated without square roots:  d1 + d2 > Bk  <=>  R < 0 or r1 r2 > R^2
 //    with R = Bk^2/2 - (r1 + r2)/2, ri = di^2.
-//  * Angle sums: instead of one atan2 per pair, each lane keeps the product
-//    z = prod (dot + i cross) of its chords and an integer K of completed
-//    turns; a chord with angle theta multiplies z and K changes by the sign
-//    rule below, so that sum(theta) = arg(z) + 2 pi K.  One atan2 per query.
-//    Sign rule (s = sign bit of the imaginary part): both factors in the same
-//    closed half plane and the product in the other one => the angle crossed
-//    +-pi: K += s(product) - s(z).  Mixed half planes never cross +-pi.  The
-//    decision uses the stored rounded values, so arg(z) + 2 pi K stays
-//    consistent through rounding (only |sum| error ~ 1 ulp per factor).
-//  * Near pairs: Alg. 1 on an explicit stack.  Nodes are dyadic [a, a + 2^-k];
-//    pending right end points are kept in an LDS ring of kStackSlots slots
-//    per lane; a pending point whose slot was reused is re-evaluated (same
-//    parameter, same code => the same value).
-//  * Curve points: O(n) Bernstein evaluation (Horner in t with powers of
-//    1 - t over pre-scaled coefficients C(n,i) w_i P_i; one reciprocal for
-//    rational segments).
+//  * Angle sums without an atan2 per pair.  For a closed polygon that avoids
+//    x, the principal angles of its edges sum to 2 pi times its signed
+//    crossings with the ray {x + (s, 0): s > 0}.  A chain of segments that
+//    join bit for bit therefore sums to the angle from its start to its end
+//    plus 2 pi (crossings of its chords and of the closing edge): a far pair
+//    costs one crossing test, and a closed loop contributes an exact integer.
+//    The few remaining angle factors (chain closures, periodic copies) go to
+//    a complex accumulator z = prod (dot + i cross) with an integer K of
+//    completed turns, sum(theta) = arg(z) + 2 pi K (sign rule on the
+//    imaginary parts, see turn_mul): one atan2 per query.
+//  * Near pairs: Alg. 1 with an explicit stack; each step halves the current
+//    interval and tests both halves, so a pair costs one step per split
+//    node.  The result is an integer correction N to the segment chord's
+//    angle (leaves' crossings minus the chord's), added only when N != 0.
+//    Deferred intervals sit in an LDS ring of kNearSlots slots per lane; one
+//    whose slot was reused is evaluated again (same parameters => the same
+//    values).
+//  * Curve points: one Horner pass in u = t / (1 - t) over zero-padded
+//    coefficient slots (no degree-dependent branch), then one reciprocal.
 #include "wn_device.h"
 
 namespace wn {
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
     __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
     __shared__ uint8_t s_join[kSegChunk];
     __shared__ float s_bef[MIXED ? kSegChunk : 1];  // FP32 upper bound of the root ellipse's axis
-    __shared__ double2 s_stack[INLINE ? kWavesPerWG * kStackSlots * kWave : 1];
+    __shared__ double4 s_stack[INLINE ? kWavesPerWG * kNearSlots * kWave : 1];
     __shared__ double s_ang[kWavesPerWG][kWave];
     __shared__ int s_flag[kWavesPerWG][kWave];
     __shared__ uint2 s_nbuf[INLINE ? 1 : kWavesPerWG][INLINE ? 1 : kNearBuf];
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
     const int gq = wave / GS, gs = wave % GS;
-    double2* stk = INLINE ? s_stack + wave * kStackSlots * kWave + lane : s_stack;
+    double4* stk = INLINE ? s_stack + wave * kNearSlots * kWave + lane : s_stack;
     const int total = single_face >= 0 ? (int)gridDim.x : item_offs[ft.num_faces];
 
     for (int iter = 0;; ++iter) {
@@ -378,10 +381,6 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
 // chunk (wave-local counter, no global atomics).  One node of Alg. 1 per
 // loop trip, so lanes with short and long recursions interleave.
 // ---------------------------------------------------------------------------
-// Pending intervals of the near pass: LDS ring of kNearSlots slots per lane,
-// each holding the two end points of a deferred interval (32 B).
-constexpr int kNearSlots = 4;
-static_assert(kNearSlots == 4, "the eviction mask assumes four slots (levels of one residue mod 4)");
 
 // Near-pair state.  The current interval [a, a + 2^-k] is always one that
 // failed its ellipse test (the root is queued for exactly that reason).
@@ -469,8 +468,7 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     const bool none = go & lfar & rfar;    // resume the deepest deferred interval
     const uint64_t k1bit = 1ull << k1;
     if (both) stk[(k1 & (kNearSlots - 1)) * kWave] = make_double4(mx, my, st.bx, st.by);
-    // the slot's previous occupant, at any level of the same residue, is evicted
-    const uint64_t evict = 0x1111111111111111ull << (k1 & (kNearSlots - 1));
+    const uint64_t evict = slot_evict_mask(k1);
     st.stored = both ? ((st.stored & ~evict) | k1bit) : st.stored;
     st.pend = both ? (st.pend | k1bit) : st.pend;
     st.pmax = (go & (k1 > st.pmax)) ? k1 : st.pmax;
@@ -617,10 +615,10 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
 // Queries that lost a near pair to a full queue: recompute the whole query
 // in line (one lane per query).  Runs after k_finalize and overwrites.
 __global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, Out out, double eps2) {
-    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
-    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    double4* stk = s_stack + wave * kNearSlots * kWave + lane;
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (i >= pts.n || i >= pts.offs[ft.num_faces] || out.lab[i] != kRedo) return;
     // face of point i: last f with offs[f] <= i

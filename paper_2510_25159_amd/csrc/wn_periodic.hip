@@ -147,7 +147,7 @@ struct PerLane {
 // Append buffered near pairs (with their copy translation); pairs that do
 // not fit in the queue are recursed here by the lane owning the query.
 __device__ void flush_near_per(const uint2* buf, const double2* sbuf, int nfill, const NearQueue& nq, int lane,
-                               PerLane& P, const Segs& sg, double eps2, double2* stk) {
+                               PerLane& P, const Segs& sg, double eps2, double4* stk) {
     if (nfill == 0) return;
     __builtin_amdgcn_wave_barrier();
     unsigned long long base = 0;
@@ -176,7 +176,7 @@ __device__ void flush_near_per(const uint2* buf, const double2* sbuf, int nfill,
 // lanes with act == false contribute nothing.
 __device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double shx, double shy, bool act,
                                           PerLane& P, uint2* buf, double2* sbuf, const NearQueue& nq, int lane,
-                                          double eps2, double2* stk) {
+                                          double eps2, double4* stk) {
     const double xq = P.qx - shx, yq = P.qy - shy;
     for (int s = L.s0; s < L.s1; ++s) {
         const double ax = sg.p0x[s] - xq, ay = sg.p0y[s] - yq;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double
 // Extended curve of loop L (Sec. 4.4) seen from the query translated by -(sx, sy).
 __device__ __forceinline__ void extended(const Segs& sg, const PLoop& L, double sx, double sy, bool act,
                                          PerLane& P, uint2* buf, double2* sbuf, const NearQueue& nq, int lane,
-                                         double eps2, double2* stk) {
+                                         double eps2, double4* stk) {
     const double xs = P.qx - sx, ys = P.qy - sy;
     const double xi = L.dx * (xs - L.b0x) + L.dy * (ys - L.b0y);
     const bool a = act && P.valid;
@@ -235,14 +235,14 @@ __device__ __forceinline__ void extended(const Segs& sg, const PLoop& L, double 
 __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
                                                       const int2* item_map, uint32_t* item_counter, NearQueue nq,
                                                       Out out, double eps2, PerTab pt) {
-    __shared__ double2 s_stack[kWavesPerWG * kStackSlots * kWave];
+    __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
     __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
     __shared__ double2 s_nsh[kWavesPerWG][kNearBuf];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
-    double2* stk = s_stack + wave * kStackSlots * kWave + lane;
+    double4* stk = s_stack + wave * kNearSlots * kWave + lane;
     const int total = item_offs[ft.num_faces];
     for (int iter = 0;; ++iter) {
         int item;
