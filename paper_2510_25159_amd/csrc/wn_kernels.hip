@@ -453,8 +453,10 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     const double hb = half_axis2(st.B, st.eta, k1);
     const bool lfar = outside_ellipse(st.ra, rm, hb);
     const bool rfar = outside_ellipse(rm, st.rb, hb);
-    const int xl = ray_cross(st.ax, st.ay, mx, my);
-    const int xr = ray_cross(mx, my, st.bx, st.by);
+    // = ray_cross(a, m) and ray_cross(m, b); exact ties are resolved only when some lane has one
+    const bool m_low = my <= 0.0;
+    const int xl = ray_cross_n(st.ay <= 0.0, m_low, cross_neg_wave(st.ax, st.ay, mx, my));
+    const int xr = ray_cross_n(m_low, st.by <= 0.0, cross_neg_wave(mx, my, st.bx, st.by));
     st.n += go ? ((lfar ? xl : 0) + (rfar ? xr : 0)) : 0;
     if (COUNT && go) {
         ++nc.split;
