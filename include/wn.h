@@ -181,6 +181,8 @@ enum {
     WN_STAT_NEAR_FLOPS = 4,   /* algorithmic FP64 flops of the near pass (cost model:
                                  split 6n+15, leaf 11; n = segment degree)                */
     WN_STAT_MAX_DEPTH = 5,    /* deepest level reached (max, not sum)                    */
+    WN_STAT_NEAR_STEPS = 6,   /* near pass: loop trips summed over its waves             */
+    WN_STAT_NEAR_LANE_STEPS = 7, /* near pass: lanes holding a pair, summed over trips    */
     WN_STATS_COUNT = 8
 };
 

@@ -392,6 +392,7 @@ struct NodeState {
     int k;
     int n;         // far children's ray crossings minus the segment chord's (see near_pair)
     int pmax;      // deepest level of this pair
+    int mode;      // 0: split; 1, 2: evaluate the left, right end of a resumed evicted interval
     uint32_t seg;  // segment (its end point is reloaded when an evicted interval ends at t = 1)
 };
 
@@ -417,11 +418,13 @@ __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_
     st.k = 0;
     st.pend = st.stored = 0;
     st.pmax = 0;
+    st.mode = 0;
 }
 
 struct NodeCount {
     uint32_t split = 0, leaf = 0, reeval = 0, maxk = 0;
     uint64_t flops = 0;
+    uint32_t trips = 0, busy = 0;  // loop trips of the wave (lane 0), trips holding a pair (every lane)
 };
 
 // One split of Alg. 1: the current interval is halved at its midpoint and
@@ -437,14 +440,35 @@ struct NodeCount {
 template <bool COUNT>
 __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* stk, bool& onb, NodeCount& nc,
                                           const Segs& sg, double qx, double qy, bool has) {
-    const bool capped = has & (st.k >= kDepthCap);  // cannot happen for a validated eps
-    const bool sp = has & !capped;
+    // The one curve evaluation of the step: the midpoint for a split, or an
+    // end point of a resumed interval whose slot was reused (such a lane
+    // spends two steps re-evaluating them, instead of making the whole wave
+    // run two extra evaluations).
+    const bool m0 = has & (st.mode == 0);
+    const bool capped = m0 & (st.k >= kDepthCap);  // cannot happen for a validated eps
+    const bool sp = m0 & !capped;
+    const bool fl = has & (st.mode == 1), fr = has & (st.mode == 2);
     const int k1 = st.k + 1;
-    const double h = ldexp(1.0, -k1);
-    const double tm = st.a + h;
+    const double tm = st.a + ldexp(1.0, -k1);
+    const double te = sp ? tm : (fl ? st.a : st.a + ldexp(1.0, -st.k));
+    const bool at_end = fr & (te == 1.0);
     double mx = 0.0, my = 0.0;
-    if (sp) bez_eval(st.c, tm, mx, my);
+    if (sp | fl | (fr & !at_end)) bez_eval(st.c, te, mx, my);
+    if (at_end) {
+        mx = sg.pnx[st.seg] - qx;
+        my = sg.pny[st.seg] - qy;
+    }
     const double rm = fma(mx, mx, my * my);
+    if (COUNT) nc.reeval += (fl | fr) ? 1 : 0;
+    // resumed interval: install the re-evaluated end point
+    st.ax = fl ? mx : st.ax;
+    st.ay = fl ? my : st.ay;
+    st.ra = fl ? rm : st.ra;
+    st.bx = fr ? mx : st.bx;
+    st.by = fr ? my : st.by;
+    st.rb = fr ? rm : st.rb;
+    st.mode = fl ? 2 : (fr ? 0 : st.mode);
+    // split
     const bool hit = sp & (rm < eps2);
     onb |= capped | hit;
     bool fin = capped | hit;
@@ -488,31 +512,19 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     const int kk = 63 - __clzll(st.pend | 1ull);
     const uint64_t kbit = 1ull << kk;
     const bool kept = (st.stored & kbit) != 0;
-    // deferred interval [a', a' + 2^-kk]: a' = (a rounded down to 2^-(kk-1)) + 2^-kk
-    const double ap = ldexp(floor(ldexp(st.a, kk - 1)), 1 - kk) + ldexp(1.0, -kk);
     double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
     if (pop & kept) p = stk[(kk & (kNearSlots - 1)) * kWave];
-    if (pop & !kept) {  // slot reused by a deeper interval: evaluate both ends again
-        bez_eval(st.c, ap, p.x, p.y);
-        const double te = ap + ldexp(1.0, -kk);
-        if (te == 1.0) {
-            p.z = sg.pnx[st.seg] - qx;
-            p.w = sg.pny[st.seg] - qy;
-        } else {
-            bez_eval(st.c, te, p.z, p.w);
-        }
-        if (COUNT) nc.reeval += 2;
-    }
     st.pend = pop ? (st.pend & ~kbit) : st.pend;
     st.stored = pop ? (st.stored & ~kbit) : st.stored;
-    st.a = pop ? ap : st.a;
+    st.a = pop ? deferred_left(st.a, kk) : st.a;
     st.k = pop ? kk : st.k;
-    st.ax = pop ? p.x : st.ax;
-    st.ay = pop ? p.y : st.ay;
-    st.ra = pop ? fma(p.x, p.x, p.y * p.y) : st.ra;
-    st.bx = pop ? p.z : st.bx;
-    st.by = pop ? p.w : st.by;
-    st.rb = pop ? fma(p.z, p.z, p.w * p.w) : st.rb;
+    st.mode = (pop & !kept) ? 1 : st.mode;  // end points to evaluate again in the next two steps
+    st.ax = (pop & kept) ? p.x : st.ax;
+    st.ay = (pop & kept) ? p.y : st.ay;
+    st.ra = (pop & kept) ? fma(p.x, p.x, p.y * p.y) : st.ra;
+    st.bx = (pop & kept) ? p.z : st.bx;
+    st.by = (pop & kept) ? p.w : st.by;
+    st.rb = (pop & kept) ? fma(p.z, p.z, p.w * p.w) : st.rb;
     return fin;
 }
 
@@ -588,6 +600,10 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
             if (next >= c_end) break;
             continue;
         }
+        if (COUNT) {
+            nc.trips += lane == 0 ? 1u : 0u;
+            nc.busy += has ? 1u : 0u;
+        }
         if (node_step<COUNT>(st, eps2, stk, onb, nc, sg, qx, qy, has)) {
             // the pair's angle is its chord angle (already in the far pass's
             // sum) plus 2 pi n; most pairs have n = 0 and write nothing
@@ -603,7 +619,11 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
         const unsigned long long re = wave_sum((unsigned long long)nc.reeval);
         const unsigned long long fl = wave_sum((unsigned long long)nc.flops);
         const uint32_t mk = wave_max(nc.maxk);
+        const unsigned long long tr = wave_sum((unsigned long long)nc.trips);
+        const unsigned long long bu = wave_sum((unsigned long long)nc.busy);
         if (lane == 0) {
+            atomicAdd(&stats.c[6], tr);
+            atomicAdd(&stats.c[7], bu);
             if (gw == 0) atomicAdd(&stats.c[0], n);
             atomicAdd(&stats.c[1], sp);
             atomicAdd(&stats.c[2], lf);

@@ -36,7 +36,8 @@ KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO, KERNEL_FAR_
 KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo", 5: "k_far_periodic",
                 6: "k_bin"}
 KERNEL_KINDS = 8
-STAT_NAMES = ["near_pairs", "splits", "leaves", "reevals", "near_flops", "max_depth"]
+STAT_NAMES = ["near_pairs", "splits", "leaves", "reevals", "near_flops", "max_depth", "near_steps",
+              "near_lane_steps"]
 STATS_COUNT = 8
 
 _P = ctypes.c_void_p
