@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--faces", type=int, default=2000, help="faces of the batched set (default: the full set)")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--mixed-steps", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=6000000, help="points of the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=15000000, help="points of the oracle sample (about 15 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--qpw", type=int, default=0)
