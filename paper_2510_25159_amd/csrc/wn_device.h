@@ -10,6 +10,19 @@ namespace wn {
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr uint8_t kRedo = 4;  // label placeholder: query must be recomputed in line
 
+// Element i of a read-only table at a wave-uniform index: read through the
+// constant address space, so that the compiler uses a scalar load into SGPRs
+// instead of broadcasting the value into VGPRs.  Only for data that no kernel
+// of the same launch writes.  (The host pass only parses device code.)
+template <class T>
+__device__ __forceinline__ T kload(const T* p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) T*)p)[i];
+#else
+    return p[i];
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // angle accumulator
 // ---------------------------------------------------------------------------

@@ -267,7 +267,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->bpc_far[m][1] = far_blocks_per_cu(false, m == 1, 128);
         h->bpc_far[m][2] = far_blocks_per_cu(false, m == 1, 256);
     }
-    h->bpc_far_per = far_periodic_blocks_per_cu();
+    h->bpc_far_per = far_periodic_blocks_per_cu(kPerQueue);
+    h->bpc_redo_per = far_periodic_blocks_per_cu(kPerRedo);
     h->bpc_near = near_blocks_per_cu();
 
     // faces ordered by segment count (largest first) for the work queues
@@ -617,7 +618,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
                                        st);
                 zero_near = false;
                 if (e == hipSuccess)
-                    e = launch_far_periodic(h->sg, one, pts, sc.item_offs, sc.item_map, nullptr, (nf + 255) / 256,
+                    e = launch_far_periodic(kPerInline, h->sg, one, pts, sc.item_offs, sc.item_map, nullptr,
+                                            (nf + 255) / 256,
                                             sc.nq, sc.out, h->eps2, h->pt, st);
                 if (e == hipSuccess) e = launch_finalize(pts, sc.out, ho[f], ho[f + 1], -1, st);
             }
@@ -646,6 +648,15 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
         nq.shift = sc.sh2;
     }
     if (e == hipSuccess) e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st);
+    if (e == hipSuccess && h->num_periodic > 0) {
+        // periodic queries that lost a near pair: recomputed in line over the
+        // periodic item table (still the last one built), before finalize
+        ProfScope ps(q.profile, WN_KERNEL_REDO, st);
+        const bool persistent = q.queue_policy != 2;
+        const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_redo_per : sc.max_items;
+        e = launch_far_periodic(kPerRedo, h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
+                                persistent ? sc.counters + 1 : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, st);
+    }
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_FINALIZE, st);
         e = launch_finalize(pts, sc.out, 0, N, F, st);
@@ -751,7 +762,7 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
         if (e == hipSuccess) {
             const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_far_per : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR_PERIODIC, st);
-            e = launch_far_periodic(h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
+            e = launch_far_periodic(kPerQueue, h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
                                     persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, st);
         }
     }

@@ -145,8 +145,11 @@ hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out
 int far_blocks_per_cu(bool inline_near, bool mixed, int qpw);
 int near_blocks_per_cu();
 hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);
-hipError_t launch_far_periodic(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
-                               const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
-                               double eps2, PerTab pt, hipStream_t st);
-int far_periodic_blocks_per_cu();
+// Periodic far pass variants: near pairs queued (overflow -> label kRedo),
+// recursed in line, or recursed in line for the kRedo-labelled queries only.
+enum : int { kPerQueue = 0, kPerInline = 1, kPerRedo = 2 };
+hipError_t launch_far_periodic(int mode, const Segs& sg, const FaceTab& ft, const Points& pts,
+                               const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
+                               NearQueue nq, Out out, double eps2, PerTab pt, hipStream_t st);
+int far_periodic_blocks_per_cu(int mode);
 }  // namespace wn

@@ -69,8 +69,9 @@ __global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, in
     const int F = ft.num_faces;
     const int chunk = (F + 1023) / 1024;
     const int r0 = min(F, tid * chunk), r1 = min(F, r0 + chunk);
-    // [0] item counter, [2..3] near-queue count (64-bit, reset by the first build of a query only)
-    if (tid == 0) counters[0] = 0;
+    // [0] far item counter, [1] periodic redo item counter, [2..3] near-queue
+    // count (64-bit, reset by the first build of a query only)
+    if (tid < 2) counters[tid] = 0;
     if (zero_near && (tid == 2 || tid == 3)) counters[tid] = 0;
     auto tiles_of = [&](int r) -> int64_t {
         const int f = ft.order[r];
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
             __syncthreads();
             if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
             __syncthreads();
-            item = s_item;
+            item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: face data via scalar loads
         } else {
             if (iter > 0) break;
             item = blockIdx.x;

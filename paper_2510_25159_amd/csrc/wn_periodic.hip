@@ -137,79 +137,86 @@ __device__ __forceinline__ long wave_max_l(long v) {
 struct PerLane {
     double qx, qy;
     int64_t qi;
-    bool valid, onb;
+    bool valid, onb, lost;
     Turn T;
     int xc;  // integer part of near pairs recursed in line (2 pi units)
     int nfill;
     int cnt;
 };
 
-// Append buffered near pairs (with their copy translation); pairs that do
-// not fit in the queue are recursed here by the lane owning the query.
-__device__ void flush_near_per(const uint2* buf, const double2* sbuf, int nfill, const NearQueue& nq, int lane,
-                               PerLane& P, const Segs& sg, double eps2, double4* stk) {
+// Per-wave resources: near-pair staging buffers (queue variant) or the
+// recursion stack (in-line variants).
+struct PerWave {
+    uint2* buf;
+    double2* sbuf;
+    NearQueue nq;
+    double4* stk;
+    double eps2;
+    int lane;
+};
+
+// Append the wave's buffered near pairs (with their copy translation) to the
+// queue with one atomic; lanes whose query lost a pair set P.lost.
+__device__ void flush_near_per(const PerWave& W, PerLane& P) {
+    const int nfill = P.nfill;
+    P.nfill = 0;
     if (nfill == 0) return;
     __builtin_amdgcn_wave_barrier();
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(nq.count, (unsigned long long)nfill);
+    if (W.lane == 0) base = atomicAdd(W.nq.count, (unsigned long long)nfill);
     base = __shfl(base, 0);
-    for (int e = lane; e < nfill; e += kWave) {
-        if (base + (unsigned long long)e < nq.cap) {
-            nq.qs[base + e] = buf[e];
-            nq.shift[base + e] = sbuf[e];
+    for (int e = W.lane; e < nfill; e += kWave) {
+        if (base + (unsigned long long)e < W.nq.cap) {
+            W.nq.qs[base + e] = W.buf[e];
+            W.nq.shift[base + e] = W.sbuf[e];
         }
     }
-    if (base + (unsigned long long)nfill > nq.cap) {
-        for (int e = 0; e < nfill; ++e) {
-            if (base + (unsigned long long)e < nq.cap) continue;
-            const uint2 ent = buf[e];
-            if ((int64_t)ent.x == P.qi && !P.onb) {
-                const double2 sh = sbuf[e];
-                (void)near_from_global(P.xc, sg, ent.y, P.qx - sh.x, P.qy - sh.y, eps2, stk, P.onb);
-            }
-        }
+    if (base + (unsigned long long)nfill > W.nq.cap) {
+        for (int e = 0; e < nfill; ++e)
+            if (base + (unsigned long long)e >= W.nq.cap && (int64_t)W.buf[e].x == P.qi) P.lost = true;
     }
     __builtin_amdgcn_wave_barrier();
 }
 
 // All segments of loop L seen from the query translated by -(shx, shy);
 // lanes with act == false contribute nothing.
+template <int MODE>
 __device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double shx, double shy, bool act,
-                                          PerLane& P, uint2* buf, double2* sbuf, const NearQueue& nq, int lane,
-                                          double eps2, double4* stk) {
+                                          PerLane& P, const PerWave& W) {
     const double xq = P.qx - shx, yq = P.qy - shy;
     for (int s = L.s0; s < L.s1; ++s) {
-        const double ax = sg.p0x[s] - xq, ay = sg.p0y[s] - yq;
-        const double bx = sg.pnx[s] - xq, by = sg.pny[s] - yq;
+        const double ax = kload(sg.p0x, s) - xq, ay = kload(sg.p0y, s) - yq;
+        const double bx = kload(sg.pnx, s) - xq, by = kload(sg.pny, s) - yq;
         const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
         const bool work = act && P.valid && !P.onb;
-        if (work && (ra < eps2 || rb < eps2)) P.onb = true;
-        const bool far = outside_ellipse(ra, rb, sg.hb2[s]);
+        if (work && (ra < W.eps2 || rb < W.eps2)) P.onb = true;
+        const bool far = outside_ellipse(ra, rb, kload(sg.hb2, s));
         if (work && far) turn_mul(P.T, ax * bx + ay * by, ax * by - ay * bx);
         const bool need = work && !P.onb && !far;
         if (need) chord_factor(P.T, ax, ay, bx, by);  // the near pass adds the integer rest
-        const uint64_t m = __ballot(need);
-        if (m) {
-            const int cntm = __popcll(m);
-            if (P.nfill + cntm > kNearBuf) {
-                flush_near_per(buf, sbuf, P.nfill, nq, lane, P, sg, eps2, stk);
-                P.nfill = 0;
+        if constexpr (MODE == kPerQueue) {
+            const uint64_t m = __ballot(need);
+            if (m) {
+                const int cntm = __popcll(m);
+                if (P.nfill + cntm > kNearBuf) flush_near_per(W, P);
+                const int rank = __popcll(m & ((1ull << W.lane) - 1ull));
+                if (need) {
+                    W.buf[P.nfill + rank] = make_uint2((uint32_t)P.qi, (uint32_t)s);
+                    W.sbuf[P.nfill + rank] = make_double2(shx, shy);
+                }
+                P.nfill += cntm;
             }
-            const int rank = __popcll(m & ((1ull << lane) - 1ull));
-            if (need) {
-                buf[P.nfill + rank] = make_uint2((uint32_t)P.qi, (uint32_t)s);
-                sbuf[P.nfill + rank] = make_double2(shx, shy);
-            }
-            P.nfill += cntm;
+        } else {
+            if (need) (void)near_from_global(P.xc, sg, (uint32_t)s, xq, yq, W.eps2, W.stk, P.onb);
         }
         if ((++P.cnt & 3) == 0) turn_norm(P.T);
     }
 }
 
 // Extended curve of loop L (Sec. 4.4) seen from the query translated by -(sx, sy).
+template <int MODE>
 __device__ __forceinline__ void extended(const Segs& sg, const PLoop& L, double sx, double sy, bool act,
-                                         PerLane& P, uint2* buf, double2* sbuf, const NearQueue& nq, int lane,
-                                         double eps2, double4* stk) {
+                                         PerLane& P, const PerWave& W) {
     const double xs = P.qx - sx, ys = P.qy - sy;
     const double xi = L.dx * (xs - L.b0x) + L.dy * (ys - L.b0y);
     const bool a = act && P.valid;
@@ -219,7 +226,7 @@ __device__ __forceinline__ void extended(const Segs& sg, const PLoop& L, double 
     const long Khi = wave_max_l(a ? khi : LONG_MIN);
     for (long k = Klo; k <= Khi; ++k) {
         const bool in = a && k >= klo && k <= khi;
-        loop_copy(sg, L, sx + (double)k * L.vx, sy + (double)k * L.vy, in, P, buf, sbuf, nq, lane, eps2, stk);
+        loop_copy<MODE>(sg, L, sx + (double)k * L.vx, sy + (double)k * L.vy, in, P, W);
     }
     if (a) {
         const double ax = L.b0x + (double)klo * L.vx - xs, ay = L.b0y + (double)klo * L.vy - ys;
@@ -232,38 +239,72 @@ __device__ __forceinline__ void extended(const Segs& sg, const PLoop& L, double 
     }
 }
 
+// Shared memory of one variant: staging buffers or recursion stacks.
+template <int MODE>
+struct PerShared;
+template <>
+struct PerShared<kPerQueue> {
+    uint2 nbuf[kWavesPerWG][kNearBuf];
+    double2 nsh[kWavesPerWG][kNearBuf];
+    int item;
+};
+template <>
+struct PerShared<kPerInline> {
+    double4 stack[kWavesPerWG * kNearSlots * kWave];
+    int item;
+};
+template <>
+struct PerShared<kPerRedo> : PerShared<kPerInline> {};
+
+// Output (all variants): the far-field angle sum (radians, integer near
+// parts included for the in-line variants) and label 0 / 2 (boundary) /
+// 3 (invalid) / kRedo; k_finalize turns them into winding numbers.
+template <int MODE>
 __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
                                                       const int2* item_map, uint32_t* item_counter, NearQueue nq,
                                                       Out out, double eps2, PerTab pt) {
-    __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
-    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
-    __shared__ double2 s_nsh[kWavesPerWG][kNearBuf];
-    __shared__ int s_item;
+    __shared__ PerShared<MODE> sh;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
-    double4* stk = s_stack + wave * kNearSlots * kWave + lane;
-    const int total = item_offs[ft.num_faces];
+    PerWave W;
+    if constexpr (MODE == kPerQueue) {
+        W.buf = sh.nbuf[wave];
+        W.sbuf = sh.nsh[wave];
+        W.stk = nullptr;
+    } else {
+        W.buf = nullptr;
+        W.sbuf = nullptr;
+        W.stk = sh.stack + wave * kNearSlots * kWave + lane;
+    }
+    W.nq = nq;
+    W.eps2 = eps2;
+    W.lane = lane;
+    const int total = kload(item_offs, ft.num_faces);
     for (int iter = 0;; ++iter) {
         int item;
         if (item_counter) {
             __syncthreads();
-            if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
+            if (tid == 0) sh.item = (int)atomicAdd(item_counter, 1u);
             __syncthreads();
-            item = s_item;
+            item = __builtin_amdgcn_readfirstlane(sh.item);  // uniform: face data via scalar loads
         } else {
             if (iter > 0) break;
             item = blockIdx.x;
         }
         if (item >= total) break;
-        const int2 mp = item_map[item];
+        const int2 mp = kload(item_map, item);
         const int f = mp.x, tile = mp.y;
-        int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+        int64_t qb = kload(pts.offs, f), qe = kload(pts.offs, f + 1);
         qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
         qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
         PerLane P;
         P.qi = qb + (int64_t)tile * (kWave * kWavesPerWG) + wave * kWave + lane;
-        const bool active = P.qi < qe;
+        bool active = P.qi < qe;
+        if constexpr (MODE == kPerRedo) {
+            active = active && out.lab[P.qi] == kRedo;
+            if (!__any(active)) continue;  // no __syncthreads below: waves may skip independently
+        }
         P.qx = P.qy = 0.0;
         if (active) {
             P.qx = pts.u[P.qi * pts.stride];
@@ -272,17 +313,18 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
         P.valid = active && fabs(P.qx) < kCoordLimit && fabs(P.qy) < kCoordLimit;
         if (!P.valid) P.qx = P.qy = 0.0;
         P.onb = false;
+        P.lost = false;
         P.T = Turn{1.0, 0.0, 0};
         P.xc = 0;
         P.nfill = 0;
         P.cnt = 0;
-        const PFace pf = pt.face[f];
+        const PFace pf = kload(pt.face, f);
         for (int u = pf.u0; u < pf.u1; ++u) {
-            const PUnit U = pt.unit[u];
+            const PUnit U = kload(pt.unit, u);
             if (U.kind == kUnitExtended) {
-                extended(sg, pt.loop[U.la], 0.0, 0.0, true, P, s_nbuf[wave], s_nsh[wave], nq, lane, eps2, stk);
+                extended<MODE>(sg, kload(pt.loop, U.la), 0.0, 0.0, true, P, W);
             } else if (U.kind == kUnitContractible) {
-                const PLoop L = pt.loop[U.la];
+                const PLoop L = kload(pt.loop, U.la);
                 const long ilo = (long)ceil((P.qx - L.bb[1]) / pf.Tu) - 1;
                 const long ihi = (long)floor((P.qx - L.bb[0]) / pf.Tu) + 1;
                 long jlo = 0, jhi = 0;
@@ -295,11 +337,10 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
                 for (long i = Ilo; i <= Ihi; ++i)
                     for (long j = Jlo; j <= Jhi; ++j) {
                         const bool in = P.valid && i >= ilo && i <= ihi && j >= jlo && j <= jhi;
-                        loop_copy(sg, L, (double)i * pf.Tu, (double)j * pf.Tv, in, P, s_nbuf[wave], s_nsh[wave], nq,
-                                  lane, eps2, stk);
+                        loop_copy<MODE>(sg, L, (double)i * pf.Tu, (double)j * pf.Tv, in, P, W);
                     }
             } else {
-                const PLoop La = pt.loop[U.la];
+                const PLoop La = kload(pt.loop, U.la);
                 const double eta = pf.nx * (P.qx - La.b0x) + pf.ny * (P.qy - La.b0y);
                 const long mlo = (long)floor((eta - U.eta_hi) / pf.Delta) - 1;
                 const long mhi = (long)ceil((eta - U.eta_lo) / pf.Delta) + 1;
@@ -307,32 +348,53 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
                 for (long m = Mlo; m <= Mhi; ++m) {
                     const bool in = P.valid && m >= mlo && m <= mhi;
                     const double tx = (double)m * pf.t1x, ty = (double)m * pf.t1y;
-                    extended(sg, La, tx, ty, in, P, s_nbuf[wave], s_nsh[wave], nq, lane, eps2, stk);
-                    extended(sg, pt.loop[U.lb], tx + U.pshx, ty + U.pshy, in, P, s_nbuf[wave], s_nsh[wave], nq, lane,
-                             eps2, stk);
+                    extended<MODE>(sg, La, tx, ty, in, P, W);
+                    extended<MODE>(sg, kload(pt.loop, U.lb), tx + U.pshx, ty + U.pshy, in, P, W);
                 }
             }
         }
-        flush_near_per(s_nbuf[wave], s_nsh[wave], P.nfill, nq, lane, P, sg, eps2, stk);
+        if constexpr (MODE == kPerQueue) flush_near_per(W, P);
         if (active) {
             out.w[P.qi] = turn_angle(P.T) + kTwoPi * (double)P.xc;
-            out.lab[P.qi] = !P.valid ? 3 : (P.onb ? 2 : 0);
+            out.lab[P.qi] = !P.valid ? 3 : (P.onb ? 2 : (P.lost ? kRedo : 0));
         }
     }
 }
 
-hipError_t launch_far_periodic(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
-                               const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
-                               double eps2, PerTab pt, hipStream_t st) {
+template <int MODE>
+static hipError_t launch_per(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+                             const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
+                             double eps2, PerTab pt, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_far_periodic, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+    hipLaunchKernelGGL(k_far_periodic<MODE>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
                        item_counter, nq, out, eps2, pt);
     return hipGetLastError();
 }
 
-int far_periodic_blocks_per_cu() {
+hipError_t launch_far_periodic(int mode, const Segs& sg, const FaceTab& ft, const Points& pts,
+                               const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
+                               NearQueue nq, Out out, double eps2, PerTab pt, hipStream_t st) {
+    switch (mode) {
+        case kPerQueue:
+            return launch_per<kPerQueue>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, st);
+        case kPerInline:
+            return launch_per<kPerInline>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, st);
+        case kPerRedo:
+            return launch_per<kPerRedo>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, st);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+int far_periodic_blocks_per_cu(int mode) {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far_periodic, kWG, 0);
+    hipError_t e = hipErrorInvalidValue;
+    if (mode == kPerQueue)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far_periodic<kPerQueue>, kWG, 0);
+    else if (mode == kPerInline)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far_periodic<kPerInline>, kWG, 0);
+    else if (mode == kPerRedo)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far_periodic<kPerRedo>, kWG, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

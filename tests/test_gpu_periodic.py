@@ -38,6 +38,18 @@ def test_config3_subset_parity(torch_cuda, c3_small, schedule):
     assert st["compared"] > 0.99 * q.num_points
 
 
+@pytest.mark.parametrize("policy", [1, 2])
+def test_periodic_queue_overflow_recomputed(torch_cuda, c3_small, policy):
+    """A near queue far too small: periodic queries that lose a pair are
+    recomputed in line after the near pass (persistent and one-block-per-item
+    launches)."""
+    f, q, w_o, n_o = c3_small
+    print(f"config3[0:32] near_capacity=1000 policy={policy}", flush=True)
+    w, lab = run_wn(f, q, schedule=1, near_capacity=1000, queue_policy=policy)
+    st = compare(w, lab, w_o, n_o)
+    assert st["compared"] > 0.99 * q.num_points
+
+
 def test_closed_noise_free_bands(torch_cuda, oracle_lib):
     f, q = W.config3(face_ids=range(40, 56), sigma=0.0, open_frac=0.0)
     w_o, n_o = oracle_lib.query_faces(f, q)
@@ -78,6 +90,8 @@ def test_mixed_planar_and_periodic_faces(torch_cuda, oracle_lib):
     for sched in (0, 1):
         w, lab = run_wn(faces, q, schedule=sched)
         compare(w, lab, w_o, n_o)
+    w, lab = run_wn(faces, q, schedule=1, near_capacity=300)  # both redo kernels
+    compare(w, lab, w_o, n_o)
 
 
 def test_topology_error_reported(torch_cuda):
