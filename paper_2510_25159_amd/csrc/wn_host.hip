@@ -663,7 +663,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     }
     if (e == hipSuccess && h->num_planar > 0) {
         ProfScope ps(q.profile, WN_KERNEL_REDO, st);
-        e = launch_redo(h->sg, FaceTab{h->ft_plan.seg_begin, nullptr, F}, pts, sc.out, h->eps2, st);
+        e = launch_redo(h->sg, FaceTab{h->ft_plan.seg_begin, nullptr, F}, pts, sc.out, h->eps2, sc.nq,
+                        (int64_t)h->cu_count * 8, st);
     }
     if (!preset) scratch_free(sc, st);
     return hip_status(e);

@@ -141,7 +141,8 @@ hipError_t launch_far(bool inline_near, bool mixed, int qpw, const Segs& sg, con
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
                        Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st);
 hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, int32_t nf, hipStream_t st);
-hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st);
+hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2,
+                       const NearQueue& nq, int64_t max_grid, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, bool mixed, int qpw);
 int near_blocks_per_cu();
 hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);

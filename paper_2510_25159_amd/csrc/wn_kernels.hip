@@ -635,15 +635,8 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
     }
 }
 
-// Queries that lost a near pair to a full queue: recompute the whole query
-// in line (one lane per query).  Runs after k_finalize and overwrites.
-__global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, Out out, double eps2) {
-    __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x >> 6;
-    double4* stk = s_stack + wave * kNearSlots * kWave + lane;
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (i >= pts.n || i >= pts.offs[ft.num_faces] || out.lab[i] != kRedo) return;
+__device__ __forceinline__ void redo_query(const Segs& sg, const FaceTab& ft, const Points& pts, const Out& out,
+                                           double eps2, double4* stk, int64_t i) {
     // face of point i: last f with offs[f] <= i
     int lo = 0, hi = ft.num_faces - 1;
     while (lo < hi) {
@@ -682,6 +675,21 @@ __global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, O
     }
 }
 
+
+// Queries that lost a near pair to a full queue: recompute the whole query
+// in line (one lane per query).  Runs after k_finalize and overwrites.  A
+// queue that never overflowed lost nothing: then the kernel returns at once.
+__global__ __launch_bounds__(kWG) void k_redo(Segs sg, FaceTab ft, Points pts, Out out, double eps2,
+                                              const unsigned long long* near_count, uint64_t near_cap) {
+    __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
+    if (*near_count <= near_cap) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    double4* stk = s_stack + wave * kNearSlots * kWave + lane;
+    const int64_t n = min(pts.n, pts.offs[ft.num_faces]);
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        if (out.lab[i] == kRedo) redo_query(sg, ft, pts, out, eps2, stk, i);
+}
 // Points are [q0, q1), further bounded by offs[nf] when nf >= 0 (the live
 // point count of a replayed graph).
 __global__ __launch_bounds__(kWG) void k_finalize(Points pts, Out out, int64_t q0, int64_t q1, int32_t nf) {
@@ -773,10 +781,11 @@ hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, i
     return hipGetLastError();
 }
 
-hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2, hipStream_t st) {
+hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2,
+                       const NearQueue& nq, int64_t max_grid, hipStream_t st) {
     if (pts.n <= 0) return hipSuccess;
-    const int64_t g = (pts.n + kWG - 1) / kWG;
-    hipLaunchKernelGGL(k_redo, dim3((unsigned)g), dim3(kWG), 0, st, sg, ft, pts, out, eps2);
+    const int64_t g = std::min<int64_t>((pts.n + kWG - 1) / kWG, std::max<int64_t>(1, max_grid));
+    hipLaunchKernelGGL(k_redo, dim3((unsigned)g), dim3(kWG), 0, st, sg, ft, pts, out, eps2, nq.count, nq.cap);
     return hipGetLastError();
 }
 

@@ -139,9 +139,9 @@ struct PerLane {
     int64_t qi;
     bool valid, onb, lost;
     Turn T;
-    int xc;  // integer part of near pairs recursed in line (2 pi units)
-    int nfill;
-    int cnt;
+    int xc;     // integer parts of near pairs recursed in line (2 pi units)
+    int nfill;  // entries in the wave's near-pair buffer (wave-uniform)
+    int cnt;    // pairs since the start (wave-uniform)
 };
 
 // Per-wave resources: near-pair staging buffers (queue variant) or the
@@ -179,7 +179,10 @@ __device__ void flush_near_per(const PerWave& W, PerLane& P) {
 }
 
 // All segments of loop L seen from the query translated by -(shx, shy);
-// lanes with act == false contribute nothing.
+// lanes with act == false contribute nothing.  Each pair multiplies in its
+// chord angle (periodic loops typically have open joints, so chains of
+// bit-joined segments as in the planar pass would be one segment long); a
+// near pair's integer rest comes from the near pass.
 template <int MODE>
 __device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double shx, double shy, bool act,
                                           PerLane& P, const PerWave& W) {
@@ -264,6 +267,7 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
                                                       const int2* item_map, uint32_t* item_counter, NearQueue nq,
                                                       Out out, double eps2, PerTab pt) {
     __shared__ PerShared<MODE> sh;
+    if (MODE == kPerRedo && *nq.count <= nq.cap) return;  // the queue never overflowed: nothing was lost
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
