@@ -93,9 +93,13 @@ __device__ __forceinline__ double turn_angle(const Turn& t) { return arg_of(t.zr
 // ---------------------------------------------------------------------------
 // ellipse test (Lemma 1 / sub-segment bound), square-root free
 // ---------------------------------------------------------------------------
+// Outside <=> R < 0 or ra rb > R^2 with R = hb2 - (ra + rb) / 2.  Both in one
+// comparison: for R < 0 the right side R |R| = -R^2 is <= 0 <= ra rb, so the
+// test holds unless ra rb = R^2 = 0 (the query on an end point, which the
+// eps test reports as on-boundary first).
 __device__ __forceinline__ bool outside_ellipse(double ra, double rb, double hb2) {
     const double R = fma(-0.5, ra + rb, hb2);
-    return (R < 0.0) | (ra * rb > R * R);  // no short circuit: no branch
+    return ra * rb > R * fabs(R);
 }
 
 __device__ __forceinline__ double half_axis2(double B, double eta, int k) {
@@ -148,6 +152,41 @@ __device__ __forceinline__ int ray_cross_n(bool a_low, bool b_low, bool neg) {
 
 __device__ __forceinline__ int ray_cross(double ax, double ay, double bx, double by) {
     return ray_cross_n(ay <= 0.0, by <= 0.0, cross_neg(ax, ay, bx, by));
+}
+
+// Wave forms for uniform control flow, on lane masks (LLVM predicate codes
+// of __builtin_amdgcn_fcmp: the comparison's lane mask, written directly).
+constexpr int kCmpOEQ = 1, kCmpOLT = 4, kCmpOLE = 5, kCmpULE = 13;
+
+__device__ __forceinline__ uint64_t low_mask(double y) { return __builtin_amdgcn_fcmp(y, 0.0, kCmpOLE); }
+
+// Lanes of m below this lane (this lane's rank among them).
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// N += ray_cross(a, b) with a_lo / b_lo the masks of a_y <= 0 / b_y <= 0.
+// Only lanes whose edge changes side of the ray's line can cross; when no
+// lane does, no orientation is computed.
+__device__ __forceinline__ void ray_cross_mask(int& N, uint64_t a_lo, uint64_t b_lo, double ax, double ay, double bx,
+                                               double by) {
+    const uint64_t sm = a_lo ^ b_lo;
+    if (sm) {
+        const double o = cross_raw(ax, ay, bx, by);
+        uint64_t nm = __builtin_amdgcn_fcmp(o, 0.0, kCmpOLT);
+        const uint64_t zm = __builtin_amdgcn_fcmp(o, 0.0, kCmpOEQ) & sm;
+        if (zm) nm |= __builtin_amdgcn_ballot_w64(cross_tie_neg(ax, ay, bx, by)) & zm;
+        const uint64_t up = sm & a_lo & ~nm, dn = sm & ~a_lo & nm;
+        const int cu = __builtin_amdgcn_inverse_ballot_w64(up) ? 1 : 0;
+        const int cd = __builtin_amdgcn_inverse_ballot_w64(dn) ? 1 : 0;
+        N += cu - cd;
+    }
+}
+
+// Lanes where !outside_ellipse(ra, rb, hb2).
+__device__ __forceinline__ uint64_t near_mask(double ra, double rb, double hb2) {
+    const double R = fma(-0.5, ra + rb, hb2);
+    return __builtin_amdgcn_fcmp(ra * rb, R * fabs(R), kCmpULE);
 }
 
 // Angle factor (a . b, a x b) of the edge a -> b for the accumulator, with

@@ -194,6 +194,8 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
         bool pb_low = false;                     // pby <= 0 (below or on the ray's line)
         float pdf = 0.f;                         // |pb| in FP32 (precision MIXED)
         bool open = false;                       // wave-uniform
+        const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+        double rmin = INFINITY;                  // smallest |b|^2 of the two-segment path
         for (int c0 = s0; c0 < s1; c0 += kSegChunk) {
             __syncthreads();
             const int sj = c0 + tid;
@@ -234,40 +236,43 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                     if constexpr (!INLINE && !MIXED) {
                         // two segments per trip: their arithmetic is independent apart
                         // from the shared end point, which gives each wave two chains
-                        // of dependent instructions to interleave
-                        auto append = [&](bool need, int j) {
-                            const uint64_t m = __builtin_amdgcn_ballot_w64(need);
+                        // of dependent instructions to interleave.  Flags live as lane
+                        // masks (SGPRs): a comparison writes its mask directly, and a
+                        // pair's orientation is only computed when some lane's chord
+                        // changes side of the ray's line.  End points closer than eps
+                        // are collected in rmin and reported after the face.
+                        auto append = [&](uint64_t m, int j) {
                             if (m) {
                                 const int cntm = __popcll(m);
                                 if (nfill + cntm > kNearBuf) {
                                     lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
                                     nfill = 0;
                                 }
-                                const int rank = __popcll(m & ((1ull << lane) - 1ull));
-                                if (need) s_nbuf[wave][nfill + rank] = make_uint2((uint32_t)qi, (uint32_t)(c0 + j));
+                                if (__builtin_amdgcn_inverse_ballot_w64(m))
+                                    s_nbuf[wave][nfill + lanes_below(m)] = make_uint2((uint32_t)qi, (uint32_t)(c0 + j));
                                 nfill += cntm;
                             }
                         };
+                        uint64_t am = __builtin_amdgcn_ballot_w64(pb_low);
                         for (; jj + 1 < re; jj += 2) {
                             const int j = j0 + jj;
                             const double bx0 = s_pnx[j] - qx, by0 = s_pny[j] - qy;
                             const double bx1 = s_pnx[j + 1] - qx, by1 = s_pny[j + 1] - qy;
                             const double rb0 = bx0 * bx0 + by0 * by0, rb1 = bx1 * bx1 + by1 * by1;
-                            onb |= valid & ((rb0 < eps2) | (rb1 < eps2));
-                            const bool b0_low = by0 <= 0.0, b1_low = by1 <= 0.0;
-                            xc += ray_cross_n(pb_low, b0_low, cross_neg_wave(pbx, pby, bx0, by0)) +
-                                  ray_cross_n(b0_low, b1_low, cross_neg_wave(bx0, by0, bx1, by1));
-                            const bool near0 = !outside_ellipse(prb, rb0, s_hb2[j]);
-                            const bool near1 = !outside_ellipse(rb0, rb1, s_hb2[j + 1]);
-                            // (an eps hit at j + 1 also drops pair j: the query is on the boundary)
-                            const bool live = valid & !onb;
+                            rmin = fmin(rmin, fmin(rb0, rb1));
+                            const uint64_t b0m = low_mask(by0), b1m = low_mask(by1);
+                            ray_cross_mask(xc, am, b0m, pbx, pby, bx0, by0);
+                            ray_cross_mask(xc, b0m, b1m, bx0, by0, bx1, by1);
+                            const uint64_t n0 = near_mask(prb, rb0, s_hb2[j]) & vm;
+                            const uint64_t n1 = near_mask(rb0, rb1, s_hb2[j + 1]) & vm;
                             pbx = bx1;
                             pby = by1;
                             prb = rb1;
-                            pb_low = b1_low;
-                            append(live & near0, j);
-                            append(live & near1, j + 1);
+                            am = b1m;
+                            append(n0, j);
+                            append(n1, j + 1);
                         }
+                        pb_low = __builtin_amdgcn_inverse_ballot_w64(am);
                     }
                     for (; jj < re; ++jj) {
                         const int j = j0 + jj;
@@ -336,6 +341,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
             }
         }
         if (open) close_chain(T, xc, csx, csy, pbx, pby);
+        onb |= valid & (rmin < eps2);
         if constexpr (!INLINE) lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
         // combine the GS partial sums of each query group
         double ang = turn_angle(T) + kTwoPi * (double)xc;
@@ -371,6 +377,176 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
             } else {
                 out.w[qi] = ang;
                 out.lab[qi] = !valid ? 3 : (onb ? 2 : (lost ? kRedo : 0));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Far-field kernel of the queued FP64 schedules with two queries per lane:
+// each wave evaluates 128 queries, so one LDS read of a segment feeds two
+// pairs and every lane carries two independent dependency chains.  Same
+// arithmetic and outputs as k_far<false, GQ, false>; flags live as lane
+// masks (SGPRs) and the orientation of a pair is only computed when some
+// lane's chord changes side of the ray's line.
+// ---------------------------------------------------------------------------
+constexpr int kQPL = 2;                                   // queries per lane
+constexpr int kQPWG2 = kWave * kQPL * kWavesPerWG;        // queries per work item (512)
+
+// flush_near for two queries per lane: lost[q] |= 1 when a pair of query
+// qi[q] did not fit in the queue.
+__device__ __forceinline__ void flush_near2(const uint2* buf, int nfill, const NearQueue& nq, int lane,
+                                            const int64_t (&qi)[kQPL], int (&lost)[kQPL]) {
+    if (nfill == 0) return;
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(nq.count, (unsigned long long)nfill);
+    base = __shfl(base, 0);
+    for (int e = lane; e < nfill; e += kWave)
+        if (base + (unsigned long long)e < nq.cap) nq.qs[base + e] = buf[e];
+    if (base + (unsigned long long)nfill > nq.cap) {
+        for (int e = 0; e < nfill; ++e) {
+            if (base + (unsigned long long)e < nq.cap) continue;
+            const int64_t x = (int64_t)buf[e].x;
+#pragma unroll
+            for (int q = 0; q < kQPL; ++q) lost[q] |= x == qi[q] ? 1 : 0;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k_far2(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
+                                              const int2* item_map, uint32_t* item_counter, NearQueue nq, Out out,
+                                              double eps2) {
+    __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
+    __shared__ uint8_t s_join[kSegChunk];
+    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    const int total = item_offs[ft.num_faces];
+    for (int iter = 0;; ++iter) {
+        int item;
+        if (item_counter) {
+            __syncthreads();
+            if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(s_item);
+        } else {
+            if (iter > 0) break;
+            item = blockIdx.x;
+        }
+        if (item >= total) break;
+        const int2 mp = item_map[item];
+        const int f = mp.x, tile = mp.y;
+        int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+        qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
+        qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+        int64_t qi[kQPL];
+        bool active[kQPL], valid[kQPL];
+        double qx[kQPL], qy[kQPL];
+        Turn T[kQPL];
+        int xc[kQPL], lost[kQPL];
+        uint64_t vm[kQPL], em[kQPL], am[kQPL];  // valid lanes, eps hits, chain end below the ray's line
+        double csx[kQPL], csy[kQPL], pbx[kQPL], pby[kQPL], prb[kQPL];
+#pragma unroll
+        for (int q = 0; q < kQPL; ++q) {
+            qi[q] = qb + (int64_t)tile * kQPWG2 + (wave * kQPL + q) * kWave + lane;
+            active[q] = qi[q] < qe;
+            qx[q] = qy[q] = 0.0;
+            if (active[q]) {
+                qx[q] = pts.u[qi[q] * pts.stride];
+                qy[q] = pts.v[qi[q] * pts.stride];
+            }
+            valid[q] = active[q] && fabs(qx[q]) < kCoordLimit && fabs(qy[q]) < kCoordLimit;
+            if (!valid[q]) qx[q] = qy[q] = 0.0;
+            vm[q] = __builtin_amdgcn_ballot_w64(valid[q]);
+            T[q] = Turn{1.0, 0.0, 0};
+            xc[q] = lost[q] = 0;
+            em[q] = am[q] = 0;
+            csx[q] = csy[q] = pbx[q] = pby[q] = prb[q] = 0.0;
+        }
+        const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
+        int nfill = 0;      // entries in this wave's near-pair buffer (wave-uniform)
+        bool open = false;  // a chain is open (wave-uniform)
+        for (int c0 = s0; c0 < s1; c0 += kSegChunk) {
+            __syncthreads();
+            const int sj = c0 + tid;
+            if (sj < s1) {
+                s_p0x[tid] = sg.p0x[sj];
+                s_p0y[tid] = sg.p0y[sj];
+                s_pnx[tid] = sg.pnx[sj];
+                s_pny[tid] = sg.pny[sj];
+                s_hb2[tid] = sg.hb2[sj];
+                s_join[tid] = sg.join[sj];
+            }
+            __syncthreads();
+            const int cn = min(kSegChunk, s1 - c0);
+            for (int j0 = 0; j0 < cn; j0 += kWave) {
+                const int jn = __builtin_amdgcn_readfirstlane(min(kWave, cn - j0));
+                const uint64_t jm = __ballot(lane < jn && s_join[j0 + lane] != 0);
+                int jj = 0;
+                while (jj < jn) {
+                    if (!(open & ((jm >> jj) & 1ull))) {  // a chain starts at segment j0 + jj
+#pragma unroll
+                        for (int q = 0; q < kQPL; ++q) {
+                            if (open) close_chain(T[q], xc[q], csx[q], csy[q], pbx[q], pby[q]);
+                            pbx[q] = s_p0x[j0 + jj] - qx[q];
+                            pby[q] = s_p0y[j0 + jj] - qy[q];
+                            prb[q] = pbx[q] * pbx[q] + pby[q] * pby[q];
+                            em[q] |= __builtin_amdgcn_fcmp(prb[q], eps2, kCmpOLT);
+                            am[q] = low_mask(pby[q]);
+                            csx[q] = pbx[q];
+                            csy[q] = pby[q];
+                        }
+                        open = true;
+                    }
+                    // the run jj .. re - 1 continues the chain without a break
+                    const uint64_t brk = jj + 1 < 64 ? ~(jm >> (jj + 1)) : ~0ull;
+                    const int re = min(jn, jj + 1 + (int)__builtin_ctzll(brk | (1ull << 63)));
+                    for (; jj < re; ++jj) {
+                        const int j = j0 + jj;
+                        const double px = s_pnx[j], py = s_pny[j], hb = s_hb2[j];
+                        uint64_t nm[kQPL];
+#pragma unroll
+                        for (int q = 0; q < kQPL; ++q) {
+                            const double bx = px - qx[q], by = py - qy[q];
+                            const double rb = bx * bx + by * by;
+                            em[q] |= __builtin_amdgcn_fcmp(rb, eps2, kCmpOLT);
+                            const uint64_t bm = low_mask(by);
+                            ray_cross_mask(xc[q], am[q], bm, pbx[q], pby[q], bx, by);
+                            nm[q] = near_mask(prb[q], rb, hb) & vm[q];
+                            pbx[q] = bx;
+                            pby[q] = by;
+                            prb[q] = rb;
+                            am[q] = bm;
+                        }
+                        if ((nm[0] | nm[1]) != 0ull) {
+                            const int n0 = __popcll(nm[0]), n1 = __popcll(nm[1]);
+                            if (nfill + n0 + n1 > kNearBuf) {
+                                flush_near2(s_nbuf[wave], nfill, nq, lane, qi, lost);
+                                nfill = 0;
+                            }
+                            const uint32_t seg = (uint32_t)(c0 + j);
+                            if (__builtin_amdgcn_inverse_ballot_w64(nm[0]))
+                                s_nbuf[wave][nfill + lanes_below(nm[0])] = make_uint2((uint32_t)qi[0], seg);
+                            if (__builtin_amdgcn_inverse_ballot_w64(nm[1]))
+                                s_nbuf[wave][nfill + n0 + lanes_below(nm[1])] = make_uint2((uint32_t)qi[1], seg);
+                            nfill += n0 + n1;
+                        }
+                    }
+                }
+            }
+        }
+        flush_near2(s_nbuf[wave], nfill, nq, lane, qi, lost);
+#pragma unroll
+        for (int q = 0; q < kQPL; ++q) {
+            if (open) close_chain(T[q], xc[q], csx[q], csy[q], pbx[q], pby[q]);
+            const bool onb = valid[q] & __builtin_amdgcn_inverse_ballot_w64(em[q]);
+            if (active[q]) {
+                out.w[qi[q]] = turn_angle(T[q]) + kTwoPi * (double)xc[q];
+                out.lab[qi[q]] = !valid[q] ? 3 : (onb ? 2 : (lost[q] ? kRedo : 0));
             }
         }
     }
@@ -800,6 +976,21 @@ static hipError_t far_occupancy(int* nb, int qpw) {
     return qpw == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_far<INLINE, 1, MIXED>, kWG, 0)
            : qpw == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_far<INLINE, 2, MIXED>, kWG, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_far<INLINE, 4, MIXED>, kWG, 0);
+}
+
+hipError_t launch_far2(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+                       const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out, double eps2,
+                       hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_far2, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map, item_counter,
+                       nq, out, eps2);
+    return hipGetLastError();
+}
+
+int far2_blocks_per_cu() {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far2, kWG, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 int far_blocks_per_cu(bool inline_near, bool mixed, int qpw) {

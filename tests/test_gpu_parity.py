@@ -43,7 +43,7 @@ def c2_small(oracle_lib):
 
 
 @pytest.mark.parametrize("schedule", [0, 1])
-@pytest.mark.parametrize("qpw", [64, 256])
+@pytest.mark.parametrize("qpw", [64, 256, 512])
 def test_config1_parity(torch_cuda, c1, schedule, qpw):
     f, q, w_o, n_o = c1
     print(f"config1 schedule={schedule} qpw={qpw}", flush=True)
@@ -52,11 +52,11 @@ def test_config1_parity(torch_cuda, c1, schedule, qpw):
     assert st["compared"] > 65000
 
 
-@pytest.mark.parametrize("schedule,policy", [(0, 0), (1, 1), (1, 2)])
-def test_config2_subset_parity(torch_cuda, c2_small, schedule, policy):
+@pytest.mark.parametrize("schedule,policy,qpw", [(0, 0, 0), (1, 1, 0), (1, 2, 0), (1, 1, 512), (1, 2, 512)])
+def test_config2_subset_parity(torch_cuda, c2_small, schedule, policy, qpw):
     f, q, w_o, n_o = c2_small
-    print(f"config2[0:24] schedule={schedule} policy={policy} points={q.num_points}", flush=True)
-    w, lab = run_wn(f, q, schedule=schedule, queue_policy=policy)
+    print(f"config2[0:24] schedule={schedule} policy={policy} qpw={qpw} points={q.num_points}", flush=True)
+    w, lab = run_wn(f, q, schedule=schedule, queue_policy=policy, queries_per_wg=qpw)
     st = compare(w, lab, w_o, n_o)
     assert st["compared"] > 0.99 * q.num_points
 
@@ -79,9 +79,10 @@ def test_mixed_precision(torch_cuda, c2_small, schedule, qpw):
     assert np.array_equal(np.isfinite(w32), ok) and np.array_equal(w32[ok], w64[ok])
 
 
-def test_near_queue_overflow_falls_back_in_line(torch_cuda, c2_small):
+@pytest.mark.parametrize("qpw", [256, 512])
+def test_near_queue_overflow_falls_back_in_line(torch_cuda, c2_small, qpw):
     f, q, w_o, n_o = c2_small
-    w, lab = run_wn(f, q, schedule=1, near_capacity=1000)
+    w, lab = run_wn(f, q, schedule=1, near_capacity=1000, queries_per_wg=qpw)
     compare(w, lab, w_o, n_o)
 
 
@@ -104,16 +105,16 @@ def test_edge_cases(torch_cuda, oracle_lib):
            rng.uniform(-1.5, 1.5, (257, 2)), np.array([[0.25, 0.5]])]
     q = W.queries_for_faces(pts)
     w_o, n_o = oracle_lib.query_faces(faces, q)
-    for sched in (0, 1):
-        w, lab = run_wn(faces, q, schedule=sched)
+    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
+        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw)
         compare(w, lab, w_o, n_o)
         assert np.all(w[5:8] == 0.0)  # face without loops
     # vertices and invalid points on the square face
     special = np.array([[1.0, 1.0], [-1.0, 1.0], [np.nan, 0.0], [np.inf, 1.0], [2e15, 0.0], [0.0, 0.0]])
     q2 = W.queries_for_faces([special])
     f2 = W.faces_from_loops([[sq]])
-    for sched in (0, 1):
-        w, lab = run_wn(f2, q2, schedule=sched)
+    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
+        w, lab = run_wn(f2, q2, schedule=sched, queries_per_wg=qpw)
         assert list(lab) == [2, 2, 3, 3, 3, 1]
         assert np.all(np.isnan(w[:5])) and abs(w[5] - 1.0) < 1e-15
 
@@ -148,8 +149,8 @@ def test_near_boundary_points(torch_cuda, oracle_lib):
         P.append(p + 10.0 ** rng.uniform(-11, -3) * rng.choice([-1, 1]) * nrm)
     q = W.queries_for_faces([np.array(P)])
     w_o, n_o = oracle_lib.query_faces(faces, q)
-    for sched in (0, 1):
-        w, lab = run_wn(faces, q, schedule=sched)
+    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
+        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw)
         st = compare(w, lab, w_o, n_o)
         assert st["compared"] > 1500
 
@@ -213,7 +214,7 @@ def test_queries_on_chords_and_ray_ties(torch_cuda, oracle_lib):
     q = W.queries_for_faces(pts)
     w_o, n_o = oracle_lib.query_faces(faces, q)
     assert np.all(n_o == 0)  # every query is well away from the curves
-    for sched in (0, 1):
-        w, lab = run_wn(faces, q, schedule=sched)
+    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
+        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw)
         st = compare(w, lab, w_o, n_o)
         assert st["compared"] == q.num_points
