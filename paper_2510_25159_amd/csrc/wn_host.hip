@@ -267,7 +267,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->bpc_far[m][1] = far_blocks_per_cu(false, m == 1, 128);
         h->bpc_far[m][2] = far_blocks_per_cu(false, m == 1, 256);
     }
-    h->bpc_far2 = far2_blocks_per_cu();
+    h->bpc_farq[0] = farq_blocks_per_cu(2);
+    h->bpc_farq[1] = farq_blocks_per_cu(4);
     h->bpc_far_per = far_periodic_blocks_per_cu(kPerQueue);
     h->bpc_redo_per = far_periodic_blocks_per_cu(kPerRedo);
     h->bpc_near = near_blocks_per_cu();
@@ -550,7 +551,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     const int rule = q.rule >= 0 ? q.rule : h->rule;
     if (sched > WN_SCHED_BINNED || prec > WN_PREC_MIXED || rule > WN_RULE_POSITIVE) return WN_E_INVALID;
     if (q.queries_per_wg != 0 && q.queries_per_wg != 64 && q.queries_per_wg != 128 && q.queries_per_wg != 256 &&
-        q.queries_per_wg != 512)
+        q.queries_per_wg != 512 && q.queries_per_wg != 1024)
         return WN_E_INVALID;
     if (q.queue_policy < 0 || q.queue_policy > 2 || q.near_capacity < 0) return WN_E_INVALID;
     if (q.depth_log && sched != WN_SCHED_PLAIN) return WN_E_UNSUPPORTED;
@@ -613,7 +614,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
             if (nf == 0) continue;
             ProfScope ps(q.profile, WN_KERNEL_FAR, st);
             if (h->h_dom[f] == WN_DOMAIN_PLANE) {
-                const int qg = qpw == 512 ? 256 : qpw;  // in-line recursion: one query per lane
+                const int qg = qpw > 256 ? 256 : qpw;  // in-line recursion: one query per lane
                 e = launch_far(true, prec == WN_PREC_MIXED, qg, h->sg, h->ft_plan, pts, nullptr, nullptr, nullptr, f,
                                (nf + qg - 1) / qg, NearQueue{}, pout, h->eps2, st);
             } else {
@@ -743,9 +744,10 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
     bool zero_near = true;
     const bool persistent = policy != 2;
     if (h->num_planar > 0) {
-        // 512: two queries per lane (FP64); the mixed-precision pass keeps one
-        const bool two = qpw == 512 && !mixed;
-        const int qg = qpw == 512 && mixed ? 256 : qpw;
+        // 512 / 1024: two / four queries per lane (FP64); the mixed-precision
+        // pass keeps one
+        const int qpl = mixed || qpw <= 256 ? 1 : qpw / 256;
+        const int qg = qpw > 256 && mixed ? 256 : qpw;
         {
             ProfScope ps(prof, WN_KERNEL_ITEMS, st);
             e = launch_build_items(h->ft_plan, pts, qg, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
@@ -754,12 +756,12 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
         }
         if (e == hipSuccess) {
             const int* bp = h->bpc_far[mixed ? 1 : 0];
-            const int bpc = two ? h->bpc_far2 : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
+            const int bpc = qpl > 1 ? h->bpc_farq[qpl / 4] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
             const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR, st);
-            if (two)
-                e = launch_far2(h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map, persistent ? sc.counters : nullptr,
-                                grid, sc.nq, sc.out, h->eps2, st);
+            if (qpl > 1)
+                e = launch_farq(qpl, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
+                                persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, st);
             else
                 e = launch_far(false, mixed, qg, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
                                persistent ? sc.counters : nullptr, -1, grid, sc.nq, sc.out, h->eps2, st);

@@ -144,11 +144,11 @@ hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, i
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2,
                        const NearQueue& nq, int64_t max_grid, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, bool mixed, int qpw);
-// Queued FP64 far pass with two queries per lane (items of 512 queries).
-hipError_t launch_far2(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+// Queued FP64 far pass with qpl (2 or 4) queries per lane (items of 256 qpl queries).
+hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                        const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out, double eps2,
                        hipStream_t st);
-int far2_blocks_per_cu();
+int farq_blocks_per_cu(int qpl);
 int near_blocks_per_cu();
 hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);
 // Periodic far pass variants: near pairs queued (overflow -> label kRedo),

@@ -383,20 +383,18 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
 }
 
 // ---------------------------------------------------------------------------
-// Far-field kernel of the queued FP64 schedules with two queries per lane:
-// each wave evaluates 128 queries, so one LDS read of a segment feeds two
-// pairs and every lane carries two independent dependency chains.  Same
+// Far-field kernel of the queued FP64 schedules with QPL queries per lane:
+// each wave evaluates 64 QPL queries, so one LDS read of a segment feeds QPL
+// pairs and every lane carries QPL independent dependency chains.  Same
 // arithmetic and outputs as k_far<false, GQ, false>; flags live as lane
 // masks (SGPRs) and the orientation of a pair is only computed when some
 // lane's chord changes side of the ray's line.
 // ---------------------------------------------------------------------------
-constexpr int kQPL = 2;                                   // queries per lane
-constexpr int kQPWG2 = kWave * kQPL * kWavesPerWG;        // queries per work item (512)
-
-// flush_near for two queries per lane: lost[q] |= 1 when a pair of query
+// flush_near for QPL queries per lane: lost[q] |= 1 when a pair of query
 // qi[q] did not fit in the queue.
-__device__ __forceinline__ void flush_near2(const uint2* buf, int nfill, const NearQueue& nq, int lane,
-                                            const int64_t (&qi)[kQPL], int (&lost)[kQPL]) {
+template <int QPL>
+__device__ __forceinline__ void flush_near_q(const uint2* buf, int nfill, const NearQueue& nq, int lane,
+                                             const int64_t (&qi)[QPL], int (&lost)[QPL]) {
     if (nfill == 0) return;
     __builtin_amdgcn_wave_barrier();
     unsigned long long base = 0;
@@ -409,15 +407,30 @@ __device__ __forceinline__ void flush_near2(const uint2* buf, int nfill, const N
             if (base + (unsigned long long)e < nq.cap) continue;
             const int64_t x = (int64_t)buf[e].x;
 #pragma unroll
-            for (int q = 0; q < kQPL; ++q) lost[q] |= x == qi[q] ? 1 : 0;
+            for (int q = 0; q < QPL; ++q) lost[q] |= x == qi[q] ? 1 : 0;
         }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k_far2(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
-                                              const int2* item_map, uint32_t* item_counter, NearQueue nq, Out out,
-                                              double eps2) {
+// occupancy target of k_farq: the register budget that keeps it
+template <int QPL>
+struct FarqWaves;
+template <>
+struct FarqWaves<2> {
+    static constexpr int w = 5;
+};
+template <>
+struct FarqWaves<4> {
+    static constexpr int w = 3;
+};
+
+template <int QPL>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<QPL>::w))) void k_farq(
+    Segs sg, FaceTab ft, Points pts, const int32_t* item_offs, const int2* item_map, uint32_t* item_counter,
+    NearQueue nq, Out out, double eps2) {
+    constexpr int kQPL = QPL;
+    constexpr int kQPWG2 = kWave * QPL * kWavesPerWG;  // queries per work item
     __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
     __shared__ uint8_t s_join[kSegChunk];
     __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
@@ -505,9 +518,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
                     // the run jj .. re - 1 continues the chain without a break
                     const uint64_t brk = jj + 1 < 64 ? ~(jm >> (jj + 1)) : ~0ull;
                     const int re = min(jn, jj + 1 + (int)__builtin_ctzll(brk | (1ull << 63)));
-                    for (; jj < re; ++jj) {
-                        const int j = j0 + jj;
-                        const double px = s_pnx[j], py = s_pny[j], hb = s_hb2[j];
+                    auto step = [&](int j, double px, double py, double hb) {
                         uint64_t nm[kQPL];
 #pragma unroll
                         for (int q = 0; q < kQPL; ++q) {
@@ -522,24 +533,39 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
                             prb[q] = rb;
                             am[q] = bm;
                         }
-                        if ((nm[0] | nm[1]) != 0ull) {
-                            const int n0 = __popcll(nm[0]), n1 = __popcll(nm[1]);
-                            if (nfill + n0 + n1 > kNearBuf) {
-                                flush_near2(s_nbuf[wave], nfill, nq, lane, qi, lost);
+                        uint64_t any = 0;
+#pragma unroll
+                        for (int q = 0; q < kQPL; ++q) any |= nm[q];
+                        if (any != 0ull) {
+                            int cnt = 0;
+#pragma unroll
+                            for (int q = 0; q < kQPL; ++q) cnt += __popcll(nm[q]);
+                            if (nfill + cnt > kNearBuf) {
+                                flush_near_q<kQPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
                                 nfill = 0;
                             }
                             const uint32_t seg = (uint32_t)(c0 + j);
-                            if (__builtin_amdgcn_inverse_ballot_w64(nm[0]))
-                                s_nbuf[wave][nfill + lanes_below(nm[0])] = make_uint2((uint32_t)qi[0], seg);
-                            if (__builtin_amdgcn_inverse_ballot_w64(nm[1]))
-                                s_nbuf[wave][nfill + n0 + lanes_below(nm[1])] = make_uint2((uint32_t)qi[1], seg);
-                            nfill += n0 + n1;
+#pragma unroll
+                            for (int q = 0; q < kQPL; ++q) {
+                                if (__builtin_amdgcn_inverse_ballot_w64(nm[q]))
+                                    s_nbuf[wave][nfill + lanes_below(nm[q])] = make_uint2((uint32_t)qi[q], seg);
+                                nfill += __popcll(nm[q]);
+                            }
                         }
+                    };
+                    for (; jj + 1 < re; jj += 2) {  // two segments per trip: no register copies between them
+                        const int j = j0 + jj;
+                        step(j, s_pnx[j], s_pny[j], s_hb2[j]);
+                        step(j + 1, s_pnx[j + 1], s_pny[j + 1], s_hb2[j + 1]);
+                    }
+                    if (jj < re) {
+                        const int j = j0 + jj++;
+                        step(j, s_pnx[j], s_pny[j], s_hb2[j]);
                     }
                 }
             }
         }
-        flush_near2(s_nbuf[wave], nfill, nq, lane, qi, lost);
+        flush_near_q<kQPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
 #pragma unroll
         for (int q = 0; q < kQPL; ++q) {
             if (open) close_chain(T[q], xc[q], csx[q], csy[q], pbx[q], pby[q]);
@@ -978,18 +1004,26 @@ static hipError_t far_occupancy(int* nb, int qpw) {
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_far<INLINE, 4, MIXED>, kWG, 0);
 }
 
-hipError_t launch_far2(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                        const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out, double eps2,
                        hipStream_t st) {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_far2, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map, item_counter,
-                       nq, out, eps2);
+    if (qpl == 2)
+        hipLaunchKernelGGL(k_farq<2>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+                           item_counter, nq, out, eps2);
+    else if (qpl == 4)
+        hipLaunchKernelGGL(k_farq<4>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+                           item_counter, nq, out, eps2);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-int far2_blocks_per_cu() {
+int farq_blocks_per_cu(int qpl) {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far2, kWG, 0);
+    hipError_t e = hipErrorInvalidValue;
+    if (qpl == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_farq<2>, kWG, 0);
+    if (qpl == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_farq<4>, kWG, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
