@@ -165,12 +165,12 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// N += ray_cross(a, b) with a_lo / b_lo the masks of a_y <= 0 / b_y <= 0.
-// Only lanes whose edge changes side of the ray's line can cross; when no
-// lane does, no orientation is computed.
+// N += ray_cross(a, b) for the lanes of `keep`, with a_lo / b_lo the masks
+// of a_y <= 0 / b_y <= 0.  Only lanes whose edge changes side of the ray's
+// line can cross; when no lane does, no orientation is computed.
 __device__ __forceinline__ void ray_cross_mask(int& N, uint64_t a_lo, uint64_t b_lo, double ax, double ay, double bx,
-                                               double by) {
-    const uint64_t sm = a_lo ^ b_lo;
+                                               double by, uint64_t keep = ~0ull) {
+    const uint64_t sm = (a_lo ^ b_lo) & keep;
     if (sm) {
         const double o = cross_raw(ax, ay, bx, by);
         uint64_t nm = __builtin_amdgcn_fcmp(o, 0.0, kCmpOLT);

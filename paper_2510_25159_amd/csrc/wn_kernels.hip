@@ -680,11 +680,15 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     const double hb = half_axis2(st.B, st.eta, k1);
     const bool lfar = outside_ellipse(st.ra, rm, hb);
     const bool rfar = outside_ellipse(rm, st.rb, hb);
-    // = ray_cross(a, m) and ray_cross(m, b); exact ties are resolved only when some lane has one
-    const bool m_low = my <= 0.0;
-    const int xl = ray_cross_n(st.ay <= 0.0, m_low, cross_neg_wave(st.ax, st.ay, mx, my));
-    const int xr = ray_cross_n(m_low, st.by <= 0.0, cross_neg_wave(mx, my, st.bx, st.by));
-    st.n += go ? ((lfar ? xl : 0) + (rfar ? xr : 0)) : 0;
+    // n += ray_cross(a, m) for a far left half, ray_cross(m, b) for a far right
+    // half, on lane masks: a half's orientation is only computed when some
+    // lane's half changes side of the ray's line
+    {
+        const uint64_t gm = __builtin_amdgcn_ballot_w64(go);
+        const uint64_t am = low_mask(st.ay), mm = low_mask(my), bm = low_mask(st.by);
+        ray_cross_mask(st.n, am, mm, st.ax, st.ay, mx, my, gm & __builtin_amdgcn_ballot_w64(lfar));
+        ray_cross_mask(st.n, mm, bm, mx, my, st.bx, st.by, gm & __builtin_amdgcn_ballot_w64(rfar));
+    }
     if (COUNT && go) {
         ++nc.split;
         nc.flops += 6 * st.c.n + 15 + 11 * ((lfar ? 1 : 0) + (rfar ? 1 : 0));
