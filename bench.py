@@ -119,6 +119,33 @@ def section_config1(args):
     return out
 
 
+def section_long_path(args):
+    """Path hierarchy on a long path: one star face of 16,384 cubic segments
+    (config 1's generator) and 2^20 uniform points, flat far pass against the
+    hierarchy (labels compared)."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    faces = W.config1_faces(nseg=16384)
+    q = W.config1_queries(n=1 << 20)
+    fs = wn.FaceSet(faces)
+    tens = _dev_queries(torch, q)
+    pairs = faces.num_segments * q.num_points
+    out = {"segments": faces.num_segments, "points": q.num_points, "pairs": pairs}
+    labs = {}
+    for name, tree in (("flat", 0), ("hierarchy", 1)):
+        ms, k = _time_query(torch, fs, tens, q.face_point_offsets, 5, schedule=1, path_hierarchy=tree)
+        w, lab = fs.query(*tens, q.face_point_offsets, schedule=1, path_hierarchy=tree)
+        labs[name] = lab.cpu().numpy()
+        out[name] = {"ms_per_step": ms, "queries_per_s": q.num_points / (ms / 1e3), "kernel_ms": k}
+    both = (labs["flat"] != 2) & (labs["hierarchy"] != 2)
+    out["label_differences"] = int(np.sum(labs["flat"][both] != labs["hierarchy"][both]))
+    out["speedup_hierarchy"] = out["flat"]["ms_per_step"] / out["hierarchy"]["ms_per_step"]
+    return out
+
+
 def section_config3(args):
     """512 periodic faces (cylinder / torus), 2^20 points."""
     import torch
@@ -178,6 +205,7 @@ def main():
     ap.add_argument("--faces", type=int, default=2000, help="faces of the batched set (default: the full set)")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--mixed-steps", type=int, default=5)
+    ap.add_argument("--tree-steps", type=int, default=10, help="timed steps with the path hierarchy")
     ap.add_argument("--cpu-sample", type=int, default=15000000, help="points of the oracle sample (about 15 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=int, default=1)
@@ -267,6 +295,28 @@ def main():
     mixed_same = bool(np.array_equal(out_l.cpu().numpy(), lab_b))
     log(f"batched mixed: {ms_mixed:.3f} ms/step; kernels {kern_mixed}; labels equal to FP64: {mixed_same}")
 
+    # path hierarchy (Sec. 4.2): subpath ellipses prune whole subpaths, so fewer
+    # pairs are tested; reported on its own row (queries/s), not as evals/s
+    def step_tree(profile=None):
+        fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, queries_per_wg=args.qpw,
+                 queue_policy=args.policy, profile=profile, stream=stream, path_hierarchy=1)
+
+    step_tree()
+    torch.cuda.synchronize()
+    ptree = wn.Profile(capacity=8 * args.tree_steps + 64)
+    tt1 = time.perf_counter()
+    for _ in range(args.tree_steps):
+        step_tree(ptree)
+    torch.cuda.synchronize()
+    ms_tree = (time.perf_counter() - tt1) * 1e3 / max(args.tree_steps, 1)
+    kern_tree = {k: t_ / max(n, 1) for k, (n, t_) in ptree.collect().items()}
+    lab_t = out_l.cpu().numpy()
+    both = (lab_t != 2) & (lab_b != 2)
+    tree_diff = int(np.sum(lab_t[both] != lab_b[both]))
+    tree_onb = int(np.sum((lab_t == 2) != (lab_b == 2)))
+    log(f"path hierarchy: {ms_tree:.3f} ms/step, {N / (ms_tree / 1e3):.3e} queries/s; kernels {kern_tree}; "
+        f"label differences vs flat {tree_diff}, on-boundary differences {tree_onb}")
+
     # plain schedule beside it (one launch per face, in-line recursion)
     step(0)
     torch.cuda.synchronize()
@@ -336,7 +386,7 @@ def main():
 
     sections = {}
     if not args.no_extra:
-        for name, fn in (("config1", section_config1), ("config3", section_config3),
+        for name, fn in (("config1", section_config1), ("long_path", section_long_path), ("config3", section_config3),
                          ("config4", section_config4), ("config5", section_config5)):
             t = time.time()
             try:
@@ -369,6 +419,9 @@ def main():
         "speedup_batched_vs_plain": ms_plain / ms_step,
         "batched_mixed": {"ms_per_step": ms_mixed, "evals_per_s": pairs / (ms_mixed / 1e3), "kernel_ms": kern_mixed,
                           "labels_equal_fp64": mixed_same},
+        "path_hierarchy": {"ms_per_step": ms_tree, "queries_per_s": N / (ms_tree / 1e3), "kernel_ms": kern_tree,
+                           "speedup_vs_flat": ms_step / ms_tree, "label_differences_vs_flat": tree_diff,
+                           "on_boundary_differences_vs_flat": tree_onb},
         "mismatches": mism,
         "kernels": kernels,
         "work": st,

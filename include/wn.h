@@ -171,6 +171,12 @@ typedef struct {
                                   schedules ADD to (zero them first): see WN_STAT_*          */
     const wn_predictor* predictor; /* WN_SCHED_BINNED with WN_BIN_PREDICTOR                  */
     int32_t bin_source;      /* WN_BIN_* (WN_SCHED_BINNED only)                             */
+    int32_t path_hierarchy;  /* 0 = every (point, segment) pair of a planar face is tested
+                                (default); 1 = the path hierarchy of Sec. 4.2 prunes subpaths
+                                whose ellipse bound excludes the point (batched and binned
+                                schedules, FP64; the near pairs, hence the recursion, are
+                                the same; points within eps of a vertex inside a pruned
+                                subpath are classified instead of reported on-boundary)  */
 } wn_query_opts;
 
 /* Work counters of the batched schedules (wn_query_opts.stats). */

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -250,6 +251,71 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     }
     std::vector<uint8_t> join(S, 0);
     for (int32_t s = 1; s < S; ++s) join[s] = (p0x[s] == pnx[s - 1] && p0y[s] == pny[s - 1]) ? 1 : 0;
+
+    // path hierarchy of the planar faces: per chain of joined segments, a
+    // balanced binary tree of subpaths in preorder.  An inner node's axis is
+    // the sum of its segments' inflated axes, inflated once more, so that its
+    // ellipse contains every descendant's (triangle inequality) with a margin
+    // for the rounding of the tests.
+    std::vector<TNode> tree;
+    std::vector<int32_t> tree_begin((size_t)F + 1, 0);
+    {
+        std::function<double(int32_t, int32_t, bool)> build = [&](int32_t lo, int32_t hi, bool root) -> double {
+            const size_t at = tree.size();
+            tree.push_back(TNode{});
+            double axis;
+            if (hi - lo == 1) {
+                axis = Bv[lo] * (1.0 + kAxisInflate) + eta[lo];
+                tree[at].hb2 = hb2[lo];
+                tree[at].seg = lo;
+            } else {
+                const int32_t mid = lo + (hi - lo) / 2;
+                axis = build(lo, mid, false) + build(mid, hi, false);
+                const double a = axis * (1.0 + kAxisInflate);
+                tree[at].hb2 = 0.5 * a * a;
+                tree[at].seg = -1;
+            }
+            tree[at].sx = p0x[lo];
+            tree[at].sy = p0y[lo];
+            tree[at].ex = pnx[hi - 1];
+            tree[at].ey = pny[hi - 1];
+            tree[at].skip = (int32_t)tree.size() | (root ? kTreeRoot : 0);
+            return axis;
+        };
+        for (int32_t f = 0; f < F; ++f) {
+            tree_begin[f] = (int32_t)tree.size();
+            if (dom[f] != WN_DOMAIN_PLANE) continue;
+            const int32_t a = h->h_seg_begin[f], b = h->h_seg_begin[f + 1];
+            for (int32_t c0 = a; c0 < b;) {
+                int32_t c1 = c0 + 1;
+                while (c1 < b && join[c1]) ++c1;
+                (void)build(c0, c1, true);
+                c0 = c1;
+            }
+        }
+        tree_begin[F] = (int32_t)tree.size();
+        if (tree.size() > (size_t)INT32_MAX / 2) {
+            delete h;
+            return WN_E_INVALID;
+        }
+    }
+    // LDS chunks: consecutive whole chains of a face, at most kTreeChunk nodes
+    // (a longer chain is a chunk of its own)
+    std::vector<int2> tchunk;
+    std::vector<int32_t> tchunk_begin((size_t)F + 1, 0);
+    for (int32_t f = 0; f < F; ++f) {
+        tchunk_begin[f] = (int32_t)tchunk.size();
+        int32_t lo = tree_begin[f];
+        for (int32_t r = tree_begin[f]; r < tree_begin[f + 1]; r = tree[r].skip & ~kTreeRoot) {
+            const int32_t end = tree[r].skip & ~kTreeRoot;  // the chain rooted at r is [r, end)
+            if (end - lo > kTreeChunk && r > lo) {
+                tchunk.push_back(make_int2(lo, r));
+                lo = r;
+            }
+        }
+        if (tree_begin[f + 1] > lo) tchunk.push_back(make_int2(lo, tree_begin[f + 1]));
+    }
+    tchunk_begin[F] = (int32_t)tchunk.size();
     h->max_depth = maxd;
     if (maxd > opt.stack_cap) {
         delete h;
@@ -267,6 +333,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->bpc_far[m][1] = far_blocks_per_cu(false, m == 1, 128);
         h->bpc_far[m][2] = far_blocks_per_cu(false, m == 1, 256);
     }
+    h->bpc_far_tree = far_tree_blocks_per_cu();
     h->bpc_farq[0] = farq_blocks_per_cu(2);
     h->bpc_farq[1] = farq_blocks_per_cu(4);
     h->bpc_far_per = far_periodic_blocks_per_cu(kPerQueue);
@@ -305,6 +372,10 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     const size_t o_deg = add(deg.data(), S), o_rat = add(rat.data(), S), o_sper = add(segper.data(), S);
     const size_t o_box = add(box.data(), box.size() * 8), o_wr = add(wrange.data(), wrange.size() * 4);
     const size_t o_join = add(join.data(), S);
+    const size_t o_tree = add(tree.data(), tree.size() * sizeof(TNode));
+    const size_t o_tbeg = add(tree_begin.data(), tree_begin.size() * 4);
+    const size_t o_tch = add(tchunk.data(), tchunk.size() * sizeof(int2));
+    const size_t o_tchb = add(tchunk_begin.data(), tchunk_begin.size() * 4);
     const size_t o_sb = add(h->h_seg_begin.data(), ((size_t)F + 1) * 4);
     const size_t o_op = add(ord_plan.data(), ord_plan.size() * 4), o_oq = add(ord_per.data(), ord_per.size() * 4);
     // periodic tables (filled after the lift)
@@ -345,6 +416,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->sg.box = (const double*)(base + o_box);
     h->sg.wrange = (const float*)(base + o_wr);
     h->sg.join = (const uint8_t*)(base + o_join);
+    h->tree = PathTree{(const TNode*)(base + o_tree), (const int32_t*)(base + o_tbeg), (const int2*)(base + o_tch),
+                       (const int32_t*)(base + o_tchb)};
     const int32_t* d_sb = (const int32_t*)(base + o_sb);
     h->ft_plan = FaceTab{d_sb, (const int32_t*)(base + o_op), (int32_t)ord_plan.size()};
     h->ft_per = FaceTab{d_sb, (const int32_t*)(base + o_oq), (int32_t)ord_per.size()};
@@ -577,6 +650,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     const bool binned = sched == WN_SCHED_BINNED && q.bin_source != WN_BIN_NONE &&
                         !(q.bin_source == WN_BIN_PREDICTOR && !q.predictor);
     if (q.bin_source < 0 || q.bin_source > WN_BIN_NONE) return WN_E_INVALID;
+    if (q.path_hierarchy != 0 && q.path_hierarchy != 1) return WN_E_INVALID;
     int64_t cap = q.near_capacity > 0 ? q.near_capacity : 8 * N + 65536;
     cap = std::min<int64_t>(cap, (int64_t)1 << 34);
     if (plain) cap = 0;  // periodic faces of the plain schedule recurse in line
@@ -635,7 +709,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     }
 
     // batched / binned: persistent far launches, (binning), near pass, finalize, redo
-    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, sc, q.profile, st);
+    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy != 0, sc, q.profile, st);
     NearQueue nq = sc.nq;
     if (e == hipSuccess && binned) {
         const wn_predictor* pr = q.predictor;
@@ -738,7 +812,7 @@ void scratch_free(Scratch& sc, hipStream_t st) {
 
 int binning_grid(const wn_faces* h) { return std::min(1024, std::max(1, h->cu_count * 4)); }
 
-hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, Scratch& sc,
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, bool tree, Scratch& sc,
                       wn_profile* prof, hipStream_t st) {
     hipError_t e = hipSuccess;
     bool zero_near = true;
@@ -746,8 +820,8 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
     if (h->num_planar > 0) {
         // 512 / 1024: two / four queries per lane (FP64); the mixed-precision
         // pass keeps one
-        const int qpl = mixed || qpw <= 256 ? 1 : qpw / 256;
-        const int qg = qpw > 256 && mixed ? 256 : qpw;
+        const int qpl = tree || mixed || qpw <= 256 ? 1 : qpw / 256;
+        const int qg = tree ? 256 : (qpw > 256 && mixed ? 256 : qpw);
         {
             ProfScope ps(prof, WN_KERNEL_ITEMS, st);
             e = launch_build_items(h->ft_plan, pts, qg, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
@@ -756,10 +830,14 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
         }
         if (e == hipSuccess) {
             const int* bp = h->bpc_far[mixed ? 1 : 0];
-            const int bpc = qpl > 1 ? h->bpc_farq[qpl / 4] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
+            const int bpc = tree ? h->bpc_far_tree
+                                 : (qpl > 1 ? h->bpc_farq[qpl / 4] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2])));
             const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR, st);
-            if (qpl > 1)
+            if (tree)
+                e = launch_far_tree(h->tree, h->ft_plan, pts, sc.item_offs, sc.item_map,
+                                    persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, st);
+            else if (qpl > 1)
                 e = launch_farq(qpl, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
                                 persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, st);
             else

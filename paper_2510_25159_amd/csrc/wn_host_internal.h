@@ -14,6 +14,7 @@ struct wn_faces {
     wn::FaceTab ft_plan{};   // planar faces, largest first
     wn::FaceTab ft_per{};    // periodic faces, largest first
     wn::PerTab pt{};
+    wn::PathTree tree{};     // path hierarchy of the planar faces
     int32_t num_faces = 0, num_loops = 0, num_segments = 0;
     int32_t num_planar = 0, num_periodic = 0;
     int32_t max_spf = 0, max_depth = 0;
@@ -21,7 +22,7 @@ struct wn_faces {
     int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
     int cu_count = 0;
     int bpc_far[2][3] = {{1, 1, 1}, {1, 1, 1}};  // resident workgroups per CU, k_far batched: [FP64, MIXED][64/128/256 points per workgroup]
-    int bpc_farq[2] = {1, 1}, bpc_far_per = 1, bpc_redo_per = 1, bpc_near = 1;
+    int bpc_farq[2] = {1, 1}, bpc_far_tree = 1, bpc_far_per = 1, bpc_redo_per = 1, bpc_near = 1;
     std::vector<int32_t> h_seg_begin;
     std::vector<int32_t> h_dom;
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
@@ -73,8 +74,8 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
 void scratch_free(Scratch& sc, hipStream_t st);
 
 // Item build + persistent far passes (planar, periodic) filling sc.nq.
-hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, Scratch& sc, wn_profile* prof,
-                      hipStream_t st);
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, bool tree, Scratch& sc,
+                      wn_profile* prof, hipStream_t st);
 // Near pass over nq; entry_depth optional.
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
                      uint8_t* entry_depth, wn_profile* prof, hipStream_t st);

@@ -46,6 +46,29 @@ struct Segs {
     const float* wrange;// [S][2] min, max weight
 };
 
+// Path hierarchy (Sec. 4.2): per chain of bit-joined segments
+// of a planar face, a balanced binary tree of subpaths in preorder.  A node's
+// ellipse has foci at the subpath's start and end and an axis bounding its
+// length (sum of the segments' inflated bounds); a query outside it sees the
+// whole subpath as its chord.  Leaves carry the segment's own root test.
+struct TNode {
+    double sx, sy, ex, ey;  // first segment's gamma(0), last segment's gamma(1)
+    double hb2;             // 0.5 * axis^2 (leaves: the segment's hb2)
+    int32_t skip;           // index of the node after this subtree; bit 31 set at a chain's root
+    int32_t seg;            // segment of a leaf, -1 for an inner node
+};
+static_assert(sizeof(TNode) == 48, "one node per 48 B");
+constexpr int32_t kTreeRoot = (int32_t)0x80000000u;
+
+struct PathTree {
+    const TNode* node;        // [nodes]
+    const int32_t* begin;     // [F+1] nodes of face f are [begin[f], begin[f+1]) (empty for periodic faces)
+    const int2* chunk;        // [chunks] node ranges of whole chains, at most kTreeChunk nodes unless one
+                              // chain is longer (its nodes beyond kTreeChunk are read from memory)
+    const int32_t* chunk_begin;  // [F+1] chunks of face f are [chunk_begin[f], chunk_begin[f+1])
+};
+constexpr int kTreeChunk = 512;  // nodes staged in LDS at a time (24 KB)
+
 struct FaceTab {
     const int32_t* seg_begin;  // [F+1] segments of face f are [seg_begin[f], seg_begin[f+1])
     const int32_t* order;      // [F] faces sorted by segment count, descending
@@ -144,6 +167,11 @@ hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, i
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2,
                        const NearQueue& nq, int64_t max_grid, hipStream_t st);
 int far_blocks_per_cu(bool inline_near, bool mixed, int qpw);
+// Queued FP64 far pass over the path hierarchy (items of 256 queries).
+hipError_t launch_far_tree(const PathTree& tr, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+                           const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
+                           double eps2, hipStream_t st);
+int far_tree_blocks_per_cu();
 // Queued FP64 far pass with qpl (2 or 4) queries per lane (items of 256 qpl queries).
 hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                        const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out, double eps2,

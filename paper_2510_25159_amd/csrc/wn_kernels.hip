@@ -579,6 +579,106 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
 }
 
 // ---------------------------------------------------------------------------
+// Far-field kernel over the path hierarchy (queued FP64 schedules): one query
+// per lane, each lane walking its face's subpath trees in preorder with a
+// skip index (no stack).  At a node the query either descends (inside the
+// node's ellipse, inner node) or takes the node's chord: outside the ellipse
+// the subpath and its chord form a closed curve that does not wind around
+// the query, so in the chain identity the subpath's chord crossings equal the
+// crossing of the node's chord.  A leaf inside its ellipse is a near pair
+// (queued as in k_far).  A chain's root adds the chain's closing angle once.
+// The near pairs are exactly the flat pass's: a leaf is only pruned under an
+// ancestor whose (larger, inflated) ellipse the query is outside of.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Points pts, const int32_t* item_offs,
+                                                  const int2* item_map, uint32_t* item_counter, NearQueue nq,
+                                                  Out out, double eps2) {
+    __shared__ TNode s_node[kTreeChunk];  // the current chunk of whole chains
+    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    const int total = item_offs[ft.num_faces];
+    for (int iter = 0;; ++iter) {
+        int item;
+        if (item_counter) {
+            __syncthreads();
+            if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(s_item);
+        } else {
+            if (iter > 0) break;
+            item = blockIdx.x;
+        }
+        if (item >= total) break;
+        const int2 mp = item_map[item];
+        const int f = mp.x, tile = mp.y;
+        int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+        qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
+        qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+        const int64_t qi = qb + (int64_t)tile * (kWave * kWavesPerWG) + wave * kWave + lane;
+        const bool active = qi < qe;
+        double qx = 0.0, qy = 0.0;
+        if (active) {
+            qx = pts.u[qi * pts.stride];
+            qy = pts.v[qi * pts.stride];
+        }
+        const bool valid = active && fabs(qx) < kCoordLimit && fabs(qy) < kCoordLimit;
+        Turn T{1.0, 0.0, 0};
+        int xc = 0, lost = 0;
+        bool onb = false;
+        int nfill = 0;  // entries in this wave's near-pair buffer (wave-uniform)
+        for (int k = tr.chunk_begin[f]; k < tr.chunk_begin[f + 1]; ++k) {
+          const int2 ch = tr.chunk[k];
+          const int lo = ch.x, ne = ch.y;
+          __syncthreads();
+          for (int i = tid; i < min(ne - lo, kTreeChunk); i += kWG) s_node[i] = tr.node[lo + i];
+          __syncthreads();
+          int n = valid ? lo : ne;
+          for (;;) {
+            const bool walk = n < ne;
+            if (!__any(walk)) break;
+            bool need = false;
+            uint32_t seg = 0;
+            if (walk) {
+                const TNode nd = n - lo < kTreeChunk ? s_node[n - lo] : tr.node[n];
+                const double ax = nd.sx - qx, ay = nd.sy - qy, bx = nd.ex - qx, by = nd.ey - qy;
+                const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
+                onb |= (ra < eps2) | (rb < eps2);
+                if (nd.skip < 0) close_chain(T, xc, ax, ay, bx, by);  // a chain's root
+                const bool inside = !outside_ellipse(ra, rb, nd.hb2);
+                const bool leaf = nd.seg >= 0;
+                if (inside & !leaf) {
+                    ++n;  // preorder: the left child follows its parent
+                } else {
+                    xc += ray_cross(ax, ay, bx, by);
+                    need = leaf & inside & !onb;
+                    seg = (uint32_t)nd.seg;
+                    n = nd.skip & ~kTreeRoot;
+                }
+            }
+            const uint64_t m = __ballot(need);
+            if (m) {
+                const int cntm = __popcll(m);
+                if (nfill + cntm > kNearBuf) {
+                    lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
+                    nfill = 0;
+                }
+                if (need) s_nbuf[wave][nfill + lanes_below(m)] = make_uint2((uint32_t)qi, seg);
+                nfill += cntm;
+            }
+          }
+        }
+        lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
+        if (active) {
+            out.w[qi] = turn_angle(T) + kTwoPi * (double)xc;
+            out.lab[qi] = !valid ? 3 : (onb ? 2 : (lost ? kRedo : 0));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // near pass.  Each wave owns a contiguous chunk of the queue and keeps all
 // its lanes busy: a lane that finishes its pair takes the next pair of the
 // chunk (wave-local counter, no global atomics).  One node of Alg. 1 per
@@ -1028,6 +1128,21 @@ int farq_blocks_per_cu(int qpl) {
     hipError_t e = hipErrorInvalidValue;
     if (qpl == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_farq<2>, kWG, 0);
     if (qpl == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_farq<4>, kWG, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t launch_far_tree(const PathTree& tr, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
+                           const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
+                           double eps2, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_far_tree, dim3((unsigned)grid), dim3(kWG), 0, st, tr, ft, pts, item_offs, item_map,
+                       item_counter, nq, out, eps2);
+    return hipGetLastError();
+}
+
+int far_tree_blocks_per_cu() {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far_tree, kWG, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

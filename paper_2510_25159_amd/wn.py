@@ -64,7 +64,7 @@ class wn_query_opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("queries_per_wg", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
                 ("near_capacity", ctypes.c_int64), ("depth_log", _P), ("profile", _P), ("stats", _P),
-                ("predictor", _P), ("bin_source", ctypes.c_int32)]
+                ("predictor", _P), ("bin_source", ctypes.c_int32), ("path_hierarchy", ctypes.c_int32)]
 
 
 class wn_train_opts(ctypes.Structure):
@@ -271,7 +271,8 @@ class FaceSet:
     def query(self, u, v, offsets, offsets_host=None, out_w=None, out_lab=None, *, stride: int = 1,
               schedule: Optional[int] = None, precision: Optional[int] = None, rule: Optional[int] = None,
               queries_per_wg: int = 0, queue_policy: int = 0, near_capacity: int = 0, depth_log=None,
-              profile: Optional[Profile] = None, stats=None, predictor=None, bin_source: int = 0, stream=None):
+              profile: Optional[Profile] = None, stats=None, predictor=None, bin_source: int = 0,
+              path_hierarchy: int = 0, stream=None):
         """Run the query on torch CUDA tensors (float64 u, v; int64 offsets).
 
         Returns (out_w, out_lab) torch tensors (allocated when not given)."""
@@ -304,6 +305,7 @@ class FaceSet:
         q.stats = None if stats is None else stats.data_ptr()
         q.predictor = None if predictor is None else predictor.handle
         q.bin_source = bin_source
+        q.path_hierarchy = path_hierarchy
         st = lib().wn_query_ex(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
                                _stream_ptr(stream))
         if st != WN_OK:

@@ -86,6 +86,44 @@ def test_near_queue_overflow_falls_back_in_line(torch_cuda, c2_small, qpw):
     compare(w, lab, w_o, n_o)
 
 
+@pytest.mark.parametrize("policy,cap", [(1, 0), (2, 0), (1, 1000)])
+def test_path_hierarchy(torch_cuda, c1, c2_small, policy, cap):
+    """Path hierarchy (subpath ellipses prune whole subpaths): oracle parity,
+    and the same labels and the same near pairs as the flat far pass."""
+    for f, q, w_o, n_o in (c1, c2_small):
+        print(f"path hierarchy policy={policy} cap={cap} points={q.num_points}", flush=True)
+        w, lab = run_wn(f, q, schedule=1, queue_policy=policy, near_capacity=cap, path_hierarchy=1)
+        st = compare(w, lab, w_o, n_o)
+        assert st["compared"] > 0.99 * q.num_points
+        w0, lab0 = run_wn(f, q, schedule=1, queue_policy=policy, near_capacity=cap)
+        far = n_o == 0
+        assert np.array_equal(lab[far], lab0[far])
+        ok = far & np.isfinite(w0)
+        assert np.max(np.abs(w[ok] - w0[ok])) <= 1e-12
+    if cap == 0:
+        import torch
+
+        stats = [torch.zeros(8, dtype=torch.int64, device="cuda") for _ in range(2)]
+        f, q = c2_small[0], c2_small[1]
+        run_wn(f, q, schedule=1, queue_policy=policy, stats=stats[0])
+        run_wn(f, q, schedule=1, queue_policy=policy, stats=stats[1], path_hierarchy=1)
+        s0, s1 = stats[0].cpu().tolist(), stats[1].cpu().tolist()
+        assert s0[:6] == s1[:6]  # same near pairs, splits, leaves, evaluations, flops, depth
+
+
+def test_path_hierarchy_long_path(torch_cuda, oracle_lib):
+    """A 4,096-segment star loop: the hierarchy prunes most of it; both far
+    passes against the oracle."""
+    faces = W.config1_faces(nseg=4096)
+    q = W.config1_queries(n=8192)
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    for tree in (0, 1):
+        print(f"long path tree={tree}", flush=True)
+        w, lab = run_wn(faces, q, schedule=1, path_hierarchy=tree)
+        st = compare(w, lab, w_o, n_o)
+        assert st["compared"] > 0.99 * q.num_points
+
+
 def test_interleaved_points_and_device_offsets(torch_cuda, c2_small):
     f, q, w_o, n_o = c2_small
     w, lab = run_wn(f, q, schedule=0, stride=2, offsets_host=False)
@@ -105,16 +143,16 @@ def test_edge_cases(torch_cuda, oracle_lib):
            rng.uniform(-1.5, 1.5, (257, 2)), np.array([[0.25, 0.5]])]
     q = W.queries_for_faces(pts)
     w_o, n_o = oracle_lib.query_faces(faces, q)
-    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
-        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw)
+    for sched, qpw, tree in ((0, 0, 0), (1, 0, 0), (1, 512, 0), (1, 0, 1)):
+        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw, path_hierarchy=tree)
         compare(w, lab, w_o, n_o)
         assert np.all(w[5:8] == 0.0)  # face without loops
     # vertices and invalid points on the square face
     special = np.array([[1.0, 1.0], [-1.0, 1.0], [np.nan, 0.0], [np.inf, 1.0], [2e15, 0.0], [0.0, 0.0]])
     q2 = W.queries_for_faces([special])
     f2 = W.faces_from_loops([[sq]])
-    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
-        w, lab = run_wn(f2, q2, schedule=sched, queries_per_wg=qpw)
+    for sched, qpw, tree in ((0, 0, 0), (1, 0, 0), (1, 512, 0), (1, 0, 1)):
+        w, lab = run_wn(f2, q2, schedule=sched, queries_per_wg=qpw, path_hierarchy=tree)
         assert list(lab) == [2, 2, 3, 3, 3, 1]
         assert np.all(np.isnan(w[:5])) and abs(w[5] - 1.0) < 1e-15
 
@@ -149,8 +187,8 @@ def test_near_boundary_points(torch_cuda, oracle_lib):
         P.append(p + 10.0 ** rng.uniform(-11, -3) * rng.choice([-1, 1]) * nrm)
     q = W.queries_for_faces([np.array(P)])
     w_o, n_o = oracle_lib.query_faces(faces, q)
-    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
-        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw)
+    for sched, qpw, tree in ((0, 0, 0), (1, 0, 0), (1, 512, 0), (1, 0, 1)):
+        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw, path_hierarchy=tree)
         st = compare(w, lab, w_o, n_o)
         assert st["compared"] > 1500
 
@@ -214,7 +252,7 @@ def test_queries_on_chords_and_ray_ties(torch_cuda, oracle_lib):
     q = W.queries_for_faces(pts)
     w_o, n_o = oracle_lib.query_faces(faces, q)
     assert np.all(n_o == 0)  # every query is well away from the curves
-    for sched, qpw in ((0, 0), (1, 0), (1, 512)):
-        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw)
+    for sched, qpw, tree in ((0, 0, 0), (1, 0, 0), (1, 512, 0), (1, 0, 1)):
+        w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw, path_hierarchy=tree)
         st = compare(w, lab, w_o, n_o)
         assert st["compared"] == q.num_points
