@@ -135,13 +135,14 @@ def section_long_path(args):
     pairs = faces.num_segments * q.num_points
     out = {"segments": faces.num_segments, "points": q.num_points, "pairs": pairs}
     labs = {}
-    for name, tree in (("flat", 0), ("hierarchy", 1)):
+    for name, tree in (("flat", 0), ("hierarchy", 1), ("auto", 2)):
         ms, k = _time_query(torch, fs, tens, q.face_point_offsets, 5, schedule=1, path_hierarchy=tree)
         w, lab = fs.query(*tens, q.face_point_offsets, schedule=1, path_hierarchy=tree)
         labs[name] = lab.cpu().numpy()
         out[name] = {"ms_per_step": ms, "queries_per_s": q.num_points / (ms / 1e3), "kernel_ms": k}
-    both = (labs["flat"] != 2) & (labs["hierarchy"] != 2)
-    out["label_differences"] = int(np.sum(labs["flat"][both] != labs["hierarchy"][both]))
+    both = (labs["flat"] != 2) & (labs["hierarchy"] != 2) & (labs["auto"] != 2)
+    out["label_differences"] = int(np.sum(labs["flat"][both] != labs["hierarchy"][both]) +
+                                   np.sum(labs["flat"][both] != labs["auto"][both]))
     out["speedup_hierarchy"] = out["flat"]["ms_per_step"] / out["hierarchy"]["ms_per_step"]
     return out
 

@@ -176,7 +176,9 @@ typedef struct {
                                 whose ellipse bound excludes the point (batched and binned
                                 schedules, FP64; the near pairs, hence the recursion, are
                                 the same; points within eps of a vertex inside a pruned
-                                subpath are classified instead of reported on-boundary)  */
+                                subpath are classified instead of reported on-boundary);
+                                2 = automatic: the hierarchy for faces with a chain of at
+                                least 512 joined segments, the flat scan for the others   */
 } wn_query_opts;
 
 /* Work counters of the batched schedules (wn_query_opts.stats). */

@@ -347,6 +347,15 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         return (h->h_seg_begin[a + 1] - h->h_seg_begin[a]) > (h->h_seg_begin[b + 1] - h->h_seg_begin[b]);
     };
     std::stable_sort(ord_plan.begin(), ord_plan.end(), by_size);
+    // automatic hierarchy: faces with a chain of at least kTreeAutoSegs segments
+    // take the tree walk, the others the flat scan
+    std::vector<int32_t> ord_tree, ord_flat;
+    for (int32_t f : ord_plan) {
+        int32_t longest = 0;
+        for (int32_t r = tree_begin[f]; r < tree_begin[f + 1]; r = tree[r].skip & ~kTreeRoot)
+            longest = std::max(longest, ((tree[r].skip & ~kTreeRoot) - r + 1) / 2);  // 2m - 1 nodes
+        (longest >= kTreeAutoSegs ? ord_tree : ord_flat).push_back(f);
+    }
     std::stable_sort(ord_per.begin(), ord_per.end(), by_size);
     h->per_pos.assign((size_t)F, 0);
     for (size_t r = 0; r < ord_per.size(); ++r) h->per_pos[ord_per[r]] = (int32_t)r;
@@ -378,6 +387,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     const size_t o_tchb = add(tchunk_begin.data(), tchunk_begin.size() * 4);
     const size_t o_sb = add(h->h_seg_begin.data(), ((size_t)F + 1) * 4);
     const size_t o_op = add(ord_plan.data(), ord_plan.size() * 4), o_oq = add(ord_per.data(), ord_per.size() * 4);
+    const size_t o_ot = add(ord_tree.data(), ord_tree.size() * 4), o_of = add(ord_flat.data(), ord_flat.size() * 4);
     // periodic tables (filled after the lift)
     const size_t o_ploop = add(nullptr, nper ? (size_t)L * sizeof(PLoop) : 0);
     const size_t o_pface = add(nullptr, nper ? (size_t)F * sizeof(PFace) : 0);
@@ -420,6 +430,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
                        (const int32_t*)(base + o_tchb)};
     const int32_t* d_sb = (const int32_t*)(base + o_sb);
     h->ft_plan = FaceTab{d_sb, (const int32_t*)(base + o_op), (int32_t)ord_plan.size()};
+    h->ft_tree = FaceTab{d_sb, (const int32_t*)(base + o_ot), (int32_t)ord_tree.size()};
+    h->ft_flat = FaceTab{d_sb, (const int32_t*)(base + o_of), (int32_t)ord_flat.size()};
     h->ft_per = FaceTab{d_sb, (const int32_t*)(base + o_oq), (int32_t)ord_per.size()};
     h->pt.seg_periodic = (const uint8_t*)(base + o_sper);
 
@@ -650,7 +662,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     const bool binned = sched == WN_SCHED_BINNED && q.bin_source != WN_BIN_NONE &&
                         !(q.bin_source == WN_BIN_PREDICTOR && !q.predictor);
     if (q.bin_source < 0 || q.bin_source > WN_BIN_NONE) return WN_E_INVALID;
-    if (q.path_hierarchy != 0 && q.path_hierarchy != 1) return WN_E_INVALID;
+    if (q.path_hierarchy < 0 || q.path_hierarchy > 2) return WN_E_INVALID;
     int64_t cap = q.near_capacity > 0 ? q.near_capacity : 8 * N + 65536;
     cap = std::min<int64_t>(cap, (int64_t)1 << 34);
     if (plain) cap = 0;  // periodic faces of the plain schedule recurse in line
@@ -709,7 +721,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     }
 
     // batched / binned: persistent far launches, (binning), near pass, finalize, redo
-    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy != 0, sc, q.profile, st);
+    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st);
     NearQueue nq = sc.nq;
     if (e == hipSuccess && binned) {
         const wn_predictor* pr = q.predictor;
@@ -812,37 +824,50 @@ void scratch_free(Scratch& sc, hipStream_t st) {
 
 int binning_grid(const wn_faces* h) { return std::min(1024, std::max(1, h->cu_count * 4)); }
 
-hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, bool tree, Scratch& sc,
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
                       wn_profile* prof, hipStream_t st) {
     hipError_t e = hipSuccess;
     bool zero_near = true;
     const bool persistent = policy != 2;
-    if (h->num_planar > 0) {
+    // planar faces: the flat scan, the hierarchy walk, or each where it pays
+    const FaceTab& flat_ft = tree == 2 ? h->ft_flat : h->ft_plan;
+    const FaceTab& tree_ft = tree == 2 ? h->ft_tree : h->ft_plan;
+    if (tree != 1 && flat_ft.num_faces > 0) {
         // 512 / 1024: two / four queries per lane (FP64); the mixed-precision
         // pass keeps one
-        const int qpl = tree || mixed || qpw <= 256 ? 1 : qpw / 256;
-        const int qg = tree ? 256 : (qpw > 256 && mixed ? 256 : qpw);
+        const int qpl = mixed || qpw <= 256 ? 1 : qpw / 256;
+        const int qg = qpw > 256 && mixed ? 256 : qpw;
         {
             ProfScope ps(prof, WN_KERNEL_ITEMS, st);
-            e = launch_build_items(h->ft_plan, pts, qg, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
+            e = launch_build_items(flat_ft, pts, qg, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
                                    zero_near, st);
             zero_near = false;
         }
         if (e == hipSuccess) {
             const int* bp = h->bpc_far[mixed ? 1 : 0];
-            const int bpc = tree ? h->bpc_far_tree
-                                 : (qpl > 1 ? h->bpc_farq[qpl / 4] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2])));
+            const int bpc = qpl > 1 ? h->bpc_farq[qpl / 4] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
             const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR, st);
-            if (tree)
-                e = launch_far_tree(h->tree, h->ft_plan, pts, sc.item_offs, sc.item_map,
-                                    persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, st);
-            else if (qpl > 1)
-                e = launch_farq(qpl, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
+            if (qpl > 1)
+                e = launch_farq(qpl, h->sg, flat_ft, pts, sc.item_offs, sc.item_map,
                                 persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, st);
             else
-                e = launch_far(false, mixed, qg, h->sg, h->ft_plan, pts, sc.item_offs, sc.item_map,
+                e = launch_far(false, mixed, qg, h->sg, flat_ft, pts, sc.item_offs, sc.item_map,
                                persistent ? sc.counters : nullptr, -1, grid, sc.nq, sc.out, h->eps2, st);
+        }
+    }
+    if (e == hipSuccess && tree != 0 && tree_ft.num_faces > 0) {
+        {
+            ProfScope ps(prof, WN_KERNEL_ITEMS, st);
+            e = launch_build_items(tree_ft, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters, zero_near,
+                                   st);
+            zero_near = false;
+        }
+        if (e == hipSuccess) {
+            const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_far_tree : sc.max_items;
+            ProfScope ps(prof, WN_KERNEL_FAR, st);
+            e = launch_far_tree(h->tree, tree_ft, pts, sc.item_offs, sc.item_map, persistent ? sc.counters : nullptr,
+                                grid, sc.nq, sc.out, h->eps2, st);
         }
     }
     if (e == hipSuccess && h->num_periodic > 0) {

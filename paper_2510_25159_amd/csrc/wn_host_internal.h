@@ -13,6 +13,8 @@ struct wn_faces {
     wn::Segs sg{};
     wn::FaceTab ft_plan{};   // planar faces, largest first
     wn::FaceTab ft_per{};    // periodic faces, largest first
+    wn::FaceTab ft_tree{};   // planar faces with a chain of >= kTreeAutoSegs segments (automatic hierarchy)
+    wn::FaceTab ft_flat{};   // the other planar faces
     wn::PerTab pt{};
     wn::PathTree tree{};     // path hierarchy of the planar faces
     int32_t num_faces = 0, num_loops = 0, num_segments = 0;
@@ -74,7 +76,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
 void scratch_free(Scratch& sc, hipStream_t st);
 
 // Item build + persistent far passes (planar, periodic) filling sc.nq.
-hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, bool tree, Scratch& sc,
+hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
                       wn_profile* prof, hipStream_t st);
 // Near pass over nq; entry_depth optional.
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,

@@ -68,6 +68,7 @@ struct PathTree {
     const int32_t* chunk_begin;  // [F+1] chunks of face f are [chunk_begin[f], chunk_begin[f+1])
 };
 constexpr int kTreeChunk = 512;  // nodes staged in LDS at a time (24 KB)
+constexpr int kTreeAutoSegs = 512;  // automatic hierarchy: faces with a chain at least this long
 
 struct FaceTab {
     const int32_t* seg_begin;  // [F+1] segments of face f are [seg_begin[f], seg_begin[f+1])

@@ -169,7 +169,7 @@ wn_status wn_predictor_train(wn_predictor* pr, const wn_faces* h, const wn_point
     if (e != hipSuccess) return hip_status(e);
     uint8_t* d_depth = nullptr;
     e = hipMallocAsync((void**)&d_depth, (size_t)cap, st);
-    if (e == hipSuccess) e = far_passes(h, pts, 256, 1, false, false, sc, nullptr, st);
+    if (e == hipSuccess) e = far_passes(h, pts, 256, 1, false, 0, sc, nullptr, st);
     if (e == hipSuccess) e = near_pass(h, pts, sc.nq, sc.out, nullptr, d_depth, nullptr, st);
     unsigned long long cnt = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&cnt, sc.nq.count, 8, hipMemcpyDeviceToHost, st);

@@ -86,13 +86,13 @@ def test_near_queue_overflow_falls_back_in_line(torch_cuda, c2_small, qpw):
     compare(w, lab, w_o, n_o)
 
 
-@pytest.mark.parametrize("policy,cap", [(1, 0), (2, 0), (1, 1000)])
-def test_path_hierarchy(torch_cuda, c1, c2_small, policy, cap):
+@pytest.mark.parametrize("policy,cap,mode", [(1, 0, 1), (2, 0, 1), (1, 1000, 1), (1, 0, 2)])
+def test_path_hierarchy(torch_cuda, c1, c2_small, policy, cap, mode):
     """Path hierarchy (subpath ellipses prune whole subpaths): oracle parity,
     and the same labels and the same near pairs as the flat far pass."""
     for f, q, w_o, n_o in (c1, c2_small):
-        print(f"path hierarchy policy={policy} cap={cap} points={q.num_points}", flush=True)
-        w, lab = run_wn(f, q, schedule=1, queue_policy=policy, near_capacity=cap, path_hierarchy=1)
+        print(f"path hierarchy mode={mode} policy={policy} cap={cap} points={q.num_points}", flush=True)
+        w, lab = run_wn(f, q, schedule=1, queue_policy=policy, near_capacity=cap, path_hierarchy=mode)
         st = compare(w, lab, w_o, n_o)
         assert st["compared"] > 0.99 * q.num_points
         w0, lab0 = run_wn(f, q, schedule=1, queue_policy=policy, near_capacity=cap)
@@ -117,7 +117,7 @@ def test_path_hierarchy_long_path(torch_cuda, oracle_lib):
     faces = W.config1_faces(nseg=4096)
     q = W.config1_queries(n=8192)
     w_o, n_o = oracle_lib.query_faces(faces, q)
-    for tree in (0, 1):
+    for tree in (0, 1, 2):
         print(f"long path tree={tree}", flush=True)
         w, lab = run_wn(faces, q, schedule=1, path_hierarchy=tree)
         st = compare(w, lab, w_o, n_o)
