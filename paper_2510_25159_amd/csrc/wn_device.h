@@ -236,6 +236,31 @@ __device__ __forceinline__ void load_coef(const Segs& sg, int s, Coef& c) {
     c.rat = sg.rat[s] != 0;
 }
 
+// The coefficient record's fourth components carry the segment's near-pass
+// data, so that a near pair gathers one contiguous 192-B record.
+struct NearSeg {
+    double B, eta, p0x, p0y, pnx, pny;
+};
+__device__ __forceinline__ void load_near_seg(const Segs& sg, int s, Coef& c, NearSeg& g) {
+    const double4* cf = reinterpret_cast<const double4*>(sg.coef) + (size_t)s * kCoef;
+    double pad[kCoef];
+#pragma unroll
+    for (int j = 0; j < kCoef; ++j) {
+        const double4 v = cf[j];
+        c.x[j] = v.x;
+        c.y[j] = v.y;
+        c.w[j] = v.z;
+        pad[j] = v.w;
+    }
+    c.n = sg.deg[s];
+    c.rat = sg.rat[s] != 0;
+    g = NearSeg{pad[kPadB], pad[kPadEta], pad[kPadP0x], pad[kPadP0y], pad[kPadPnx], pad[kPadPny]};
+}
+__device__ __forceinline__ double2 seg_end_point(const Segs& sg, int s) {
+    const double4* cf = reinterpret_cast<const double4*>(sg.coef) + (size_t)s * kCoef;
+    return make_double2(cf[kPadPnx].w, cf[kPadPny].w);
+}
+
 // Reciprocal to full precision: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double recip(double d) {
     double r = __builtin_amdgcn_rcp(d);
@@ -384,12 +409,12 @@ __device__ int near_pair(int& N, const Coef& c, double B, double eta, double pnx
 // Near pair with all segment data read from global memory (integer part only).
 __device__ __forceinline__ int near_from_global(int& N, const Segs& sg, uint32_t s, double qx, double qy,
                                                 double eps2, double4* stk, bool& onb) {
-    const double ax = sg.p0x[s] - qx, ay = sg.p0y[s] - qy;
-    const double pnx = sg.pnx[s], pny = sg.pny[s];
-    const double bx = pnx - qx, by = pny - qy;
     Coef c;
-    load_coef(sg, s, c);
-    return near_pair(N, c, sg.B[s], sg.eta[s], pnx, pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
+    NearSeg g;
+    load_near_seg(sg, s, c, g);
+    const double ax = g.p0x - qx, ay = g.p0y - qy;
+    const double bx = g.pnx - qx, by = g.pny - qy;
+    return near_pair(N, c, g.B, g.eta, g.pnx, g.pny, qx, qy, ax, ay, ax * ax + ay * ay, bx, by, bx * bx + by * by,
                      eps2, stk, onb);
 }
 

@@ -247,6 +247,9 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
                 slot[2] = c;
                 slot[3] = 0.0;
             }
+            // the near pass's per-segment data in the slots' fourth components
+            const double pads[kCoef] = {B, e, u[0], v[0], u[n], v[n]};
+            for (int j = 0; j < kCoef; ++j) coef[((size_t)s * kCoef + j) * 4 + 3] = pads[j];
         }
     }
     std::vector<uint8_t> join(S, 0);

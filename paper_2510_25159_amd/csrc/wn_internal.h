@@ -9,6 +9,9 @@ namespace wn {
 
 constexpr int kMaxDeg = 5;
 constexpr int kCoef = kMaxDeg + 1;  // coefficient slots per segment
+// fourth components of a segment's coefficient slots
+constexpr int kPadB = 0, kPadEta = 1, kPadP0x = 2, kPadP0y = 3, kPadPnx = 4, kPadPny = 5;
+static_assert(kCoef == 6, "six padding doubles per segment record");
 constexpr int kWave = 64;
 constexpr int kWG = 256;            // threads per workgroup of the pair kernels
 constexpr int kWavesPerWG = kWG / kWave;
@@ -38,7 +41,8 @@ struct Segs {
     const double* hb2;  // [S] 0.5 * (B (1 + kAxisInflate) + eta)^2 : root ellipse test
     const double* B;    // [S] derivative bound (Lemma 1 / App. A.1)
     const double* eta;  // [S] absolute rounding margin of the ellipse axis
-    const double* coef; // [S][kCoef][4]: slot j = (x, y, w, 0) of C(n, n-j) w_{n-j} P_{n-j}
+    const double* coef; // [S][kCoef][4]: slot j = (x, y, w, pad_j) of C(n, n-j) w_{n-j} P_{n-j};
+                        // pad_j = B, eta, p0x, p0y, pnx, pny (kPad*) for the near pass
     const uint8_t* deg; // [S] degree 1..5
     const uint8_t* rat; // [S] 1 if any weight != 1
     const uint8_t* join;// [S] 1 when gamma(0) equals the previous segment's gamma(1) bit for bit

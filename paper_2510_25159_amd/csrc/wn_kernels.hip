@@ -700,21 +700,22 @@ struct NodeState {
 };
 
 __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_t s, double qx, double qy) {
-    load_coef(sg, s, st.c);
+    NearSeg g;
+    load_near_seg(sg, s, st.c, g);
     // sum_i C(n,i) w_i (P_i - q) B_i(t) / sum_i C(n,i) w_i B_i(t) = gamma(t) - q
 #pragma unroll
     for (int j = 0; j < kCoef; ++j) {
         st.c.x[j] = fma(-st.c.w[j], qx, st.c.x[j]);
         st.c.y[j] = fma(-st.c.w[j], qy, st.c.y[j]);
     }
-    st.B = sg.B[s];
-    st.eta = sg.eta[s];
+    st.B = g.B;
+    st.eta = g.eta;
     st.seg = s;
-    st.ax = sg.p0x[s] - qx;
-    st.ay = sg.p0y[s] - qy;
+    st.ax = g.p0x - qx;
+    st.ay = g.p0y - qy;
     st.ra = st.ax * st.ax + st.ay * st.ay;
-    st.bx = sg.pnx[s] - qx;
-    st.by = sg.pny[s] - qy;
+    st.bx = g.pnx - qx;
+    st.by = g.pny - qy;
     st.rb = st.bx * st.bx + st.by * st.by;
     st.n = -ray_cross(st.ax, st.ay, st.bx, st.by);
     st.a = 0.0;
@@ -758,8 +759,9 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     double mx = 0.0, my = 0.0;
     if (sp | fl | (fr & !at_end)) bez_eval(st.c, te, mx, my);
     if (at_end) {
-        mx = sg.pnx[st.seg] - qx;
-        my = sg.pny[st.seg] - qy;
+        const double2 e = seg_end_point(sg, (int)st.seg);
+        mx = e.x - qx;
+        my = e.y - qy;
     }
     const double rm = fma(mx, mx, my * my);
     if (COUNT) nc.reeval += (fl | fr) ? 1 : 0;

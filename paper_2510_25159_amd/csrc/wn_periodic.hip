@@ -69,6 +69,11 @@ __global__ __launch_bounds__(256) void k_lift(LiftArgs a, Segs sg) {
             slot[0] = a.cpu[c0 + j] * slot[2] + ox * slot[2];
             slot[1] = a.cpv[c0 + j] * slot[2] + oy * slot[2];
         }
+        double* rec = coef + (size_t)s * kCoef * 4;  // the near pass's copy of the lifted end points
+        rec[kPadP0x * 4 + 3] = p0x[s];
+        rec[kPadP0y * 4 + 3] = p0y[s];
+        rec[kPadPnx * 4 + 3] = pnx[s];
+        rec[kPadPny * 4 + 3] = pny[s];
     }
     PLoop L{};
     L.s0 = s0;
