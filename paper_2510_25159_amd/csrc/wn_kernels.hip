@@ -765,13 +765,8 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     }
     const double rm = fma(mx, mx, my * my);
     if (COUNT) nc.reeval += (fl | fr) ? 1 : 0;
-    // resumed interval: install the re-evaluated end point
-    st.ax = fl ? mx : st.ax;
-    st.ay = fl ? my : st.ay;
-    st.ra = fl ? rm : st.ra;
-    st.bx = fr ? mx : st.bx;
-    st.by = fr ? my : st.by;
-    st.rb = fr ? rm : st.rb;
+    // a resumed interval's re-evaluated end point is installed with the
+    // split's updates below (such a lane does not split in this step)
     st.mode = fl ? 2 : (fr ? 0 : st.mode);
     // split
     const bool hit = sp & (rm < eps2);
@@ -807,14 +802,7 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     st.stored = both ? ((st.stored & ~evict) | k1bit) : st.stored;
     st.pend = both ? (st.pend | k1bit) : st.pend;
     st.pmax = (go & (k1 > st.pmax)) ? k1 : st.pmax;
-    // continue left: b <- m;  continue right: a <- m
-    st.bx = left ? mx : st.bx;
-    st.by = left ? my : st.by;
-    st.rb = left ? rm : st.rb;
     st.a = right ? tm : st.a;
-    st.ax = right ? mx : st.ax;
-    st.ay = right ? my : st.ay;
-    st.ra = right ? rm : st.ra;
     st.k = (left | right) ? k1 : st.k;
     fin |= none & (st.pend == 0);
     const bool pop = none & (st.pend != 0);
@@ -828,12 +816,17 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     st.a = pop ? deferred_left(st.a, kk) : st.a;
     st.k = pop ? kk : st.k;
     st.mode = (pop & !kept) ? 1 : st.mode;  // end points to evaluate again in the next two steps
-    st.ax = (pop & kept) ? p.x : st.ax;
-    st.ay = (pop & kept) ? p.y : st.ay;
-    st.ra = (pop & kept) ? fma(p.x, p.x, p.y * p.y) : st.ra;
-    st.bx = (pop & kept) ? p.z : st.bx;
-    st.by = (pop & kept) ? p.w : st.by;
-    st.rb = (pop & kept) ? fma(p.z, p.z, p.w * p.w) : st.rb;
+    // end points of the next interval: m for a re-evaluated end, for the left
+    // end when continuing right and the right end when continuing left; the
+    // stored pair of a resumed interval; else unchanged (the cases exclude
+    // each other, so each field takes two selects)
+    const bool take_a = fl | right, take_b = fr | left, pk = pop & kept;
+    st.ax = take_a ? mx : (pk ? p.x : st.ax);
+    st.ay = take_a ? my : (pk ? p.y : st.ay);
+    st.ra = take_a ? rm : (pk ? fma(p.x, p.x, p.y * p.y) : st.ra);
+    st.bx = take_b ? mx : (pk ? p.z : st.bx);
+    st.by = take_b ? my : (pk ? p.w : st.by);
+    st.rb = take_b ? rm : (pk ? fma(p.z, p.z, p.w * p.w) : st.rb);
     return fin;
 }
 
