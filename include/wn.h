@@ -238,6 +238,27 @@ const char* wn_status_string(wn_status s);
 wn_status wn_segment_bound(const double* cp_u, const double* cp_v, const double* cp_w, int32_t degree,
                            double* out_B);
 
+/* NURBS p-curve to (rational) Bezier segments (Sec. 3.1: B-spline and NURBS
+ * curves subdivide into Bezier segments): every interior knot is inserted
+ * (Boehm's rule, in homogeneous coordinates) until its multiplicity equals
+ * the degree; each knot span of nonzero length is then one segment.
+ *   degree       1..5
+ *   num_cps      n >= degree + 1; cp_u, cp_v [n]; cp_w [n] weights > 0 (finite),
+ *                or NULL for a non-rational B-spline (out_w is then not written)
+ *   knots        [n + degree + 1], non-decreasing and clamped: the first and the
+ *                last value each repeated degree + 1 times, U[degree] < U[n]
+ *   out_cap      capacity of out_u, out_v (and out_w) in points
+ *   out_u/v/w    segment i's control points are entries i*degree .. i*degree +
+ *                degree (neighbours share their joint), so k segments fill
+ *                k*degree + 1 points; the joints coincide with the curve's
+ *                points at the knots
+ *   out_segments number of segments k (also set when out_cap is too small,
+ *                which returns WN_E_INVALID without writing the outputs)
+ * Host-only, all pointers host.  WN_E_INVALID for malformed arguments. */
+wn_status wn_nurbs_to_bezier(int32_t degree, int32_t num_cps, const double* knots, const double* cp_u,
+                             const double* cp_v, const double* cp_w, int64_t out_cap, double* out_u, double* out_v,
+                             double* out_w, int32_t* out_segments);
+
 /* Create a profile able to time `capacity` kernel launches (events are
  * created here, on the current device).  Timing a launch beyond the capacity
  * is skipped silently. */

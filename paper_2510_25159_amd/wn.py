@@ -27,7 +27,7 @@ EXPORTS = [
     "wn_profile_create", "wn_profile_collect", "wn_profile_destroy",
     "wn_predictor_create", "wn_predictor_destroy", "wn_predictor_train", "wn_predictor_get_params",
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
-    "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy",
+    "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy", "wn_nurbs_to_bezier",
 ]
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -116,6 +116,9 @@ def lib():
         L.wn_destroy_faces.argtypes = [_P]
         L.wn_segment_bound.restype = ctypes.c_int
         L.wn_segment_bound.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.wn_nurbs_to_bezier.restype = ctypes.c_int
+        L.wn_nurbs_to_bezier.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, _P, _P, _P,
+                                         ctypes.POINTER(ctypes.c_int32)]
         L.wn_profile_create.restype = ctypes.c_int
         L.wn_profile_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_P)]
         L.wn_profile_collect.restype = ctypes.c_int
@@ -170,6 +173,32 @@ def segment_bound(cp, w=None) -> float:
     if st != WN_OK:
         raise WnError(st, "wn_segment_bound")
     return out.value
+
+
+def nurbs_to_bezier(degree: int, knots, cp, w=None):
+    """Split a clamped NURBS curve into (rational) Bezier segments (host).
+
+    Returns a list of (control points [degree+1, 2], weights [degree+1] or None),
+    one per knot span of nonzero length."""
+    knots = np.ascontiguousarray(knots, dtype=np.float64)
+    cp = np.ascontiguousarray(cp, dtype=np.float64)
+    u = np.ascontiguousarray(cp[:, 0])
+    v = np.ascontiguousarray(cp[:, 1])
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    n = len(cp)
+    cap = n + degree * max(len(knots), 1)  # every interior knot raised to multiplicity degree
+    ou, ov = np.empty(cap), np.empty(cap)
+    ow = None if ww is None else np.empty(cap)
+    segs = ctypes.c_int32(0)
+    st = lib().wn_nurbs_to_bezier(degree, n, _np_ptr(knots), _np_ptr(u), _np_ptr(v), _np_ptr(ww), cap, _np_ptr(ou),
+                                  _np_ptr(ov), _np_ptr(ow), ctypes.byref(segs))
+    if st != WN_OK:
+        raise WnError(st, "wn_nurbs_to_bezier")
+    out = []
+    for i in range(segs.value):
+        sl = slice(i * degree, i * degree + degree + 1)
+        out.append((np.column_stack([ou[sl], ov[sl]]), None if ow is None else ow[sl].copy()))
+    return out
 
 
 def default_options(**kw) -> wn_options:

@@ -256,3 +256,31 @@ def test_queries_on_chords_and_ray_ties(torch_cuda, oracle_lib):
         w, lab = run_wn(faces, q, schedule=sched, queries_per_wg=qpw, path_hierarchy=tree)
         st = compare(w, lab, w_o, n_o)
         assert st["compared"] == q.num_points
+
+
+def test_nurbs_faces(torch_cuda, oracle_lib):
+    """Faces given as NURBS loops, split by the library's knot insertion: a
+    rational quadratic circle (closed form: omega = 1 inside, 0 outside) and a
+    closed random quintic with interior knots (oracle)."""
+    from paper_2510_25159_amd import wn
+    from tests.test_nurbs import CIRCLE_CP, CIRCLE_KNOTS, CIRCLE_W
+
+    circle = wn.nurbs_to_bezier(2, CIRCLE_KNOTS, CIRCLE_CP, CIRCLE_W)
+    rng = np.random.default_rng(12)
+    th = np.sort(rng.uniform(0, 2 * np.pi, 11))
+    r = rng.uniform(0.6, 1.4, 11)
+    cp = np.column_stack([r * np.cos(th), r * np.sin(th)])
+    cp = np.vstack([cp, cp[:1]])  # closed: clamped ends at the same point
+    knots = np.concatenate([np.zeros(6), [0.3, 0.3, 0.55, 0.7, 0.8, 0.8], np.ones(6)])
+    wts = rng.uniform(0.5, 2.0, len(cp))
+    blob = wn.nurbs_to_bezier(5, knots, cp, wts)
+    faces = W.faces_from_loops([[circle], [blob]], rational=True)
+    P = rng.uniform(-1.6, 1.6, (20000, 2))
+    q = W.queries_for_faces([P, P])
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    for sched in (0, 1):
+        w, lab = run_wn(faces, q, schedule=sched)
+        compare(w, lab, w_o, n_o)
+        rad = np.hypot(P[:, 0], P[:, 1])
+        far = np.abs(rad - 1.0) > 1e-6
+        assert np.allclose(w[:20000][far], (rad[far] < 1.0).astype(float), atol=1e-12)
