@@ -218,8 +218,8 @@ def main():
                     help="run one plain device copy of this size first (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(queries and faces shard trivially; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(queries and faces shard across GPUs without any exchange).", file=sys.stderr)
         sys.exit(2)
 
     import torch
