@@ -202,10 +202,10 @@ int build_periodic_face(int dom, double Tu, double Tv, int l0, int l1, const std
                     bshx = shx;
                     bshy = shy;
                 } else {
-                    double qx, qy;
-                    loop_point(segs, loops[B[best]], qx, qy);
-                    // nearer when the current best lies on the candidate's left
-                    if (host_extended(segs, Lb, qx + bshx - shx, qy + bshy - shy) > 0.0) {
+                    // the candidate replaces the best when it lies on the best's
+                    // left (App. C.2, PairLoops): the beta copies face alpha with
+                    // their left sides, so it is then the nearer one
+                    if (host_extended(segs, loops[B[best]], px + shx - bshx, py + shy - bshy) > 0.0) {
                         best = (int)j;
                         bshx = shx;
                         bshy = shy;

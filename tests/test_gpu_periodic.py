@@ -117,3 +117,58 @@ def test_config3_full_sampled(torch_cuda, oracle_lib):
     st = compare(w[idx], lab[idx], w_o, n_o)
     print(st, flush=True)
     assert set(np.unique(lab)).issubset({0, 1, 2})
+
+
+def _circle_segs(c, r, dom, n=12, cw=False):
+    """A closed polygonal circle, each segment cut back into the base cell."""
+    th = np.linspace(0, 2 * np.pi, n + 1)
+    if cw:
+        th = th[::-1]
+    pts = np.asarray(c) + r * np.column_stack([np.cos(th), np.sin(th)])
+    segs = []
+    for i in range(n):
+        cp = np.stack([pts[i], pts[i + 1]])
+        mid = cp.mean(0)
+        sh = np.array([-T * np.floor(mid[0] / T), -T * np.floor(mid[1] / T) if dom == W.DOMAIN_TORUS else 0.0])
+        segs.append((cp + sh, None))
+    return segs
+
+
+def _band_loops(rng, vec, s0, width, nrm, nsa=7, nsb=5, amp=0.0):
+    axes = (0, 1) if vec[1] != 0 else (0,)
+    a = W.WrappedCurve(s0, vec, amp, rng)
+    b = W.WrappedCurve(s0 + width * nrm + rng.uniform(0, 1) * vec, -vec, amp, rng)
+    out = []
+    for cv, ns in ((a, nsa), (b, nsb)):
+        lp = W.periodic_loop(cv, ns, (T, T), axes)
+        out.append([(cp, None) for cp in lp.cps])
+    return out
+
+
+def test_mixed_loop_kinds_and_two_torus_pairs(torch_cuda, oracle_lib):
+    """Periodic faces beyond the configuration's: a cylinder band with
+    contractible holes (one across the seam) next to its non-contractible
+    loops, and a torus with two pairs of (1, 0) loops plus a hole."""
+    rng = np.random.default_rng(31)
+    # cylinder: band -1 < v < 1.5 (bumpy), holes at v = 0.2
+    band = _band_loops(rng, np.array([T, 0.0]), np.array([0.4, -1.0]), 2.5, np.array([0.0, 1.0]), amp=0.1)
+    holes = [_circle_segs((2.0, 0.2), 0.5, W.DOMAIN_CYLINDER_U, cw=True),
+             _circle_segs((T - 0.2, 0.3), 0.45, W.DOMAIN_CYLINDER_U, cw=True)]
+    # torus: bands 0.5 < v < 1.5 and 3.5 < v < 4.6, a hole inside the first
+    nrm = np.array([0.0, 1.0])
+    p1 = _band_loops(rng, np.array([T, 0.0]), np.array([0.3, 0.5]), 1.0, nrm)
+    p2 = _band_loops(rng, np.array([T, 0.0]), np.array([1.1, 3.5]), 1.1, nrm, amp=0.05)
+    thole = [_circle_segs((4.0, 1.0), 0.3, W.DOMAIN_TORUS, cw=True)]
+    faces = W.faces_from_loops([band + holes, p1 + p2 + thole], domains=[W.DOMAIN_CYLINDER_U, W.DOMAIN_TORUS],
+                               periods=[[T, T], [T, T]])
+    Pc = np.column_stack([rng.uniform(-T, 2 * T, 6000), rng.uniform(-2.0, 2.5, 6000)])
+    Pt = rng.uniform(-T, 2 * T, (6000, 2))
+    q = W.queries_for_faces([Pc, Pt])
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    assert set(np.unique(np.round(w_o[n_o == 0]))) <= {0.0, 1.0}
+    assert np.sum(np.round(w_o[n_o == 0]) == 1.0) > 1000
+    for sched in (1, 0):
+        print(f"mixed loop kinds schedule={sched}", flush=True)
+        w, lab = run_wn(faces, q, schedule=sched)
+        st = compare(w, lab, w_o, n_o)
+        assert st["compared"] > 0.98 * q.num_points

@@ -61,6 +61,33 @@ def test_torus_straight_band_closed_form(oracle_lib, h):
     np.testing.assert_allclose(w, want, atol=1e-12)
 
 
+@pytest.mark.parametrize("h", [(1, 0), (2, 3), (1, -2)])
+def test_torus_two_straight_bands_closed_form(oracle_lib, h):
+    """Two pairs of (h, -h) loops on one torus: each alpha pairs with the
+    nearest beta on its left (App. C.2), so omega is 1 inside either band and 0
+    in the two gaps, whatever order the loops come in."""
+    rng = np.random.default_rng(h[0] * 7 + h[1] + 50)
+    vec = np.array([h[0] * T, h[1] * T])
+    L = np.hypot(*vec)
+    delta = T * T / L
+    nrm = np.array([-vec[1], vec[0]]) / L
+    s0 = rng.uniform(0, T, 2)
+    # bands [0, 0.2) and [0.45, 0.8) of the family spacing, measured from alpha 1
+    edges = np.array([0.0, 0.2, 0.45, 0.8]) * delta
+    curves = []
+    for k, (e, d) in enumerate(zip(edges, (vec, -vec, vec, -vec))):
+        curves.append((W.WrappedCurve(s0 + e * nrm + rng.uniform(0, 1) * vec, d, 0.0, rng), 4 + k))
+    for order in ([0, 1, 2, 3], [0, 3, 2, 1], [2, 1, 0, 3]):
+        f = _face([curves[i] for i in order], W.DOMAIN_TORUS)
+        P = rng.uniform(-T, 2 * T, (3000, 2))
+        fr = np.mod((P - s0) @ nrm / delta, 1.0)
+        ok = np.all(np.abs(fr[:, None] - np.array([0.0, 0.2, 0.45, 0.8, 1.0])[None, :]) > 1e-7, axis=1)
+        P, fr = P[ok], fr[ok]
+        w, near = _eval(oracle_lib, f, P)
+        want = ((fr < 0.2) | ((fr > 0.45) & (fr < 0.8))).astype(float)
+        np.testing.assert_allclose(w, want, atol=1e-12)
+
+
 def test_lattice_translation_and_window_invariance(oracle_lib):
     """Closed loops: omega is lattice periodic.  Open loops (chained by their
     own end-to-start vector, App. C) keep the window invariance exactly.
