@@ -243,7 +243,7 @@ wn_status wn_segment_bound(const double* cp_u, const double* cp_v, const double*
  * (Boehm's rule, in homogeneous coordinates) until its multiplicity equals
  * the degree; each knot span of nonzero length is then one segment.
  *   degree       1..5
- *   num_cps      n >= degree + 1; cp_u, cp_v [n]; cp_w [n] weights > 0 (finite),
+ *   num_cps      degree + 1 <= n <= 16384; cp_u, cp_v [n]; cp_w [n] weights > 0 (finite),
  *                or NULL for a non-rational B-spline (out_w is then not written)
  *   knots        [n + degree + 1], non-decreasing and clamped: the first and the
  *                last value each repeated degree + 1 times, U[degree] < U[n]

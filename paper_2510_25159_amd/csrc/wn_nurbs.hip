@@ -23,13 +23,17 @@ struct H3 {
 
 bool finite_cp(double v) { return isfinite(v) && fabs(v) < wn::kCoordLimit; }
 
+constexpr int kMaxNurbsCps = 16384;
+
 }  // namespace
 
 extern "C" wn_status wn_nurbs_to_bezier(int32_t degree, int32_t num_cps, const double* knots, const double* cp_u,
                                         const double* cp_v, const double* cp_w, int64_t out_cap, double* out_u,
                                         double* out_v, double* out_w, int32_t* out_segments) {
     const int p = degree;
-    if (p < 1 || p > wn::kMaxDeg || num_cps < p + 1 || num_cps > (1 << 24) || !knots || !cp_u || !cp_v ||
+    // each insertion rewrites the control polygon (O(num_cps)); longer curves
+    // are to be split into several NURBS first
+    if (p < 1 || p > wn::kMaxDeg || num_cps < p + 1 || num_cps > kMaxNurbsCps || !knots || !cp_u || !cp_v ||
         !out_segments)
         return WN_E_INVALID;
     const int n = num_cps;
