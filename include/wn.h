@@ -349,12 +349,13 @@ wn_status wn_plan_create(const wn_faces* faces, const wn_points* points, double*
                          const wn_query_opts* q, void* stream, wn_plan** out);
 /* Replay the captured graph on `stream` (asynchronous). */
 wn_status wn_plan_launch(wn_plan* p, void* stream);
-/* Autotuner: time every (points per workgroup in {64, 128, 256}) x (queue
- * policy in {persistent, one workgroup per item}) on the plan's current
- * buffers (`reps` runs each, HIP-event timed), keep the fastest and
- * re-capture the graph.  Synchronous.  report (host, nullable, 8 doubles):
+/* Autotuner: time every (points per workgroup in {64, 128, 256, 512}) x
+ * (queue policy in {persistent, one workgroup per item}) on the plan's
+ * current buffers (`reps` runs each, HIP-event timed), keep the fastest and
+ * re-capture the graph.  Synchronous.  report (host, nullable, 10 doubles):
  * average milliseconds in the order (64,p), (64,w), (128,p), (128,w),
- * (256,p), (256,w), then the chosen points per workgroup and policy. */
+ * (256,p), (256,w), (512,p), (512,w), then the chosen points per workgroup
+ * and policy. */
 wn_status wn_plan_autotune(wn_plan* p, int32_t reps, void* stream, double* report);
 void wn_plan_destroy(wn_plan* p);
 
