@@ -157,8 +157,9 @@ typedef struct {
     int32_t schedule;        /* -1 = the handle's default, else wn_schedule               */
     int32_t precision;       /* -1 = the handle's default, else wn_precision              */
     int32_t rule;            /* -1 = the handle's default, else wn_rule                   */
-    int32_t queries_per_wg;  /* 0 = tuned; else 64, 128 or 256 queries per workgroup, or 512
-                                (two per lane: FP64 batched/binned far pass; otherwise 256) */
+    int32_t queries_per_wg;  /* 0 = tuned; else 64, 128 or 256 queries per workgroup, or 512 /
+                                1024 (two / four per lane: FP64 batched/binned far pass;
+                                otherwise 256)                                             */
     int32_t queue_policy;    /* 0 = tuned, 1 = persistent workgroups popping an atomic work
                                 queue, 2 = one workgroup per work item (batched schedules)  */
     int64_t near_capacity;   /* 0 = default (8 * num_points + 65536) near-queue entries    */
