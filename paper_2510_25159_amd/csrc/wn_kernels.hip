@@ -629,6 +629,13 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
         int xc = 0, lost = 0;
         bool onb = false;
         int nfill = 0;  // entries in this wave's near-pair buffer (wave-uniform)
+        // every chain's closing angle, once per query, in uniform control flow
+        // (the roots follow each other through their skip indices)
+        for (int r = kload(tr.begin, f), re_ = kload(tr.begin, f + 1); r < re_;) {
+            const TNode rt = kload(tr.node, r);
+            if (valid) close_chain(T, xc, rt.sx - qx, rt.sy - qy, rt.ex - qx, rt.ey - qy);
+            r = rt.skip & ~kTreeRoot;
+        }
         for (int k = tr.chunk_begin[f]; k < tr.chunk_begin[f + 1]; ++k) {
           const int2 ch = tr.chunk[k];
           const int lo = ch.x, ne = ch.y;
@@ -646,17 +653,13 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
                 const double ax = nd.sx - qx, ay = nd.sy - qy, bx = nd.ex - qx, by = nd.ey - qy;
                 const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
                 onb |= (ra < eps2) | (rb < eps2);
-                if (nd.skip < 0) close_chain(T, xc, ax, ay, bx, by);  // a chain's root
                 const bool inside = !outside_ellipse(ra, rb, nd.hb2);
                 const bool leaf = nd.seg >= 0;
-                if (inside & !leaf) {
-                    ++n;  // preorder: the left child follows its parent
-                } else {
-                    xc += ray_cross(ax, ay, bx, by);
-                    need = leaf & inside & !onb;
-                    seg = (uint32_t)nd.seg;
-                    n = nd.skip & ~kTreeRoot;
-                }
+                const bool take = !inside | leaf;  // the node's chord stands for its subpath
+                ray_cross_mask(xc, low_mask(ay), low_mask(by), ax, ay, bx, by, __builtin_amdgcn_ballot_w64(take));
+                need = take & leaf & inside & !onb;
+                seg = (uint32_t)nd.seg;
+                n = take ? (nd.skip & ~kTreeRoot) : n + 1;  // preorder: the left child follows its parent
             }
             const uint64_t m = __ballot(need);
             if (m) {
