@@ -40,6 +40,7 @@ SEED_C3 = 3
 SEED_C4_TRAIN = 40
 SEED_C4_EVAL = 41
 SEED_C5 = 5
+SEED_BREP = 6
 
 
 @dataclass
@@ -610,6 +611,110 @@ def config3(seed: int = SEED_C3, num_faces: int = 512, face_ids: Optional[Sequen
     q = Queries(u=np.ascontiguousarray(P[:, 0]), v=np.ascontiguousarray(P[:, 1]),
                 face_point_offsets=np.asarray(offs, dtype=np.int64))
     return faces, q
+
+
+# --------------------------------------------------------------------------
+# Applications (Sec. 5.4): multi-patch surfaces and tessellation grids
+# --------------------------------------------------------------------------
+@dataclass
+class Patches:
+    """Faces grouped by base surface, with sample points on each surface."""
+    faces: "Faces"
+    surface_face_offsets: np.ndarray  # int32 [S+1]
+    surface_faces: np.ndarray  # int32 [K]
+    u: np.ndarray  # float64 [N], grouped by surface
+    v: np.ndarray
+    surface_point_offsets: np.ndarray  # int64 [S+1]
+
+    @property
+    def num_surfaces(self) -> int:
+        return len(self.surface_face_offsets) - 1
+
+
+def _moved(lp: _Loop, scale: float, center) -> _Loop:
+    out = _Loop()
+    for cp, w in zip(lp.cps, lp.ws):
+        out.cps.append(cp * scale + np.asarray(center, dtype=np.float64))
+        out.ws.append(None if w is None else w.copy())
+    return out
+
+
+def brep_patches(seed: int = SEED_BREP, num_surfaces: int = 64, points_per_surface: int = 16384,
+                 faces_lo: int = 2, faces_hi: int = 6, periodic_every: int = 4, seg_hi: int = 256,
+                 unreferenced: int = 0) -> Patches:
+    """A synthetic multi-patch B-Rep (the Boolean-union models of Sec. 5.4.1):
+    each base surface is referenced by several trimmed faces and sampled
+    uniformly over its parameter rectangle.
+
+    * planar surfaces ([-2, 2]^2): faces_lo..faces_hi faces, each a batched-set
+      face (star outer loop with holes) scaled by U(0.35, 0.9) and moved to a
+      centre in U(-1.2, 1.2)^2; faces may overlap;
+    * every ``periodic_every``-th surface is a cylinder ([0, 2 pi) x [-pi, pi))
+      referenced by two faces of the periodic set (bands with open, noisy
+      loops);
+    * ``unreferenced`` extra faces at the end belong to no surface."""
+    face_loops, doms, pers = [], [], []
+    sfo, sff, pts, spo = [0], [], [], [0]
+    for s in range(num_surfaces):
+        rng = _face_rng(seed, s)
+        periodic = periodic_every > 0 and s % periodic_every == periodic_every - 1
+        if periodic:
+            for j in range(2):
+                loops, _, dom, per = config3_face(seed, 2 * (2 * s + j), queries=1)
+                sff.append(len(face_loops))
+                face_loops.append(loops)
+                doms.append(dom)
+                pers.append(list(per))
+            P = np.column_stack([rng.uniform(0, TWO_PI, points_per_surface),
+                                 rng.uniform(-np.pi, np.pi, points_per_surface)])
+        else:
+            k = int(rng.integers(faces_lo, faces_hi + 1))
+            for j in range(k):
+                loops, _, _ = config2_face(seed, 64 * s + j, q_lo=1, q_hi=1, near_frac=0.0, seg_hi=seg_hi)
+                scale = rng.uniform(0.35, 0.9)
+                c = rng.uniform(-1.2, 1.2, 2)
+                sff.append(len(face_loops))
+                face_loops.append([_moved(lp, scale, c) for lp in loops])
+                doms.append(DOMAIN_PLANE)
+                pers.append([0.0, 0.0])
+            P = rng.uniform(-2.0, 2.0, size=(points_per_surface, 2))
+        sfo.append(len(sff))
+        pts.append(P)
+        spo.append(spo[-1] + len(P))
+    for j in range(unreferenced):
+        loops, _, _ = config2_face(seed, 10 ** 6 + j, q_lo=1, q_hi=1, near_frac=0.0, seg_hi=seg_hi)
+        face_loops.append(loops)
+        doms.append(DOMAIN_PLANE)
+        pers.append([0.0, 0.0])
+    faces = _assemble(face_loops, doms, pers, rational=True)
+    P = np.concatenate(pts) if pts else np.zeros((0, 2))
+    return Patches(faces, np.asarray(sfo, dtype=np.int32), np.asarray(sff, dtype=np.int32),
+                   np.ascontiguousarray(P[:, 0]), np.ascontiguousarray(P[:, 1]), np.asarray(spo, dtype=np.int64))
+
+
+def tessellation_grids(faces: "Faces", n: int, margin: float = 0.05):
+    """One n x n grid per face (u0, v0, du, dv, nu, nv): the period cell of a
+    periodic face (cylinder [0, T_u) x [-pi, pi), torus [0, T_u) x [0, T_v),
+    as the periodic set lays them out), the control points' bounding box
+    widened by ``margin`` of its size for a planar face."""
+    grids = []
+    F = len(faces.face_loop_offsets) - 1
+    for f in range(F):
+        dom = int(faces.face_domain[f])
+        Tu, Tv = float(faces.face_period[2 * f]), float(faces.face_period[2 * f + 1])
+        if dom == DOMAIN_TORUS:
+            grids.append((0.0, 0.0, Tu / n, Tv / n, n, n))
+        elif dom == DOMAIN_CYLINDER_U:
+            grids.append((0.0, -np.pi, Tu / n, TWO_PI / n, n, n))
+        else:
+            l0, l1 = faces.face_loop_offsets[f], faces.face_loop_offsets[f + 1]
+            s0, s1 = faces.loop_seg_offsets[l0], faces.loop_seg_offsets[l1]
+            c0, c1 = faces.seg_cp_offsets[s0], faces.seg_cp_offsets[s1]
+            u, v = faces.cp_u[c0:c1], faces.cp_v[c0:c1]
+            w, h = u.max() - u.min(), v.max() - v.min()
+            u0, v0 = u.min() - margin * w, v.min() - margin * h
+            grids.append((float(u0), float(v0), (1 + 2 * margin) * w / n, (1 + 2 * margin) * h / n, n, n))
+    return grids
 
 
 # --------------------------------------------------------------------------
