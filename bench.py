@@ -147,6 +147,83 @@ def section_long_path(args):
     return out
 
 
+def _seg_counts(faces):
+    lso = np.asarray(faces.loop_seg_offsets)
+    flo = np.asarray(faces.face_loop_offsets)
+    return lso[flo[1:]] - lso[flo[:-1]]
+
+
+def section_tessellation(args):
+    """Tessellation driver (wn_classify_grid): the cell centres of a 128 x 128
+    grid over the period cell of each of the 512 periodic faces (8.4M
+    samples), generated on the device and classified."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    faces, _ = W.config3()
+    grids = W.tessellation_grids(faces, 128)
+    fs = wn.FaceSet(faces)
+    n = sum(g[4] * g[5] for g in grids)
+    pairs = int(np.sum(_seg_counts(faces) * np.array([g[4] * g[5] for g in grids])))
+    out = {"faces": faces.num_faces, "samples": n, "segment_pairs": pairs}
+    for name, sched in (("batched", 1),):
+        fs.classify_grid(grids, schedule=sched)
+        torch.cuda.synchronize()
+        reps = 5
+        prof = wn.Profile(64 * (reps + 1))
+        t = time.perf_counter()
+        for _ in range(reps):
+            u, v, w, lab = fs.classify_grid(grids, schedule=sched, profile=prof)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        k = {a: b / max(m, 1) for a, (m, b) in prof.collect().items()}
+        lab = lab.cpu().numpy()
+        out[name] = {"ms_per_call": ms, "samples_per_s": n / (ms / 1e3), "kernel_ms": k,
+                     "inside_fraction": float(np.mean(lab == 1))}
+    return out
+
+
+def section_multipatch(args):
+    """Multi-patch driver (wn_classify_surfaces): 128 base surfaces (every
+    fourth a cylinder with two periodic faces, the others planar with 2-6
+    trimmed faces) and 32,768 uniform samples per surface."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    p = W.brep_patches(num_surfaces=128, points_per_surface=32768)
+    fs = wn.FaceSet(p.faces)
+    dev = torch.device("cuda:0")
+    u, v = torch.from_numpy(p.u).to(dev), torch.from_numpy(p.v).to(dev)
+    spo = p.surface_point_offsets
+    nps = np.diff(spo)
+    segs = _seg_counts(p.faces)
+    copies, pairs = 0, 0
+    for s in range(p.num_surfaces):
+        fl = p.surface_faces[p.surface_face_offsets[s]:p.surface_face_offsets[s + 1]]
+        copies += int(nps[s]) * len(fl)
+        pairs += int(nps[s]) * int(segs[fl].sum())
+    out = {"surfaces": p.num_surfaces, "faces": p.faces.num_faces, "points": int(spo[-1]), "face_copies": copies,
+           "segment_pairs": pairs}
+    fs.classify_surfaces(p.surface_face_offsets, p.surface_faces, u, v, spo)
+    torch.cuda.synchronize()
+    reps = 5
+    prof = wn.Profile(64 * (reps + 1))
+    t = time.perf_counter()
+    for _ in range(reps):
+        lab, face = fs.classify_surfaces(p.surface_face_offsets, p.surface_faces, u, v, spo, profile=prof)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    k = {a: b / max(m, 1) for a, (m, b) in prof.collect().items()}
+    lab = lab.cpu().numpy()
+    out["batched"] = {"ms_per_call": ms, "points_per_s": int(spo[-1]) / (ms / 1e3), "kernel_ms": k,
+                      "inside_fraction": float(np.mean(lab == 1))}
+    return out
+
+
 def section_config3(args):
     """512 periodic faces (cylinder / torus), 2^20 points."""
     import torch
@@ -388,7 +465,8 @@ def main():
     sections = {}
     if not args.no_extra:
         for name, fn in (("config1", section_config1), ("long_path", section_long_path), ("config3", section_config3),
-                         ("config4", section_config4), ("config5", section_config5)):
+                         ("config4", section_config4), ("config5", section_config5),
+                         ("tessellation", section_tessellation), ("multipatch", section_multipatch)):
             t = time.time()
             try:
                 sections[name] = fn(args)

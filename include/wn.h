@@ -260,6 +260,59 @@ wn_status wn_nurbs_to_bezier(int32_t degree, int32_t num_cps, const double* knot
                              const double* cp_v, const double* cp_w, int64_t out_cap, double* out_u, double* out_v,
                              double* out_w, int32_t* out_segments);
 
+/* Applications of Sec. 5.4 on the same query pipeline. */
+
+/* A uniform grid over a face's parameter rectangle: nu x nv cells of size
+ * du x dv whose lower-left corner is (u0, v0). */
+typedef struct {
+    double u0, v0; /* lower-left corner (finite)                 */
+    double du, dv; /* cell size (finite, > 0)                    */
+    int32_t nu, nv; /* cells along u and along v (>= 0)           */
+} wn_grid;
+
+/* Tessellation driver (Sec. 5.4.3: the sample points of a uniform grid in
+ * the parameter domain are classified so that the cells outside the trimmed
+ * region can be removed, periodic faces included).  Classifies the cell
+ * centres of grids[f] against face f for every face.
+ *   grids        host [num_faces]; the total number of cells must be < 2^31 - 1
+ *   samples      face by face, row-major inside a face (i along u fastest):
+ *                cell (i, j) of face f is sample sum_{g<f} nu_g nv_g + j nu_f + i,
+ *                at u = u0 + (i + 0.5) du, v = v0 + (j + 0.5) dv, the product and
+ *                the sum each rounded once (no fused multiply-add)
+ *   out_u, out_v device double [samples], receive the sample coordinates; if
+ *                either is NULL the library stages them in its own memory
+ *   out_winding, out_inside  device [samples], as in wn_query (either may be NULL)
+ *   q            per-call overrides as in wn_query_ex (may be NULL)
+ * Uploads the grid table and synchronizes `stream` once before launching
+ * anything; the rest is asynchronous on `stream` (staging freed
+ * stream-ordered).  WN_E_INVALID for malformed grids, WN_E_NOMEM when the
+ * staging memory cannot be allocated, otherwise as wn_query_ex. */
+wn_status wn_classify_grid(const wn_faces* faces, const wn_grid* grids, double* out_u, double* out_v,
+                           double* out_winding, uint8_t* out_inside, const wn_query_opts* q, void* stream);
+
+/* Multi-patch classification (Sec. 5.4.1: a point sampled on a base surface
+ * is inside when it lies inside any trimmed face that references the
+ * surface).  Surface s is referenced by the faces
+ * surface_faces[surface_face_offsets[s] .. surface_face_offsets[s+1]) (host
+ * arrays; each face belongs to at most one surface; faces of no surface are
+ * not queried).  `points` holds the sample points grouped by SURFACE: its
+ * offsets have num_surfaces + 1 entries and the host copy
+ * (face_point_offsets_host) is required.
+ *   out_inside   device uint8 [num_points] or NULL: WN_INSIDE if some face of
+ *                the point's surface labels it inside, else WN_ON_BOUNDARY if
+ *                some face does, else WN_INVALID_POINT for invalid coordinates,
+ *                else WN_OUTSIDE (also for every point of a surface with no face)
+ *   out_face     device int32 [num_points] or NULL: the first face in the
+ *                surface's list that labels the point inside, or -1
+ * The points are copied once per referencing face (face-major staging of
+ * 17 bytes per copy; copies in total < 2^31 - 1) and queried in one call.
+ * Uploads the tables and synchronizes `stream` once before launching
+ * anything; the rest is asynchronous on `stream`.  WN_E_INVALID for
+ * malformed tables, otherwise as wn_classify_grid. */
+wn_status wn_classify_surfaces(const wn_faces* faces, int32_t num_surfaces, const int32_t* surface_face_offsets,
+                               const int32_t* surface_faces, const wn_points* points, uint8_t* out_inside,
+                               int32_t* out_face, const wn_query_opts* q, void* stream);
+
 /* Create a profile able to time `capacity` kernel launches (events are
  * created here, on the current device).  Timing a launch beyond the capacity
  * is skipped silently. */

@@ -28,6 +28,7 @@ EXPORTS = [
     "wn_predictor_create", "wn_predictor_destroy", "wn_predictor_train", "wn_predictor_get_params",
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
     "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy", "wn_nurbs_to_bezier",
+    "wn_classify_grid", "wn_classify_surfaces",
 ]
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -58,6 +59,11 @@ class wn_options(ctypes.Structure):
 class wn_points(ctypes.Structure):
     _fields_ = [("num_points", ctypes.c_int64), ("u", _P), ("v", _P), ("stride", ctypes.c_int64),
                 ("face_point_offsets", _P), ("face_point_offsets_host", _P)]
+
+
+class wn_grid(ctypes.Structure):
+    _fields_ = [("u0", ctypes.c_double), ("v0", ctypes.c_double), ("du", ctypes.c_double), ("dv", ctypes.c_double),
+                ("nu", ctypes.c_int32), ("nv", ctypes.c_int32)]
 
 
 class wn_query_opts(ctypes.Structure):
@@ -148,6 +154,11 @@ def lib():
         L.wn_plan_autotune.restype = ctypes.c_int
         L.wn_plan_autotune.argtypes = [_P, ctypes.c_int32, _P, _P]
         L.wn_plan_destroy.argtypes = [_P]
+        L.wn_classify_grid.restype = ctypes.c_int
+        L.wn_classify_grid.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.POINTER(wn_query_opts), _P]
+        L.wn_classify_surfaces.restype = ctypes.c_int
+        L.wn_classify_surfaces.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(wn_points), _P, _P,
+                                           ctypes.POINTER(wn_query_opts), _P]
         L.wn_get_faces_info.restype = ctypes.c_int
         L.wn_get_faces_info.argtypes = [_P, ctypes.POINTER(wn_faces_info)]
         _lib = L
@@ -318,28 +329,84 @@ class FaceSet:
         if offsets_host is not None:
             hoffs = np.ascontiguousarray(offsets_host, dtype=np.int64)
         p = wn_points(n, u.data_ptr(), v.data_ptr(), stride, offsets.data_ptr(), _np_ptr(hoffs))
-        q = wn_query_opts()
-        lib().wn_default_query_opts(ctypes.byref(q))
-        if schedule is not None:
-            q.schedule = schedule
-        if precision is not None:
-            q.precision = precision
-        if rule is not None:
-            q.rule = rule
-        q.queries_per_wg = queries_per_wg
-        q.queue_policy = queue_policy
-        q.near_capacity = near_capacity
-        q.depth_log = None if depth_log is None else depth_log.data_ptr()
-        q.profile = None if profile is None else profile.handle
-        q.stats = None if stats is None else stats.data_ptr()
-        q.predictor = None if predictor is None else predictor.handle
-        q.bin_source = bin_source
-        q.path_hierarchy = path_hierarchy
+        q = _query_opts(schedule=schedule, precision=precision, rule=rule, queries_per_wg=queries_per_wg,
+                        queue_policy=queue_policy, near_capacity=near_capacity, depth_log=depth_log, profile=profile,
+                        stats=stats, predictor=predictor, bin_source=bin_source, path_hierarchy=path_hierarchy)
         st = lib().wn_query_ex(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
                                _stream_ptr(stream))
         if st != WN_OK:
             raise WnError(st, "wn_query_ex")
         return out_w, out_lab
+
+    def classify_grid(self, grids, *, out_uv: bool = True, stream=None, **opts):
+        """Tessellation driver: classify the cell centres of one uniform grid
+        per face.  ``grids`` is a sequence of (u0, v0, du, dv, nu, nv), one per
+        face.  Returns (u, v, omega, label) torch tensors over all cells, face
+        by face and row-major inside a face (u and v are None when
+        ``out_uv`` is false)."""
+        import torch
+
+        assert len(grids) == self.num_faces
+        g = (wn_grid * self.num_faces)(*[wn_grid(float(a), float(b), float(c), float(d), int(e), int(f))
+                                         for a, b, c, d, e, f in grids])
+        n = sum(max(int(e), 0) * max(int(f), 0) for _, _, _, _, e, f in grids)  # the library validates
+        dev = torch.device("cuda", torch.cuda.current_device())
+        u = torch.empty(n, dtype=torch.float64, device=dev) if out_uv else None
+        v = torch.empty(n, dtype=torch.float64, device=dev) if out_uv else None
+        w = torch.empty(n, dtype=torch.float64, device=dev)
+        lab = torch.empty(n, dtype=torch.uint8, device=dev)
+        q = _query_opts(**opts)
+        st = lib().wn_classify_grid(self._h, ctypes.cast(g, _P), None if u is None else u.data_ptr(),
+                                    None if v is None else v.data_ptr(), w.data_ptr(), lab.data_ptr(),
+                                    ctypes.byref(q), _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_classify_grid")
+        return u, v, w, lab
+
+    def classify_surfaces(self, surface_face_offsets, surface_faces, u, v, surface_point_offsets, *, stride: int = 1,
+                          stream=None, **opts):
+        """Multi-patch classification: points on base surfaces (grouped by
+        surface; host offsets) against every face that references their
+        surface.  Returns (label uint8, first inside face int32) tensors."""
+        import torch
+
+        sfo = np.ascontiguousarray(surface_face_offsets, dtype=np.int32)
+        sff = np.ascontiguousarray(surface_faces, dtype=np.int32)
+        hoffs = np.ascontiguousarray(surface_point_offsets, dtype=np.int64)
+        offs = torch.from_numpy(hoffs).to(u.device)
+        n = int(hoffs[-1])
+        lab = torch.empty(n, dtype=torch.uint8, device=u.device)
+        face = torch.empty(n, dtype=torch.int32, device=u.device)
+        p = wn_points(n, u.data_ptr(), v.data_ptr(), stride, offs.data_ptr(), _np_ptr(hoffs))
+        q = _query_opts(**opts)
+        st = lib().wn_classify_surfaces(self._h, len(sfo) - 1, _np_ptr(sfo), _np_ptr(sff), ctypes.byref(p),
+                                        lab.data_ptr(), face.data_ptr(), ctypes.byref(q), _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_classify_surfaces")
+        return lab, face
+
+
+def _query_opts(schedule=None, precision=None, rule=None, queries_per_wg=0, queue_policy=0, near_capacity=0,
+                depth_log=None, profile=None, stats=None, predictor=None, bin_source=0, path_hierarchy=0):
+    """wn_query_opts from keyword overrides (None / 0 = default)."""
+    q = wn_query_opts()
+    lib().wn_default_query_opts(ctypes.byref(q))
+    if schedule is not None:
+        q.schedule = schedule
+    if precision is not None:
+        q.precision = precision
+    if rule is not None:
+        q.rule = rule
+    q.queries_per_wg = queries_per_wg
+    q.queue_policy = queue_policy
+    q.near_capacity = near_capacity
+    q.depth_log = None if depth_log is None else depth_log.data_ptr()
+    q.profile = None if profile is None else profile.handle
+    q.stats = None if stats is None else stats.data_ptr()
+    q.predictor = None if predictor is None else predictor.handle
+    q.bin_source = bin_source
+    q.path_hierarchy = path_hierarchy
+    return q
 
 
 def _points(u, v, offsets, stride=1, n=None):
