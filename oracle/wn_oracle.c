@@ -26,6 +26,7 @@
  * widening invariants.  parity unpinned: the pairing of wavy loops whose
  * normal ranges interleave (checked only through the 0/1 postcondition).
  */
+#include <limits.h>
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>

@@ -33,6 +33,8 @@ import numpy as np
 DOMAIN_PLANE = 0
 DOMAIN_CYLINDER_U = 1
 DOMAIN_TORUS = 2
+DOMAIN_SPHERE_U = 3  # periodic in u, poles at both ends of v (punctured)
+DOMAIN_CONE_U = 4  # periodic in u, apex at one end of v (punctured)
 
 SEED_C1 = 1
 SEED_C2 = 2
@@ -601,6 +603,63 @@ def config3(seed: int = SEED_C3, num_faces: int = 512, face_ids: Optional[Sequen
     face_loops, pts_all, doms, pers, offs = [], [], [], [], [0]
     for f in ids:
         loops, pts, dom, per = config3_face(seed, f, **kw)
+        face_loops.append(loops)
+        pts_all.append(pts)
+        doms.append(dom)
+        pers.append(per)
+        offs.append(offs[-1] + len(pts))
+    faces = _assemble(face_loops, doms, pers, rational=False)
+    P = np.concatenate(pts_all)
+    q = Queries(u=np.ascontiguousarray(P[:, 0]), v=np.ascontiguousarray(P[:, 1]),
+                face_point_offsets=np.asarray(offs, dtype=np.int64))
+    return faces, q
+
+
+# --------------------------------------------------------------------------
+# Sphere- and cone-like faces (Sec. 4.3: the singular points are punctured)
+# --------------------------------------------------------------------------
+SEED_SPHERE = 7
+
+
+def sphere_face(seed: int, f: int, queries: int = 2048, open_frac: float = 0.2, gap=(1e-4, 1e-2),
+                sigma: float = 1e-5, seg_lo: int = 16, seg_hi: int = 64):
+    """Face f of a sphere/cone set: cell [0, 2pi) x [-pi/2, pi/2], periodic
+    in u, even f sphere (poles at v = -+pi/2), odd f cone (apex at v = -pi/2).
+    The face is one of: a cap above a +u loop, a cap below a -u loop (a cone's
+    apex region), a band, or both caps (spheres only); loops are wavy
+    (amplitude <= 0.12), at least 0.5 apart in height, opened and perturbed
+    like the periodic set; half of the faces get a contractible star hole in
+    their inside region."""
+    rng = _face_rng(seed, f)
+    T = TWO_PI
+    domain = DOMAIN_SPHERE_U if f % 2 == 0 else DOMAIN_CONE_U
+    kinds = ["cap_up", "cap_down", "band", "both"] if domain == DOMAIN_SPHERE_U else ["cap_down", "band"]
+    kind = kinds[int(rng.integers(0, len(kinds)))]
+    c1 = rng.uniform(-0.9, -0.1)
+    c2 = c1 + rng.uniform(0.5, 1.0)
+    specs = {"cap_up": [(c1, +1)], "cap_down": [(c2, -1)], "band": [(c1, +1), (c2, -1)],
+             "both": [(c1, -1), (c2, +1)]}[kind]
+    loops = []
+    for c, d in specs:
+        cv = WrappedCurve((rng.uniform(0, T), c), (d * T, 0.0), rng.uniform(0.02, 0.12), rng)
+        lp = periodic_loop(cv, int(rng.integers(seg_lo, seg_hi + 1)), (T, T), (0,))
+        _open_and_noise(lp, rng, rng.uniform() < open_frac, gap[0], gap[1], sigma)
+        loops.append(lp)
+    if rng.uniform() < 0.5:
+        # a clockwise star hole inside the face's inside region
+        vc = {"cap_up": c1 + 0.45, "cap_down": c2 - 0.45, "band": 0.5 * (c1 + c2), "both": c2 + 0.45}[kind]
+        hc = StarCurve(rng, rho=0.08, center=(rng.uniform(0.5, T - 0.5), vc))
+        ns = int(rng.integers(6, 17))
+        loops.append(reverse_loop(sampled_star_loop(hc, ns, rng.integers(1, 4, ns))))
+    pts = np.column_stack([rng.uniform(0, T, queries), rng.uniform(-0.5 * np.pi, 0.5 * np.pi, queries)])
+    return loops, pts, domain, (T, 0.0)
+
+
+def sphere_set(seed: int = SEED_SPHERE, num_faces: int = 64, face_ids: Optional[Sequence[int]] = None, **kw):
+    ids = list(range(num_faces)) if face_ids is None else list(face_ids)
+    face_loops, pts_all, doms, pers, offs = [], [], [], [], [0]
+    for f in ids:
+        loops, pts, dom, per = sphere_face(seed, f, **kw)
         face_loops.append(loops)
         pts_all.append(pts)
         doms.append(dom)

@@ -195,3 +195,65 @@ def test_topology_errors(oracle_lib):
     f2 = _face([(b, 9), (c, 9)], W.DOMAIN_TORUS)  # gcd(2, 4) = 2
     with pytest.raises(oracle_lib.OracleError):
         _eval(oracle_lib, f2, [[1.0, 1.0]])
+
+
+# -- punctured sphere / cone (Sec. 4.3) -----------------------------------------
+def _polyline_loop(us, vs):
+    """Degree-1 segments through (us[k], vs[k]); the last vertex is the first
+    translated by (+-T, 0), so the loop wraps once around u."""
+    return [(np.array([[us[k], vs[k]], [us[k + 1], vs[k + 1]]]), None) for k in range(len(us) - 1)]
+
+
+def _latitude(c, direction, n=5):
+    u = np.linspace(0.0, T, n + 1) if direction > 0 else np.linspace(T, 0.0, n + 1)
+    return _polyline_loop(u, np.full(n + 1, c)), (lambda uu: np.full_like(uu, c))
+
+
+def _zigzag(c, direction, K=8, amp=0.2):
+    k = np.arange(K + 1)
+    u = T * k / K if direction > 0 else T * (K - k) / K
+    v = c + amp * (-1.0) ** k
+    uu, vv = (u, v) if direction > 0 else (u[::-1], v[::-1])
+    return _polyline_loop(u, v), (lambda x: np.interp(np.mod(x, T), uu, vv))
+
+
+@pytest.mark.parametrize("domain", [3, 4])
+def test_punctured_sphere_closed_forms(oracle_lib, domain):
+    """Loops around the poles of a sphere (around the apex of a cone): a cap
+    above a +u loop, a cap below a -u loop, a band, both caps (the band's
+    complement), a zigzag cap and a cap with a clockwise square hole.  Each
+    label follows from comparing v with the loops' heights at u."""
+    rng = np.random.default_rng(31 + domain)
+    P = np.column_stack([rng.uniform(-T, 2 * T, 4000), rng.uniform(-1.5, 1.5, 4000)])
+    hole = _polyline_loop(np.array([2.0, 2.0, 2.6, 2.6, 2.0]), np.array([0.9, 1.3, 1.3, 0.9, 0.9]))
+    in_hole = (np.mod(P[:, 0], T) > 2.0) & (np.mod(P[:, 0], T) < 2.6) & (P[:, 1] > 0.9) & (P[:, 1] < 1.3)
+    cases = []
+    up, f_up = _latitude(0.3, +1)
+    cases.append(([up], lambda u, v: v > f_up(u)))
+    dn, f_dn = _latitude(0.3, -1)
+    cases.append(([dn], lambda u, v: v < f_dn(u)))
+    lo, f_lo = _latitude(-0.5, +1)
+    hi, f_hi = _latitude(0.4, -1)
+    cases.append(([lo, hi], lambda u, v: (v > f_lo(u)) & (v < f_hi(u))))
+    lo2, _ = _latitude(-0.5, -1)
+    hi2, _ = _latitude(0.4, +1)
+    cases.append(([hi2, lo2], lambda u, v: (v < -0.5) | (v > 0.4)))
+    zz, f_zz = _zigzag(-0.1, +1)
+    cases.append(([zz], lambda u, v: v > f_zz(u)))
+    cases.append(([up, hole], lambda u, v: (v > 0.3) & ~in_hole))
+    for loops, want_fn in cases:
+        f = W.faces_from_loops([loops], domains=[domain], periods=[[T, 0.0]])
+        want = want_fn(P[:, 0], P[:, 1]).astype(float)
+        w, near = _eval(oracle_lib, f, P)
+        clear = near == 0
+        assert clear.mean() > 0.99
+        np.testing.assert_allclose(w[clear], want[clear], rtol=0, atol=1e-12)
+
+
+def test_punctured_sphere_inconsistent_face(oracle_lib):
+    """Two loops both running +u: the regions' constants span two units."""
+    a, _ = _latitude(-0.5, +1)
+    b, _ = _latitude(0.4, +1)
+    f = W.faces_from_loops([[a, b]], domains=[3], periods=[[T, 0.0]])
+    with pytest.raises(oracle_lib.OracleError):
+        _eval(oracle_lib, f, [[1.0, 0.0]])
