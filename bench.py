@@ -153,6 +153,22 @@ def _seg_counts(faces):
     return lso[flo[1:]] - lso[flo[:-1]]
 
 
+def section_spheres(args):
+    """512 sphere- and cone-like faces (punctured, u-periodic), 2^20 points."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    faces, q = W.sphere_set(num_faces=512)
+    fs = wn.FaceSet(faces)
+    tens = _dev_queries(torch, q)
+    out = {"faces": faces.num_faces, "segments": faces.num_segments, "points": q.num_points}
+    ms, k = _time_query(torch, fs, tens, q.face_point_offsets, 10, schedule=1)
+    out["batched"] = {"ms_per_step": ms, "queries_per_s": q.num_points / (ms / 1e3), "kernel_ms": k}
+    return out
+
+
 def section_tessellation(args):
     """Tessellation driver (wn_classify_grid): the cell centres of a 128 x 128
     grid over the period cell of each of the 512 periodic faces (8.4M
@@ -466,7 +482,8 @@ def main():
     if not args.no_extra:
         for name, fn in (("config1", section_config1), ("long_path", section_long_path), ("config3", section_config3),
                          ("config4", section_config4), ("config5", section_config5),
-                         ("tessellation", section_tessellation), ("multipatch", section_multipatch)):
+                         ("spheres", section_spheres), ("tessellation", section_tessellation),
+                         ("multipatch", section_multipatch)):
             t = time.time()
             try:
                 sections[name] = fn(args)

@@ -48,7 +48,19 @@ typedef enum {
 typedef enum {
     WN_DOMAIN_PLANE = 0,      /* simply connected rectangle                  */
     WN_DOMAIN_CYLINDER_U = 1, /* periodic in u with period T_u (uni-periodic)  */
-    WN_DOMAIN_TORUS = 2       /* periodic in u and v (bi-periodic)             */
+    WN_DOMAIN_TORUS = 2,      /* periodic in u and v (bi-periodic)             */
+    /* Sphere- and cone-like: periodic in u with singular points (poles, apex)
+     * at the ends of the v range.  The singular points are punctured, which
+     * leaves the cylinder case (Sec. 4.3): loops that run around a pole are
+     * non-contractible (h = (+-1, 0)) and no pole edge is given.  The face's
+     * winding number is the cylinder's plus one constant c per face, chosen
+     * so that every region between the non-contractible loops gets 0 or 1:
+     * c = S/2 - m, S the sum of their h_u and m the least partial sum of
+     * their h_u taken from the lowest loop up (a cap around one pole:
+     * c = 1/2; a band: c = 0; both caps: c = 1).  A face whose regions would
+     * span more than one unit is WN_E_TOPOLOGY. */
+    WN_DOMAIN_SPHERE_U = 3,
+    WN_DOMAIN_CONE_U = 4
 } wn_domain;
 
 /* Arithmetic of the root ellipse test of planar faces (Alg. 1; the

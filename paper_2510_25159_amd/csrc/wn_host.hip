@@ -152,7 +152,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     int32_t nper = 0;
     for (int32_t f = 0; f < F; ++f) {
         dom[f] = d->face_domain ? d->face_domain[f] : WN_DOMAIN_PLANE;
-        if (dom[f] < WN_DOMAIN_PLANE || dom[f] > WN_DOMAIN_TORUS) return WN_E_INVALID;
+        if (dom[f] < WN_DOMAIN_PLANE || dom[f] > WN_DOMAIN_CONE_U) return WN_E_INVALID;
         if (dom[f] != WN_DOMAIN_PLANE) {
             if (!d->face_period) return WN_E_INVALID;
             const double Tu = d->face_period[2 * f], Tv = d->face_period[2 * f + 1];

@@ -122,7 +122,11 @@ struct PFace {
     double Tu, Tv;             // periods
     double t1x, t1y;           // family step t_1 (torus)
     double Delta, nx, ny;      // family spacing and left normal of h* (T_u, T_v) (torus)
+    double offset;             // constant added to the winding number (punctured sphere / cone), turns
 };
+
+// Domains periodic in u only: the cylinder and the punctured sphere / cone.
+inline __host__ __device__ bool u_periodic_only(int dom) { return dom == 1 || dom == 3 || dom == 4; }
 
 struct PerTab {
     const PLoop* loop;   // [L]

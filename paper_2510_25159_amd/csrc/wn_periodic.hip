@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
         }
         if constexpr (MODE == kPerQueue) flush_near_per(W, P);
         if (active) {
-            out.w[P.qi] = turn_angle(P.T) + kTwoPi * (double)P.xc;
+            out.w[P.qi] = turn_angle(P.T) + kTwoPi * ((double)P.xc + pf.offset);
             out.lab[P.qi] = !P.valid ? 3 : (P.onb ? 2 : (P.lost ? kRedo : 0));
         }
     }

@@ -83,6 +83,59 @@ void loop_point(const std::vector<HostSeg>& segs, const PLoop& L, double& x, dou
     y = g.y[0];
 }
 
+// Mean height of the extended curve of a non-contractible loop over one
+// copy: the integral of v du along the lifted loop (its segments sampled as
+// polylines) over the copy's u extent.  Two extended curves that do not
+// cross are ordered by it (their difference is the area between them).
+double mean_height(const std::vector<HostSeg>& segs, const PLoop& L) {
+    constexpr int kSamples = 64;
+    double I = 0.0;
+    for (int s = L.s0; s < L.s1; ++s) {
+        const HostSeg& g = segs[s];
+        double px = g.x[0], py = g.y[0];
+        for (int k = 1; k <= kSamples; ++k) {
+            double x, y;
+            if (k == kSamples) {
+                x = g.x[g.n];
+                y = g.y[g.n];
+            } else {
+                hseg_eval(g, (double)k / kSamples, x, y);
+            }
+            I += 0.5 * (py + y) * (x - px);
+            px = x;
+            py = y;
+        }
+    }
+    return I / L.vx;
+}
+
+// Punctured sphere / cone (Sec. 4.3: puncturing the singular points leaves
+// the cylinder case).  On the cylinder each extended curve adds +1/2 on its
+// left and -1/2 on its right, so from below all of them the winding number
+// steps by +1 across a loop running in +u and by -1 across one running in -u:
+// region k gets -S/2 + p_k, p_k the partial sums of sign(h_u) in height
+// order.  The constant c = S/2 - min_k p_k maps the regions to {0, 1}; a
+// spread of more than one unit is no valid face (returns 1).
+int puncture_offset(const std::vector<HostSeg>& segs, const std::vector<PLoop>& loops, int l0, int l1,
+                    double& c) {
+    std::vector<std::pair<double, int>> hs;
+    for (int l = l0; l < l1; ++l) {
+        const PLoop& L = loops[l];
+        if (L.s1 == L.s0 || L.h0 == 0) continue;
+        hs.push_back({mean_height(segs, L), L.h0 > 0 ? 1 : -1});
+    }
+    std::sort(hs.begin(), hs.end());
+    int p = 0, lo = 0, hi = 0;
+    for (const auto& e : hs) {
+        p += e.second;
+        lo = std::min(lo, p);
+        hi = std::max(hi, p);
+    }
+    if (hi - lo > 1) return 1;
+    c = 0.5 * (double)p - (double)lo;
+    return 0;
+}
+
 long gcd_l(long a, long b) {
     a = a < 0 ? -a : a;
     b = b < 0 ? -b : b;
@@ -146,7 +199,7 @@ int build_periodic_face(int dom, double Tu, double Tv, int l0, int l1, const std
             U.kind = kUnitContractible;
             U.la = l;
             units.push_back(U);
-        } else if (dom == 1) {
+        } else if (u_periodic_only(dom)) {
             if (hs0 > 1) return 1;  // a simple loop on a cylinder has |h| <= 1
             PUnit U{};
             U.kind = kUnitExtended;
@@ -154,6 +207,7 @@ int build_periodic_face(int dom, double Tu, double Tv, int l0, int l1, const std
             units.push_back(U);
         }
     }
+    if ((dom == 3 || dom == 4) && puncture_offset(segs, loops, l0, l1, pf.offset) != 0) return 1;
     if (dom == 2 && (hs0 != 0 || hs1 != 0)) {
         if (gcd_l(hs0, hs1) != 1) return 1;
         std::vector<int> A, B;

@@ -15,7 +15,7 @@ import numpy as np
 from .build import LIB
 
 WN_OK, WN_E_INVALID, WN_E_NOMEM, WN_E_DEVICE, WN_E_TOPOLOGY, WN_E_DEPTH, WN_E_UNSUPPORTED = range(7)
-PLANE, CYLINDER_U, TORUS = 0, 1, 2
+PLANE, CYLINDER_U, TORUS, SPHERE_U, CONE_U = 0, 1, 2, 3, 4
 PREC_FP64, PREC_MIXED = 0, 1
 RULE_NONZERO, RULE_POSITIVE = 0, 1
 SCHED_PLAIN, SCHED_BATCHED, SCHED_BINNED = 0, 1, 2

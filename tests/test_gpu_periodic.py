@@ -172,3 +172,41 @@ def test_mixed_loop_kinds_and_two_torus_pairs(torch_cuda, oracle_lib):
         w, lab = run_wn(faces, q, schedule=sched)
         st = compare(w, lab, w_o, n_o)
         assert st["compared"] > 0.98 * q.num_points
+
+
+@pytest.fixture(scope="module")
+def spheres(oracle_lib):
+    f, q = W.sphere_set(num_faces=24)
+    w, n = oracle_lib.query_faces(f, q)
+    return f, q, w, n
+
+
+@pytest.mark.parametrize("schedule,policy", [(1, 0), (0, 0), (1, 2)])
+def test_punctured_sphere_and_cone_parity(torch_cuda, spheres, schedule, policy):
+    """Sphere- and cone-like faces (caps, bands, both caps, holes; open and
+    perturbed loops) against the oracle: the punctured cylinder case plus the
+    per-face constant (found by the library from the loops' mean heights, by
+    the oracle from a scan of the extended curves)."""
+    f, q, w_o, n_o = spheres
+    print(f"spheres[0:24] schedule={schedule} policy={policy} points={q.num_points}", flush=True)
+    w, lab = run_wn(f, q, schedule=schedule, queue_policy=policy)
+    st = compare(w, lab, w_o, n_o)
+    assert st["compared"] > 0.99 * q.num_points
+    assert 0.2 < np.mean(lab == 1) < 0.8
+
+
+def test_punctured_sphere_topology_error(torch_cuda):
+    """Two loops running +u on a sphere: no valid face (the regions' values
+    would span two units)."""
+    from paper_2510_25159_amd import wn
+
+    rng = np.random.default_rng(2)
+    loops = []
+    for c in (-0.5, 0.4):
+        cv = W.WrappedCurve((0.3, c), (2 * np.pi, 0.0), 0.05, rng)
+        lp = W.periodic_loop(cv, 9, (2 * np.pi, 2 * np.pi), (0,))
+        loops.append([(cp, None) for cp in lp.cps])
+    f = W.faces_from_loops([loops], domains=[W.DOMAIN_SPHERE_U], periods=[[2 * np.pi, 0.0]])
+    with pytest.raises(wn.WnError) as e:
+        wn.FaceSet(f)
+    assert e.value.status == wn.WN_E_TOPOLOGY
