@@ -97,3 +97,32 @@ def test_split_rejects_malformed(wnlib):
             wnlib.nurbs_to_bezier(p, knots, c)
     with pytest.raises(wnlib.WnError):
         wnlib.nurbs_to_bezier(2, CIRCLE_KNOTS, CIRCLE_CP, [1, 1, 1, 1, -1, 1, 1, 1, 1])  # weight <= 0
+
+
+def test_oracle_span_interpolation():
+    """The oracle's own span split (interpolation of the homogeneous curve)
+    reproduces the curve: each segment's points equal nurbs_point on its span,
+    the circle's segments lie on the unit circle, and a single-span curve
+    returns its own control points."""
+    rng = np.random.default_rng(9)
+    for p in range(1, 6):
+        for rational in (True, False):
+            knots, cp, w = random_nurbs(rng, p, rational)
+            U = np.asarray(knots)
+            spans = [(U[k], U[k + 1]) for k in range(p, len(U) - p - 1) if U[k + 1] > U[k]]
+            segs = O.spans_to_bezier(knots, p, cp, w)
+            assert len(segs) == len(spans)
+            for (a, b), (scp, sw) in zip(spans, segs):
+                for t in np.linspace(0, 1, 9):
+                    x = O.bezier_point(scp, sw, t)
+                    tt = a + (b - a) * t
+                    y = O.nurbs_point(knots, p, cp, w, min(tt, np.nextafter(b, a)) if tt >= b and b < 1 else tt)
+                    assert np.allclose(x, y, rtol=0, atol=1e-11), (p, rational, a, b, t)
+    for scp, sw in O.spans_to_bezier(CIRCLE_KNOTS, 2, CIRCLE_CP, CIRCLE_W):
+        for t in np.linspace(0, 1, 17):
+            assert abs(np.hypot(*O.bezier_point(scp, sw, t)) - 1.0) < 1e-13
+    single = [0.0] * 4 + [1.0] * 4
+    cp = rng.uniform(-1, 1, (4, 2))
+    w = rng.uniform(0.5, 2, 4)
+    (scp, sw), = O.spans_to_bezier(single, 3, cp, w)
+    assert np.allclose(scp, cp, atol=1e-13) and np.allclose(sw, w, atol=1e-13)
