@@ -325,6 +325,40 @@ wn_status wn_classify_surfaces(const wn_faces* faces, int32_t num_surfaces, cons
                                const int32_t* surface_faces, const wn_points* points, uint8_t* out_inside,
                                int32_t* out_face, const wn_query_opts* q, void* stream);
 
+/* Faces whose loops are chains of NURBS p-curves (Sec. 3.1: B-Rep trimming
+ * curves are NURBS; they subdivide into Bezier segments).  All pointers HOST.
+ *   face_loop_offsets  [num_faces+1]  faces -> loops
+ *   loop_curve_offsets [num_loops+1]  loops -> ordered curves
+ *   curve_degree       [num_curves]   1..5
+ *   curve_cp_offsets   [num_curves+1] curves -> control points (int64)
+ *   knots              the curves' clamped knot vectors back to back: curve c
+ *                      owns (cp count + degree + 1) entries, starting where
+ *                      curve c-1's end
+ *   cp_u, cp_v         control points; cp_w weights or NULL (non-rational)
+ *   face_domain, face_period  as in wn_faces_desc */
+typedef struct {
+    int32_t num_faces;
+    int32_t num_loops;
+    int32_t num_curves;
+    const int32_t* face_loop_offsets;
+    const int32_t* loop_curve_offsets;
+    const int32_t* curve_degree;
+    const int64_t* curve_cp_offsets;
+    const double* knots;
+    const double* cp_u;
+    const double* cp_v;
+    const double* cp_w;
+    const int32_t* face_domain;
+    const double* face_period;
+} wn_nurbs_faces_desc;
+
+/* wn_create_faces for NURBS loops: every curve is split into Bezier segments
+ * by wn_nurbs_to_bezier (knot insertion), in order, and the segments replace
+ * the curve in its loop; then as wn_create_faces.  WN_E_INVALID for
+ * malformed tables or curves (the conditions of wn_nurbs_to_bezier). */
+wn_status wn_create_faces_nurbs(const wn_nurbs_faces_desc* desc, const wn_options* opt, void* stream,
+                                wn_faces** out);
+
 /* Create a profile able to time `capacity` kernel launches (events are
  * created here, on the current device).  Timing a launch beyond the capacity
  * is skipped silently. */

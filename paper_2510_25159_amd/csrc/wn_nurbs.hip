@@ -85,3 +85,63 @@ extern "C" wn_status wn_nurbs_to_bezier(int32_t degree, int32_t num_cps, const d
     }
     return WN_OK;
 }
+
+extern "C" wn_status wn_create_faces_nurbs(const wn_nurbs_faces_desc* d, const wn_options* opt, void* stream,
+                                           wn_faces** out) {
+    if (!d || !out || d->num_faces < 0 || d->num_loops < 0 || d->num_curves < 0 || !d->face_loop_offsets ||
+        !d->loop_curve_offsets || (d->num_curves > 0 && (!d->curve_degree || !d->curve_cp_offsets || !d->knots ||
+                                                         !d->cp_u || !d->cp_v)))
+        return WN_E_INVALID;
+    const int32_t F = d->num_faces, L = d->num_loops, C = d->num_curves;
+    if (d->face_loop_offsets[0] != 0 || d->face_loop_offsets[F] != L) return WN_E_INVALID;
+    if (d->loop_curve_offsets[0] != 0 || d->loop_curve_offsets[L] != C) return WN_E_INVALID;
+    for (int32_t l = 0; l < L; ++l)
+        if (d->loop_curve_offsets[l + 1] < d->loop_curve_offsets[l]) return WN_E_INVALID;
+    if (C > 0 && d->curve_cp_offsets[0] != 0) return WN_E_INVALID;
+    // split every curve; the segments of curve c follow those of curve c - 1
+    std::vector<int32_t> curve_seg((size_t)C + 1, 0);
+    std::vector<int64_t> seg_cp(1, 0);
+    std::vector<double> u, v, w;
+    const bool rational = d->cp_w != nullptr;
+    int64_t kb = 0;
+    for (int32_t c = 0; c < C; ++c) {
+        const int p = d->curve_degree[c];
+        const int64_t c0 = d->curve_cp_offsets[c], c1 = d->curve_cp_offsets[c + 1];
+        const int64_t n = c1 - c0;
+        if (n < p + 1 || n > kMaxNurbsCps || p < 1 || p > wn::kMaxDeg) return WN_E_INVALID;
+        const int64_t cap = (n - p) * p + 1;  // at most n - p spans
+        std::vector<double> ou((size_t)cap), ov((size_t)cap), ow(rational ? (size_t)cap : 0);
+        int32_t k = 0;
+        const wn_status st = wn_nurbs_to_bezier(p, (int32_t)n, d->knots + kb, d->cp_u + c0, d->cp_v + c0,
+                                                rational ? d->cp_w + c0 : nullptr, cap, ou.data(), ov.data(),
+                                                rational ? ow.data() : nullptr, &k);
+        if (st != WN_OK) return st;
+        kb += n + p + 1;
+        for (int32_t sgi = 0; sgi < k; ++sgi) {
+            for (int i = 0; i <= p; ++i) {
+                const size_t at = (size_t)sgi * p + i;
+                u.push_back(ou[at]);
+                v.push_back(ov[at]);
+                if (rational) w.push_back(ow[at]);
+            }
+            seg_cp.push_back((int64_t)u.size());
+        }
+        curve_seg[c + 1] = curve_seg[c] + k;
+    }
+    std::vector<int32_t> loop_seg((size_t)L + 1, 0);
+    for (int32_t l = 0; l <= L; ++l) loop_seg[l] = curve_seg[d->loop_curve_offsets[l]];
+    wn_faces_desc fd{};
+    fd.num_faces = F;
+    fd.num_loops = L;
+    fd.num_segments = curve_seg[C];
+    fd.num_cps = (int64_t)u.size();
+    fd.face_loop_offsets = d->face_loop_offsets;
+    fd.loop_seg_offsets = loop_seg.data();
+    fd.seg_cp_offsets = seg_cp.data();
+    fd.cp_u = u.data();
+    fd.cp_v = v.data();
+    fd.cp_w = rational ? w.data() : nullptr;
+    fd.face_domain = d->face_domain;
+    fd.face_period = d->face_period;
+    return wn_create_faces(&fd, opt, stream, out);
+}

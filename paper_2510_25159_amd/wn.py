@@ -28,7 +28,7 @@ EXPORTS = [
     "wn_predictor_create", "wn_predictor_destroy", "wn_predictor_train", "wn_predictor_get_params",
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
     "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy", "wn_nurbs_to_bezier",
-    "wn_classify_grid", "wn_classify_surfaces",
+    "wn_classify_grid", "wn_classify_surfaces", "wn_create_faces_nurbs",
 ]
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -49,6 +49,13 @@ class wn_faces_desc(ctypes.Structure):
                 ("num_cps", ctypes.c_int64), ("face_loop_offsets", _P), ("loop_seg_offsets", _P),
                 ("seg_cp_offsets", _P), ("cp_u", _P), ("cp_v", _P), ("cp_w", _P), ("face_domain", _P),
                 ("face_period", _P)]
+
+
+class wn_nurbs_faces_desc(ctypes.Structure):
+    _fields_ = [("num_faces", ctypes.c_int32), ("num_loops", ctypes.c_int32), ("num_curves", ctypes.c_int32),
+                ("face_loop_offsets", _P), ("loop_curve_offsets", _P), ("curve_degree", _P),
+                ("curve_cp_offsets", _P), ("knots", _P), ("cp_u", _P), ("cp_v", _P), ("cp_w", _P),
+                ("face_domain", _P), ("face_period", _P)]
 
 
 class wn_options(ctypes.Structure):
@@ -154,6 +161,9 @@ def lib():
         L.wn_plan_autotune.restype = ctypes.c_int
         L.wn_plan_autotune.argtypes = [_P, ctypes.c_int32, _P, _P]
         L.wn_plan_destroy.argtypes = [_P]
+        L.wn_create_faces_nurbs.restype = ctypes.c_int
+        L.wn_create_faces_nurbs.argtypes = [ctypes.POINTER(wn_nurbs_faces_desc), ctypes.POINTER(wn_options), _P,
+                                            ctypes.POINTER(_P)]
         L.wn_classify_grid.restype = ctypes.c_int
         L.wn_classify_grid.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.POINTER(wn_query_opts), _P]
         L.wn_classify_surfaces.restype = ctypes.c_int
@@ -289,6 +299,35 @@ class FaceSet:
             raise WnError(st, "wn_create_faces")
         self._h = h
         self.num_faces = d.num_faces
+
+    @classmethod
+    def from_nurbs(cls, face_loop_offsets, loop_curve_offsets, curve_degree, curve_cp_offsets, knots, cp_u, cp_v,
+                   cp_w=None, face_domain=None, face_period=None, stream=None, **opts) -> "FaceSet":
+        """Faces whose loops are chains of NURBS curves (host arrays; the
+        curves' knot vectors back to back), split by wn_create_faces_nurbs."""
+        self = cls.__new__(cls)
+        self._h = None
+        a = dict(flo=np.ascontiguousarray(face_loop_offsets, dtype=np.int32),
+                 lco=np.ascontiguousarray(loop_curve_offsets, dtype=np.int32),
+                 deg=np.ascontiguousarray(curve_degree, dtype=np.int32),
+                 cco=np.ascontiguousarray(curve_cp_offsets, dtype=np.int64),
+                 kn=np.ascontiguousarray(knots, dtype=np.float64),
+                 cu=np.ascontiguousarray(cp_u, dtype=np.float64), cv=np.ascontiguousarray(cp_v, dtype=np.float64),
+                 cw=None if cp_w is None else np.ascontiguousarray(cp_w, dtype=np.float64),
+                 dom=None if face_domain is None else np.ascontiguousarray(face_domain, dtype=np.int32),
+                 per=None if face_period is None else np.ascontiguousarray(face_period, dtype=np.float64))
+        d = wn_nurbs_faces_desc(len(a["flo"]) - 1, len(a["lco"]) - 1, len(a["deg"]), _np_ptr(a["flo"]),
+                                _np_ptr(a["lco"]), _np_ptr(a["deg"]), _np_ptr(a["cco"]), _np_ptr(a["kn"]),
+                                _np_ptr(a["cu"]), _np_ptr(a["cv"]), _np_ptr(a["cw"]), _np_ptr(a["dom"]),
+                                _np_ptr(a["per"]))
+        o = default_options(**opts)
+        h = _P()
+        st = lib().wn_create_faces_nurbs(ctypes.byref(d), ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h))
+        if st != WN_OK:
+            raise WnError(st, "wn_create_faces_nurbs")
+        self._h = h
+        self.num_faces = d.num_faces
+        return self
 
     def info(self) -> wn_faces_info:
         i = wn_faces_info()

@@ -259,13 +259,16 @@ def test_queries_on_chords_and_ray_ties(torch_cuda, oracle_lib):
 
 
 def test_nurbs_faces(torch_cuda, oracle_lib):
-    """Faces given as NURBS loops, split by the library's knot insertion: a
-    rational quadratic circle (closed form: omega = 1 inside, 0 outside) and a
-    closed random quintic with interior knots (oracle)."""
+    """Faces given as NURBS loops: a rational quadratic circle (closed form:
+    omega = 1 inside, 0 outside), a closed random quintic with interior knots,
+    and the circle as a loop of two half-circle curves.  The library splits
+    them by knot insertion (wn_nurbs_to_bezier + wn_create_faces, and
+    wn_create_faces_nurbs); the oracle gets its own split (interpolation of
+    each span)."""
+    from oracle import nurbs as ON
     from paper_2510_25159_amd import wn
     from tests.test_nurbs import CIRCLE_CP, CIRCLE_KNOTS, CIRCLE_W
 
-    circle = wn.nurbs_to_bezier(2, CIRCLE_KNOTS, CIRCLE_CP, CIRCLE_W)
     rng = np.random.default_rng(12)
     th = np.sort(rng.uniform(0, 2 * np.pi, 11))
     r = rng.uniform(0.6, 1.4, 11)
@@ -273,14 +276,39 @@ def test_nurbs_faces(torch_cuda, oracle_lib):
     cp = np.vstack([cp, cp[:1]])  # closed: clamped ends at the same point
     knots = np.concatenate([np.zeros(6), [0.3, 0.3, 0.55, 0.7, 0.8, 0.8], np.ones(6)])
     wts = rng.uniform(0.5, 2.0, len(cp))
-    blob = wn.nurbs_to_bezier(5, knots, cp, wts)
-    faces = W.faces_from_loops([[circle], [blob]], rational=True)
+    s2 = 2 ** -0.5
+    half_knots = [0, 0, 0, 0.5, 0.5, 1, 1, 1]
+    upper = ([[1, 0], [1, 1], [0, 1], [-1, 1], [-1, 0]], [1, s2, 1, s2, 1])
+    lower = ([[-1, 0], [-1, -1], [0, -1], [1, -1], [1, 0]], [1, s2, 1, s2, 1])
+    curves = [(2, CIRCLE_KNOTS, CIRCLE_CP, CIRCLE_W), (5, knots, cp, wts), (2, half_knots, *upper),
+              (2, half_knots, *lower)]
+    loops = [[0], [1], [2, 3]]  # face f = loop f
+    # oracle faces from the oracle's split
+    o_loops = [[[seg for c in lp for seg in ON.spans_to_bezier(curves[c][1], curves[c][0], curves[c][2],
+                                                                 curves[c][3])]] for lp in loops]
+    faces_o = W.faces_from_loops(o_loops, rational=True)
     P = rng.uniform(-1.6, 1.6, (20000, 2))
-    q = W.queries_for_faces([P, P])
-    w_o, n_o = oracle_lib.query_faces(faces, q)
+    q = W.queries_for_faces([P, P, P])
+    w_o, n_o = oracle_lib.query_faces(faces_o, q)
+    rad = np.hypot(P[:, 0], P[:, 1])
+    far = np.abs(rad - 1.0) > 1e-6
+    for f in (0, 2):
+        assert np.allclose(w_o[f * 20000:(f + 1) * 20000][far], (rad[far] < 1.0).astype(float), atol=1e-12)
+    # library: split then create, and create from NURBS
+    l_loops = [[[seg for c in lp for seg in wn.nurbs_to_bezier(curves[c][0], curves[c][1], curves[c][2],
+                                                                curves[c][3])]] for lp in loops]
+    faces_l = W.faces_from_loops(l_loops, rational=True)
+    fs_n = wn.FaceSet.from_nurbs([0, 1, 2, 3], [0, 1, 2, 4], [c[0] for c in curves],
+                                 np.cumsum([0] + [len(c[2]) for c in curves]),
+                                 np.concatenate([np.asarray(c[1], dtype=float) for c in curves]),
+                                 np.concatenate([np.asarray(c[2], dtype=float)[:, 0] for c in curves]),
+                                 np.concatenate([np.asarray(c[2], dtype=float)[:, 1] for c in curves]),
+                                 np.concatenate([np.asarray(c[3], dtype=float) for c in curves]))
     for sched in (0, 1):
-        w, lab = run_wn(faces, q, schedule=sched)
+        w, lab = run_wn(faces_l, q, schedule=sched)
         compare(w, lab, w_o, n_o)
-        rad = np.hypot(P[:, 0], P[:, 1])
-        far = np.abs(rad - 1.0) > 1e-6
-        assert np.allclose(w[:20000][far], (rad[far] < 1.0).astype(float), atol=1e-12)
+        w2, lab2 = run_wn(None, q, schedule=sched, faceset=fs_n)
+        compare(w2, lab2, w_o, n_o)
+        assert np.array_equal(lab2, lab)
+    with pytest.raises(wn.WnError):  # a curve with too few control points
+        wn.FaceSet.from_nurbs([0, 1], [0, 1], [3], [0, 3], np.zeros(7), [0, 1, 2], [0, 1, 0])
