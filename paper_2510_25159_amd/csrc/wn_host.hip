@@ -712,10 +712,10 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
                 e = launch_build_items(one, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters, zero_near,
                                        st);
                 zero_near = false;
+                if (e == hipSuccess) e = launch_spatial_order(one, pts, sc.perm, st);
                 if (e == hipSuccess)
                     e = launch_far_periodic(kPerInline, h->sg, one, pts, sc.item_offs, sc.item_map, nullptr,
-                                            (nf + 255) / 256,
-                                            sc.nq, sc.out, h->eps2, h->pt, st);
+                                            (nf + 255) / 256, sc.nq, sc.out, h->eps2, h->pt, sc.perm, st);
                 if (e == hipSuccess) e = launch_finalize(pts, sc.out, ho[f], ho[f + 1], -1, st);
             }
         }
@@ -750,7 +750,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
         const bool persistent = q.queue_policy != 2;
         const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_redo_per : sc.max_items;
         e = launch_far_periodic(kPerRedo, h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
-                                persistent ? sc.counters + 1 : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, st);
+                                persistent ? sc.counters + 1 : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, sc.perm,
+                                st);
     }
     if (e == hipSuccess) {
         ProfScope ps(q.profile, WN_KERNEL_FINALIZE, st);
@@ -795,7 +796,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
     const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
     const size_t o_q2 = take(binned ? (size_t)cap * 8 : 0), o_s2 = take(binned && periodic ? (size_t)cap * 16 : 0);
     const size_t o_bn = take(binned ? (size_t)cap : 0), o_wh = take(binned ? (size_t)G * 32 * 4 : 0);
-    const size_t o_dp = take(depth ? (size_t)cap : 0);
+    const size_t o_dp = take(depth ? (size_t)cap : 0), o_pm = take(periodic ? (size_t)N * 4 : 0);
     const size_t o_wt = take(depth ? (size_t)N * 8 : 0), o_lt = take(depth ? (size_t)N : 0);
     const hipError_t e = stream_ordered ? hipMallocAsync(&sc.base, total, st) : hipMalloc(&sc.base, total);
     if (e != hipSuccess) return e;
@@ -806,6 +807,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
     sc.nq = NearQueue{(uint2*)(b + o_nq), periodic ? (double2*)(b + o_sh) : nullptr,
                       (unsigned long long*)(sc.counters + 2), (uint64_t)cap};
     sc.out = Out{out_w ? out_w : (double*)(b + o_w), out_lab ? out_lab : (uint8_t*)(b + o_l), nullptr, 0, rule};
+    sc.perm = periodic ? (uint32_t*)(b + o_pm) : nullptr;
     if (binned) {
         sc.qs2 = (uint2*)(b + o_q2);
         sc.sh2 = periodic ? (double2*)(b + o_s2) : nullptr;
@@ -879,12 +881,14 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
             e = launch_build_items(h->ft_per, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
                                    zero_near, st);
             zero_near = false;
+            if (e == hipSuccess) e = launch_spatial_order(h->ft_per, pts, sc.perm, st);
         }
         if (e == hipSuccess) {
             const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_far_per : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR_PERIODIC, st);
             e = launch_far_periodic(kPerQueue, h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
-                                    persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, st);
+                                    persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, sc.perm,
+                                    st);
         }
     }
     return e;

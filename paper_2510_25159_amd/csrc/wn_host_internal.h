@@ -59,6 +59,7 @@ struct Scratch {
     int64_t max_items = 0;
     NearQueue nq{};
     Out out{};
+    uint32_t* perm = nullptr;  // spatial order of the periodic faces' points (periodic face sets)
     // binned schedule
     uint2* qs2 = nullptr;
     double2* sh2 = nullptr;

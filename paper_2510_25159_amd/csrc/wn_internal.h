@@ -193,6 +193,9 @@ hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);
 enum : int { kPerQueue = 0, kPerInline = 1, kPerRedo = 2 };
 hipError_t launch_far_periodic(int mode, const Segs& sg, const FaceTab& ft, const Points& pts,
                                const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
-                               NearQueue nq, Out out, double eps2, PerTab pt, hipStream_t st);
+                               NearQueue nq, Out out, double eps2, PerTab pt, const uint32_t* perm, hipStream_t st);
+// Spatial order of the points of every face of ft (one workgroup per face):
+// perm[slot] = point index; perm == nullptr in launch_far_periodic = identity.
+hipError_t launch_spatial_order(const FaceTab& ft, const Points& pts, uint32_t* perm, hipStream_t st);
 int far_periodic_blocks_per_cu(int mode);
 }  // namespace wn

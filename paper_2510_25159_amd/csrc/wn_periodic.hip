@@ -270,7 +270,8 @@ struct PerShared<kPerRedo> : PerShared<kPerInline> {};
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
                                                       const int2* item_map, uint32_t* item_counter, NearQueue nq,
-                                                      Out out, double eps2, PerTab pt) {
+                                                      Out out, double eps2, PerTab pt,
+                                                      const uint32_t* perm) {
     __shared__ PerShared<MODE> sh;
     if (MODE == kPerRedo && *nq.count <= nq.cap) return;  // the queue never overflowed: nothing was lost
     const int tid = threadIdx.x;
@@ -308,8 +309,10 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
         qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
         qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
         PerLane P;
-        P.qi = qb + (int64_t)tile * (kWave * kWavesPerWG) + wave * kWave + lane;
-        bool active = P.qi < qe;
+        // slot of the face's (spatially ordered) point list -> point index
+        const int64_t slot = qb + (int64_t)tile * (kWave * kWavesPerWG) + wave * kWave + lane;
+        bool active = slot < qe;
+        P.qi = (perm && active) ? (int64_t)perm[slot] : slot;
         if constexpr (MODE == kPerRedo) {
             active = active && out.lab[P.qi] == kRedo;
             if (!__any(active)) continue;  // no __syncthreads below: waves may skip independently
@@ -370,26 +373,121 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
     }
 }
 
+// Spatial order of each periodic face's points: a counting sort by the
+// Morton index of their 16 x 16 bin in the bounding box of the face's points
+// (points with invalid coordinates go to bin 0).  perm[qb + r] is the r-th
+// point of the face in that order, so a wave holds neighbouring points whose
+// copy windows overlap and the wave's union of windows stays narrow.  The
+// results do not depend on the order: a lane only accumulates the copies of
+// its own window, in the same order.  One workgroup per face.
+constexpr int kOrderSide = 16, kOrderBins = kOrderSide * kOrderSide;
+static_assert(kOrderBins == kWG, "one bin per thread");
+
+__device__ __forceinline__ uint32_t morton8(uint32_t x, uint32_t y) {
+    uint32_t z = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) z |= ((x >> b) & 1u) << (2 * b) | ((y >> b) & 1u) << (2 * b + 1);
+    return z;
+}
+
+__global__ __launch_bounds__(kWG) void k_spatial_order(FaceTab ft, Points pts, uint32_t* perm) {
+    __shared__ uint32_t s_cnt[kOrderBins];
+    __shared__ double s_box[kWavesPerWG][4];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int f = ft.order[blockIdx.x];
+    int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+    qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
+    qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+    auto ok = [](double x) { return fabs(x) < kCoordLimit; };  // false for NaN
+    double b0 = INFINITY, b1 = -INFINITY, b2 = INFINITY, b3 = -INFINITY;
+    for (int64_t i = qb + tid; i < qe; i += kWG) {
+        const double u = pts.u[i * pts.stride], v = pts.v[i * pts.stride];
+        if (ok(u) && ok(v)) {
+            b0 = fmin(b0, u);
+            b1 = fmax(b1, u);
+            b2 = fmin(b2, v);
+            b3 = fmax(b3, v);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        b0 = fmin(b0, __shfl_xor(b0, off));
+        b1 = fmax(b1, __shfl_xor(b1, off));
+        b2 = fmin(b2, __shfl_xor(b2, off));
+        b3 = fmax(b3, __shfl_xor(b3, off));
+    }
+    if (lane == 0) {
+        s_box[wave][0] = b0;
+        s_box[wave][1] = b1;
+        s_box[wave][2] = b2;
+        s_box[wave][3] = b3;
+    }
+    s_cnt[tid] = 0;
+    __syncthreads();
+    for (int w = 0; w < kWavesPerWG; ++w) {
+        b0 = fmin(b0, s_box[w][0]);
+        b1 = fmax(b1, s_box[w][1]);
+        b2 = fmin(b2, s_box[w][2]);
+        b3 = fmax(b3, s_box[w][3]);
+    }
+    const double su = b1 > b0 ? kOrderSide / (b1 - b0) : 0.0, sv = b3 > b2 ? kOrderSide / (b3 - b2) : 0.0;
+    auto bin_of = [&](int64_t i) -> uint32_t {
+        const double u = pts.u[i * pts.stride], v = pts.v[i * pts.stride];
+        if (!(ok(u) && ok(v))) return 0u;
+        const int x = min(kOrderSide - 1, max(0, (int)((u - b0) * su)));
+        const int y = min(kOrderSide - 1, max(0, (int)((v - b2) * sv)));
+        return morton8((uint32_t)x, (uint32_t)y);
+    };
+    for (int64_t i = qb + tid; i < qe; i += kWG) atomicAdd(&s_cnt[bin_of(i)], 1u);
+    __syncthreads();
+    // exclusive scan of the 256 counts (Hillis-Steele on the inclusive sums)
+    uint32_t c = s_cnt[tid];
+    const uint32_t mine = c;
+    for (int off = 1; off < kOrderBins; off <<= 1) {
+        __syncthreads();
+        const uint32_t o = tid >= off ? s_cnt[tid - off] : 0u;
+        __syncthreads();
+        c += o;
+        s_cnt[tid] = c;
+    }
+    __syncthreads();
+    s_cnt[tid] = c - mine;
+    __syncthreads();
+    for (int64_t i = qb + tid; i < qe; i += kWG) {
+        const uint32_t r = atomicAdd(&s_cnt[bin_of(i)], 1u);
+        perm[qb + r] = (uint32_t)i;
+    }
+}
+
+hipError_t launch_spatial_order(const FaceTab& ft, const Points& pts, uint32_t* perm, hipStream_t st) {
+    if (ft.num_faces <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spatial_order, dim3((unsigned)ft.num_faces), dim3(kWG), 0, st, ft, pts, perm);
+    return hipGetLastError();
+}
+
 template <int MODE>
 static hipError_t launch_per(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                              const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
-                             double eps2, PerTab pt, hipStream_t st) {
+                             double eps2, PerTab pt, const uint32_t* perm, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_far_periodic<MODE>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
-                       item_counter, nq, out, eps2, pt);
+                       item_counter, nq, out, eps2, pt, perm);
     return hipGetLastError();
 }
 
 hipError_t launch_far_periodic(int mode, const Segs& sg, const FaceTab& ft, const Points& pts,
                                const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
-                               NearQueue nq, Out out, double eps2, PerTab pt, hipStream_t st) {
+                               NearQueue nq, Out out, double eps2, PerTab pt, const uint32_t* perm, hipStream_t st) {
     switch (mode) {
         case kPerQueue:
-            return launch_per<kPerQueue>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, st);
+            return launch_per<kPerQueue>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, perm,
+                                   st);
         case kPerInline:
-            return launch_per<kPerInline>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, st);
+            return launch_per<kPerInline>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, perm,
+                                   st);
         case kPerRedo:
-            return launch_per<kPerRedo>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, st);
+            return launch_per<kPerRedo>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, perm,
+                                   st);
         default:
             return hipErrorInvalidValue;
     }
