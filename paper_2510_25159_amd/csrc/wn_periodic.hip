@@ -379,8 +379,12 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
 // point of the face in that order, so a wave holds neighbouring points whose
 // copy windows overlap and the wave's union of windows stays narrow.  The
 // results do not depend on the order: a lane only accumulates the copies of
-// its own window, in the same order.  One workgroup per face.
+// its own window, in the same order.  One workgroup per face; faces with more
+// than kOrderMaxPoints points get the identity.
 constexpr int kOrderSide = 16, kOrderBins = kOrderSide * kOrderSide;
+// Faces with more points keep the caller's order (one workgroup would take
+// too long over them; large faces already fill several waves per copy).
+constexpr int64_t kOrderMaxPoints = 65536;
 static_assert(kOrderBins == kWG, "one bin per thread");
 
 __device__ __forceinline__ uint32_t morton8(uint32_t x, uint32_t y) {
@@ -398,6 +402,10 @@ __global__ __launch_bounds__(kWG) void k_spatial_order(FaceTab ft, Points pts, u
     int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
     qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
     qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+    if (qe - qb > kOrderMaxPoints) {
+        for (int64_t i = qb + tid; i < qe; i += kWG) perm[i] = (uint32_t)i;
+        return;
+    }
     auto ok = [](double x) { return fabs(x) < kCoordLimit; };  // false for NaN
     double b0 = INFINITY, b1 = -INFINITY, b2 = INFINITY, b3 = -INFINITY;
     for (int64_t i = qb + tid; i < qe; i += kWG) {

@@ -210,3 +210,23 @@ def test_punctured_sphere_topology_error(torch_cuda):
     with pytest.raises(wn.WnError) as e:
         wn.FaceSet(f)
     assert e.value.status == wn.WN_E_TOPOLOGY
+
+
+def test_large_and_small_periodic_faces(torch_cuda, oracle_lib):
+    """A torus face with more points than the spatial order handles (its
+    points keep their order) next to a small cylinder face (ordered), against
+    the oracle on a sample of each, under both schedules and both queue
+    policies."""
+    f, q = W.config3(face_ids=[1, 2], queries=70000)
+    offs = q.face_point_offsets.copy()
+    keep = np.concatenate([np.arange(offs[0], offs[1]), np.arange(offs[1], offs[1] + 3000)])
+    q2 = W.Queries(u=q.u[keep].copy(), v=q.v[keep].copy(),
+                   face_point_offsets=np.array([0, offs[1] - offs[0], offs[1] - offs[0] + 3000], dtype=np.int64))
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([rng.choice(70000, 3000, replace=False), 70000 + np.arange(3000)])
+    fid = q2.face_ids()[idx]
+    w_o, n_o = oracle_lib.query(f, fid, q2.u[idx], q2.v[idx])
+    print(f"config3 faces 1 (70000 points) and 2 (3000 points)", flush=True)
+    for sched, pol in ((1, 0), (1, 2), (0, 0)):
+        w, lab = run_wn(f, q2, schedule=sched, queue_policy=pol)
+        compare(w[idx], lab[idx], w_o, n_o)
