@@ -395,6 +395,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     const size_t o_ploop = add(nullptr, nper ? (size_t)L * sizeof(PLoop) : 0);
     const size_t o_pface = add(nullptr, nper ? (size_t)F * sizeof(PFace) : 0);
     const size_t o_punit = add(nullptr, nper ? (size_t)(2 * L + 1) * sizeof(PUnit) : 0);
+    const size_t o_frec = add(nullptr, nper ? (size_t)S * sizeof(FarRec) : 0);
     if (total == 0) total = 256;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMalloc(&h->dmem, total);
@@ -429,6 +430,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->sg.box = (const double*)(base + o_box);
     h->sg.wrange = (const float*)(base + o_wr);
     h->sg.join = (const uint8_t*)(base + o_join);
+    h->sg.frec = nper ? (const FarRec*)(base + o_frec) : nullptr;
     h->tree = PathTree{(const TNode*)(base + o_tree), (const int32_t*)(base + o_tbeg), (const int2*)(base + o_tch),
                        (const int32_t*)(base + o_tchb)};
     const int32_t* d_sb = (const int32_t*)(base + o_sb);
@@ -530,6 +532,23 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
             }
         }
         if (units.size() > (size_t)(2 * L + 1)) return fail(WN_E_TOPOLOGY);
+        // far-test records: the lifted end points (the lift's own additions,
+        // repeated with its offsets) and the final hb2
+        std::vector<FarRec> frec((size_t)S);
+        for (int32_t f = 0; f < F; ++f) {
+            if (dom[f] == WN_DOMAIN_PLANE) continue;
+            for (int32_t s = h->h_seg_begin[f]; s < h->h_seg_begin[f + 1]; ++s) {
+                const int64_t c0 = d->seg_cp_offsets[s], c1 = d->seg_cp_offsets[s + 1] - 1;
+                FarRec& r = frec[s];
+                r.p0x = d->cp_u[c0] + seg_off[2 * s];
+                r.p0y = d->cp_v[c0] + seg_off[2 * s + 1];
+                r.pnx = d->cp_u[c1] + seg_off[2 * s];
+                r.pny = d->cp_v[c1] + seg_off[2 * s + 1];
+                r.hb2 = hb2[s];
+            }
+        }
+        e = hipMemcpyAsync(base + o_frec, frec.data(), (size_t)S * sizeof(FarRec), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return fail(hip_status(e));
         e = hipMemcpyAsync(base + o_eta, eta.data(), (size_t)S * 8, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(base + o_hb2, hb2.data(), (size_t)S * 8, hipMemcpyHostToDevice, st);
         if (e == hipSuccess && !units.empty())

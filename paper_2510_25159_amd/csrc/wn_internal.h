@@ -33,6 +33,12 @@ constexpr double kCoordLimit = 1e15;
 // Per-segment data.  Far-field arrays are structure-of-arrays (coalesced
 // staging into LDS); the recursion coefficients of one segment are contiguous
 // (each near-pair lane gathers a different segment).
+// Far-test record of a periodic segment: lifted end points and the root
+// ellipse's hb2, 64-B aligned so that one scalar load fetches it.
+struct alignas(64) FarRec {
+    double p0x, p0y, pnx, pny, hb2, pad[3];
+};
+
 struct Segs {
     const double* p0x;  // [S] curve start gamma(0)
     const double* p0y;
@@ -48,6 +54,7 @@ struct Segs {
     const uint8_t* join;// [S] 1 when gamma(0) equals the previous segment's gamma(1) bit for bit
     const double* box;  // [S][4] control-point box umin, umax, vmin, vmax (lifted for periodic faces)
     const float* wrange;// [S][2] min, max weight
+    const FarRec* frec; // [S] periodic segments' far-test records (face sets with periodic faces)
 };
 
 // Path hierarchy (Sec. 4.2): per chain of bit-joined segments

@@ -192,13 +192,16 @@ template <int MODE>
 __device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double shx, double shy, bool act,
                                           PerLane& P, const PerWave& W) {
     const double xq = P.qx - shx, yq = P.qy - shy;
+    FarRec nx = kload(sg.frec, L.s0);
     for (int s = L.s0; s < L.s1; ++s) {
-        const double ax = kload(sg.p0x, s) - xq, ay = kload(sg.p0y, s) - yq;
-        const double bx = kload(sg.pnx, s) - xq, by = kload(sg.pny, s) - yq;
+        const FarRec r = nx;  // loaded one segment ahead
+        nx = kload(sg.frec, s + 1 < L.s1 ? s + 1 : s);
+        const double ax = r.p0x - xq, ay = r.p0y - yq;
+        const double bx = r.pnx - xq, by = r.pny - yq;
         const double ra = ax * ax + ay * ay, rb = bx * bx + by * by;
         const bool work = act && P.valid && !P.onb;
         if (work && (ra < W.eps2 || rb < W.eps2)) P.onb = true;
-        const bool far = outside_ellipse(ra, rb, kload(sg.hb2, s));
+        const bool far = outside_ellipse(ra, rb, r.hb2);
         if (work && far) turn_mul(P.T, ax * bx + ay * by, ax * by - ay * bx);
         const bool need = work && !P.onb && !far;
         if (need) chord_factor(P.T, ax, ay, bx, by);  // the near pass adds the integer rest
