@@ -305,7 +305,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--qpw", type=int, default=0)
     ap.add_argument("--policy", type=int, default=0)
-    ap.add_argument("--no-extra", action="store_true", help="skip the config 1/3/4/5 sections")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra sections")
+    ap.add_argument("--sections", default="", help="comma list of the extra sections to run (default: all)")
     ap.add_argument("--serving-duration", type=float, default=10.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration under rocprofv3)")
@@ -480,10 +481,13 @@ def main():
 
     sections = {}
     if not args.no_extra:
+        only = {x for x in args.sections.split(",") if x}
         for name, fn in (("config1", section_config1), ("long_path", section_long_path), ("config3", section_config3),
                          ("config4", section_config4), ("config5", section_config5),
                          ("spheres", section_spheres), ("tessellation", section_tessellation),
                          ("multipatch", section_multipatch)):
+            if only and name not in only:
+                continue
             t = time.time()
             try:
                 sections[name] = fn(args)
