@@ -170,8 +170,8 @@ typedef struct {
     int32_t precision;       /* -1 = the handle's default, else wn_precision              */
     int32_t rule;            /* -1 = the handle's default, else wn_rule                   */
     int32_t queries_per_wg;  /* 0 = tuned; else 64, 128 or 256 queries per workgroup, or 512 /
-                                1024 (two / four per lane: FP64 batched/binned far pass;
-                                otherwise 256)                                             */
+                                768 / 1024 (two / three / four per lane: FP64 batched/binned
+                                far pass; otherwise 256)                                   */
     int32_t queue_policy;    /* 0 = tuned, 1 = persistent workgroups popping an atomic work
                                 queue, 2 = one workgroup per work item (batched schedules)  */
     int64_t near_capacity;   /* 0 = default (8 * num_points + 65536) near-queue entries    */
@@ -449,13 +449,13 @@ wn_status wn_plan_create(const wn_faces* faces, const wn_points* points, double*
                          const wn_query_opts* q, void* stream, wn_plan** out);
 /* Replay the captured graph on `stream` (asynchronous). */
 wn_status wn_plan_launch(wn_plan* p, void* stream);
-/* Autotuner: time every (points per workgroup in {64, 128, 256, 512}) x
- * (queue policy in {persistent, one workgroup per item}) on the plan's
+/* Autotuner: time every (points per workgroup in {64, 128, 256, 512, 1024})
+ * x (queue policy in {persistent, one workgroup per item}) on the plan's
  * current buffers (`reps` runs each, HIP-event timed), keep the fastest and
- * re-capture the graph.  Synchronous.  report (host, nullable, 10 doubles):
+ * re-capture the graph.  Synchronous.  report (host, nullable, 12 doubles):
  * average milliseconds in the order (64,p), (64,w), (128,p), (128,w),
- * (256,p), (256,w), (512,p), (512,w), then the chosen points per workgroup
- * and policy. */
+ * (256,p), (256,w), (512,p), (512,w), (1024,p), (1024,w), then the chosen
+ * points per workgroup and policy. */
 wn_status wn_plan_autotune(wn_plan* p, int32_t reps, void* stream, double* report);
 void wn_plan_destroy(wn_plan* p);
 

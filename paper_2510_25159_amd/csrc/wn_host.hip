@@ -337,8 +337,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->bpc_far[m][2] = far_blocks_per_cu(false, m == 1, 256);
     }
     h->bpc_far_tree = far_tree_blocks_per_cu();
-    h->bpc_farq[0] = farq_blocks_per_cu(2);
-    h->bpc_farq[1] = farq_blocks_per_cu(4);
+    for (int qpl = 2; qpl <= 4; ++qpl) h->bpc_farq[qpl] = farq_blocks_per_cu(qpl);
     h->bpc_far_per = far_periodic_blocks_per_cu(kPerQueue);
     h->bpc_redo_per = far_periodic_blocks_per_cu(kPerRedo);
     h->bpc_near = near_blocks_per_cu();
@@ -633,8 +632,11 @@ void wn_profile_destroy(wn_profile* p) {
 
 static int pick_qpw(int64_t n, int cu) {
     // enough workgroups to cover every CU a few times before using 4 query
-    // groups per workgroup (segment split over waves otherwise), and two
-    // queries per lane beyond that
+    // groups per workgroup (segment split over waves otherwise), two queries
+    // per lane beyond that, and four once there are 16 items per CU (the
+    // four-query kernel runs 3 workgroups per CU: with fewer items its last
+    // round leaves CUs idle)
+    if (n >= (int64_t)cu * 1024 * 16) return 1024;
     if (n >= (int64_t)cu * 512 * 4) return 512;
     if (n >= (int64_t)cu * 256 * 4) return 256;
     if (n >= (int64_t)cu * 128 * 4) return 128;
@@ -658,7 +660,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     const int rule = q.rule >= 0 ? q.rule : h->rule;
     if (sched > WN_SCHED_BINNED || prec > WN_PREC_MIXED || rule > WN_RULE_POSITIVE) return WN_E_INVALID;
     if (q.queries_per_wg != 0 && q.queries_per_wg != 64 && q.queries_per_wg != 128 && q.queries_per_wg != 256 &&
-        q.queries_per_wg != 512 && q.queries_per_wg != 1024)
+        q.queries_per_wg != 512 && q.queries_per_wg != 768 && q.queries_per_wg != 1024)
         return WN_E_INVALID;
     if (q.queue_policy < 0 || q.queue_policy > 2 || q.near_capacity < 0) return WN_E_INVALID;
     if (q.depth_log && sched != WN_SCHED_PLAIN) return WN_E_UNSUPPORTED;
@@ -869,7 +871,7 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
         }
         if (e == hipSuccess) {
             const int* bp = h->bpc_far[mixed ? 1 : 0];
-            const int bpc = qpl > 1 ? h->bpc_farq[qpl / 4] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
+            const int bpc = qpl > 1 ? h->bpc_farq[qpl] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
             const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
             ProfScope ps(prof, WN_KERNEL_FAR, st);
             if (qpl > 1)

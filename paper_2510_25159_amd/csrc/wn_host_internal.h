@@ -24,7 +24,7 @@ struct wn_faces {
     int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
     int cu_count = 0;
     int bpc_far[2][3] = {{1, 1, 1}, {1, 1, 1}};  // resident workgroups per CU, k_far batched: [FP64, MIXED][64/128/256 points per workgroup]
-    int bpc_farq[2] = {1, 1}, bpc_far_tree = 1, bpc_far_per = 1, bpc_redo_per = 1, bpc_near = 1;
+    int bpc_farq[5] = {1, 1, 1, 1, 1}, bpc_far_tree = 1, bpc_far_per = 1, bpc_redo_per = 1, bpc_near = 1;
     std::vector<int32_t> h_seg_begin;
     std::vector<int32_t> h_dom;
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order

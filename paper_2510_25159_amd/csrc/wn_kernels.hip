@@ -421,6 +421,10 @@ struct FarqWaves<2> {
     static constexpr int w = 5;
 };
 template <>
+struct FarqWaves<3> {
+    static constexpr int w = 4;
+};
+template <>
 struct FarqWaves<4> {
     static constexpr int w = 3;
 };
@@ -1113,6 +1117,9 @@ hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points&
     if (qpl == 2)
         hipLaunchKernelGGL(k_farq<2>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
                            item_counter, nq, out, eps2);
+    else if (qpl == 3)
+        hipLaunchKernelGGL(k_farq<3>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
+                           item_counter, nq, out, eps2);
     else if (qpl == 4)
         hipLaunchKernelGGL(k_farq<4>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
                            item_counter, nq, out, eps2);
@@ -1125,6 +1132,7 @@ int farq_blocks_per_cu(int qpl) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     if (qpl == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_farq<2>, kWG, 0);
+    if (qpl == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_farq<3>, kWG, 0);
     if (qpl == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_farq<4>, kWG, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }

@@ -103,12 +103,13 @@ wn_status wn_plan_autotune(wn_plan* p, int32_t reps, void* stream, double* repor
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const wn_points pts = p->pts;
-    const int qpws[4] = {64, 128, 256, 512};
+    constexpr int kQ = 5;
+    const int qpws[kQ] = {64, 128, 256, 512, 1024};
     const int pols[2] = {1, 2};
     double best = 1e300;
     int bq = 256, bp = 1, k = 0;
     wn_status ws = WN_OK;
-    for (int i = 0; i < 4 && e == hipSuccess && ws == WN_OK; ++i)
+    for (int i = 0; i < kQ && e == hipSuccess && ws == WN_OK; ++i)
         for (int j = 0; j < 2 && e == hipSuccess && ws == WN_OK; ++j, ++k) {
             wn_query_opts q = p->q;
             q.queries_per_wg = qpws[i];
@@ -136,8 +137,8 @@ wn_status wn_plan_autotune(wn_plan* p, int32_t reps, void* stream, double* repor
     p->q.queries_per_wg = bq;
     p->q.queue_policy = bp;
     if (report) {
-        report[8] = bq;
-        report[9] = bp;
+        report[2 * kQ] = bq;
+        report[2 * kQ + 1] = bp;
     }
     return capture(p);
 }

@@ -564,14 +564,13 @@ class Plan:
             raise WnError(st, "wn_plan_launch")
 
     def autotune(self, reps: int = 3, stream=None) -> dict:
-        rep = np.zeros(10, dtype=np.float64)
+        rep = np.zeros(12, dtype=np.float64)
         st = lib().wn_plan_autotune(self._h, reps, _stream_ptr(stream), _np_ptr(rep))
         if st != WN_OK:
             raise WnError(st, "wn_plan_autotune")
-        names = ["64/persistent", "64/per-item", "128/persistent", "128/per-item", "256/persistent", "256/per-item",
-                 "512/persistent", "512/per-item"]
-        return {"ms": dict(zip(names, rep[:8].tolist())), "queries_per_wg": int(rep[8]),
-                "queue_policy": int(rep[9])}
+        names = [f"{q}/{p}" for q in (64, 128, 256, 512, 1024) for p in ("persistent", "per-item")]
+        return {"ms": dict(zip(names, rep[:10].tolist())), "queries_per_wg": int(rep[10]),
+                "queue_policy": int(rep[11])}
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -52,7 +52,8 @@ def test_config1_parity(torch_cuda, c1, schedule, qpw):
     assert st["compared"] > 65000
 
 
-@pytest.mark.parametrize("schedule,policy,qpw", [(0, 0, 0), (1, 1, 0), (1, 2, 0), (1, 1, 512), (1, 2, 512)])
+@pytest.mark.parametrize("schedule,policy,qpw", [(0, 0, 0), (1, 1, 0), (1, 2, 0), (1, 1, 512), (1, 2, 512),
+                                                 (1, 1, 768), (1, 2, 1024)])
 def test_config2_subset_parity(torch_cuda, c2_small, schedule, policy, qpw):
     f, q, w_o, n_o = c2_small
     print(f"config2[0:24] schedule={schedule} policy={policy} qpw={qpw} points={q.num_points}", flush=True)
@@ -79,7 +80,7 @@ def test_mixed_precision(torch_cuda, c2_small, schedule, qpw):
     assert np.array_equal(np.isfinite(w32), ok) and np.array_equal(w32[ok], w64[ok])
 
 
-@pytest.mark.parametrize("qpw", [256, 512])
+@pytest.mark.parametrize("qpw", [256, 512, 768, 1024])
 def test_near_queue_overflow_falls_back_in_line(torch_cuda, c2_small, qpw):
     f, q, w_o, n_o = c2_small
     w, lab = run_wn(f, q, schedule=1, near_capacity=1000, queries_per_wg=qpw)
