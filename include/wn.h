@@ -259,7 +259,7 @@ wn_status wn_segment_bound(const double* cp_u, const double* cp_v, const double*
  *   num_cps      degree + 1 <= n <= 16384; cp_u, cp_v [n]; cp_w [n] weights > 0 (finite),
  *                or NULL for a non-rational B-spline (out_w is then not written)
  *   knots        [n + degree + 1], non-decreasing and clamped: the first and the
- *                last value each repeated degree + 1 times, U[degree] < U[n]
+ *                last value each repeated exactly degree + 1 times, U[degree] < U[n]
  *   out_cap      capacity of out_u, out_v (and out_w) in points
  *   out_u/v/w    segment i's control points are entries i*degree .. i*degree +
  *                degree (neighbours share their joint), so k segments fill

@@ -43,6 +43,9 @@ extern "C" wn_status wn_nurbs_to_bezier(int32_t degree, int32_t num_cps, const d
     for (int i = 1; i <= p; ++i)
         if (U[i] != U[0] || U[n + p - i] != U[n + p]) return WN_E_INVALID;
     if (!(U[p] < U[n])) return WN_E_INVALID;
+    // the end values appear exactly p + 1 times (more would leave basis
+    // functions without support inside [U[p], U[n]])
+    if (!(U[p + 1] > U[p]) || !(U[n - 1] < U[n])) return WN_E_INVALID;
     std::vector<H3> H((size_t)n);
     for (int i = 0; i < n; ++i) {
         const double w = cp_w ? cp_w[i] : 1.0;
@@ -75,10 +78,11 @@ extern "C" wn_status wn_nurbs_to_bezier(int32_t degree, int32_t num_cps, const d
         }
         k = e;
     }
+    if (((int64_t)H.size() - 1) % p != 0) return WN_E_INVALID;  // cannot happen for a validated knot vector
     const int64_t segs = ((int64_t)H.size() - 1) / p;
     *out_segments = (int32_t)segs;
     if (out_cap < segs * p + 1 || !out_u || !out_v || (cp_w && !out_w)) return WN_E_INVALID;
-    for (size_t i = 0; i < H.size(); ++i) {
+    for (size_t i = 0; i < (size_t)(segs * p + 1); ++i) {
         out_u[i] = H[i].x / H[i].w;
         out_v[i] = H[i].y / H[i].w;
         if (cp_w) out_w[i] = H[i].w;

@@ -91,6 +91,8 @@ def test_split_rejects_malformed(wnlib):
         (2, [0, 0, 0, 0.6, 0.4, 1, 1], cp),               # decreasing
         (1, [0, 0, 0.5, 0.5, 1, 1], cp),                  # multiplicity 2 > degree 1: a break
         (2, [0, 0, 0, 0, 0, 0, 0], cp),                   # empty domain
+        (2, [0, 0, 0, 0.5, 1, 1, 1, 1], np.zeros((5, 2))),  # end value repeated p + 2 times
+        (2, [0, 0, 0, 0, 0.5, 1, 1, 1], np.zeros((5, 2))),  # start value repeated p + 2 times
     ]
     for p, knots, c in bad:
         with pytest.raises(wnlib.WnError):
