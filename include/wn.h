@@ -340,6 +340,8 @@ typedef struct {
     int32_t num_faces;
     int32_t num_loops;
     int32_t num_curves;
+    int64_t num_cps;    /* entries of cp_u, cp_v (and cp_w): must equal curve_cp_offsets[num_curves] */
+    int64_t num_knots;  /* entries of knots: must equal the sum of (cp count + degree + 1) */
     const int32_t* face_loop_offsets;
     const int32_t* loop_curve_offsets;
     const int32_t* curve_degree;

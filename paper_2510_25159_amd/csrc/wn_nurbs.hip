@@ -102,6 +102,18 @@ extern "C" wn_status wn_create_faces_nurbs(const wn_nurbs_faces_desc* d, const w
     for (int32_t l = 0; l < L; ++l)
         if (d->loop_curve_offsets[l + 1] < d->loop_curve_offsets[l]) return WN_E_INVALID;
     if (C > 0 && d->curve_cp_offsets[0] != 0) return WN_E_INVALID;
+    if (d->num_cps < 0 || d->num_knots < 0 || (C > 0 && d->curve_cp_offsets[C] != d->num_cps)) return WN_E_INVALID;
+    {  // every curve's control points and knots inside the arrays
+        int64_t kt = 0;
+        for (int32_t c = 0; c < C; ++c) {
+            const int64_t c0 = d->curve_cp_offsets[c], c1 = d->curve_cp_offsets[c + 1];
+            const int p = d->curve_degree[c];
+            if (c1 < c0 || c1 > d->num_cps || p < 1 || p > wn::kMaxDeg) return WN_E_INVALID;
+            kt += (c1 - c0) + p + 1;
+            if (kt > d->num_knots) return WN_E_INVALID;
+        }
+        if (kt != d->num_knots) return WN_E_INVALID;
+    }
     // split every curve; the segments of curve c follow those of curve c - 1
     std::vector<int32_t> curve_seg((size_t)C + 1, 0);
     std::vector<int64_t> seg_cp(1, 0);

@@ -53,6 +53,7 @@ class wn_faces_desc(ctypes.Structure):
 
 class wn_nurbs_faces_desc(ctypes.Structure):
     _fields_ = [("num_faces", ctypes.c_int32), ("num_loops", ctypes.c_int32), ("num_curves", ctypes.c_int32),
+                ("num_cps", ctypes.c_int64), ("num_knots", ctypes.c_int64),
                 ("face_loop_offsets", _P), ("loop_curve_offsets", _P), ("curve_degree", _P),
                 ("curve_cp_offsets", _P), ("knots", _P), ("cp_u", _P), ("cp_v", _P), ("cp_w", _P),
                 ("face_domain", _P), ("face_period", _P)]
@@ -316,7 +317,8 @@ class FaceSet:
                  cw=None if cp_w is None else np.ascontiguousarray(cp_w, dtype=np.float64),
                  dom=None if face_domain is None else np.ascontiguousarray(face_domain, dtype=np.int32),
                  per=None if face_period is None else np.ascontiguousarray(face_period, dtype=np.float64))
-        d = wn_nurbs_faces_desc(len(a["flo"]) - 1, len(a["lco"]) - 1, len(a["deg"]), _np_ptr(a["flo"]),
+        d = wn_nurbs_faces_desc(len(a["flo"]) - 1, len(a["lco"]) - 1, len(a["deg"]), len(a["cu"]), len(a["kn"]),
+                                _np_ptr(a["flo"]),
                                 _np_ptr(a["lco"]), _np_ptr(a["deg"]), _np_ptr(a["cco"]), _np_ptr(a["kn"]),
                                 _np_ptr(a["cu"]), _np_ptr(a["cv"]), _np_ptr(a["cw"]), _np_ptr(a["dom"]),
                                 _np_ptr(a["per"]))
