@@ -349,6 +349,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         return (h->h_seg_begin[a + 1] - h->h_seg_begin[a]) > (h->h_seg_begin[b + 1] - h->h_seg_begin[b]);
     };
     std::stable_sort(ord_plan.begin(), ord_plan.end(), by_size);
+    h->h_ord_plan = ord_plan;
     // automatic hierarchy: faces with a chain of at least kTreeAutoSegs segments
     // take the tree walk, the others the flat scan
     std::vector<int32_t> ord_tree, ord_flat;
@@ -559,12 +560,25 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->pt.unit = (const PUnit*)(base + o_punit);
         h->pt.face = (const PFace*)(base + o_pface);
     }
+    // side stream of the overlapped passes (none: no overlap)
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+        if (h->side) (void)hipStreamDestroy(h->side);
+        h->side = nullptr;
+        h->ev_fork = h->ev_join = nullptr;
+        (void)hipGetLastError();
+    }
     *out = h;
     return WN_OK;
 }
 
 void wn_destroy_faces(wn_faces* h) {
     if (!h) return;
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->dmem) (void)hipFree(h->dmem);
     delete h;
 }
@@ -745,7 +759,11 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     }
 
     // batched / binned: persistent far launches, (binning), near pass, finalize, redo
-    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st);
+    // the far/near overlap is for the plain batched FP64 query (not binned, not
+    // captured into a plan, no work counters)
+    sc.near_lo = nullptr;
+    const int64_t* ovl = (!binned && !preset && !q.stats && prec == WN_PREC_FP64) ? p->face_point_offsets_host : nullptr;
+    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st, ovl);
     NearQueue nq = sc.nq;
     if (e == hipSuccess && binned) {
         const wn_predictor* pr = q.predictor;
@@ -763,7 +781,17 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
         nq.qs = sc.qs2;
         nq.shift = sc.sh2;
     }
-    if (e == hipSuccess) e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st);
+    if (e == hipSuccess && sc.near_lo) {
+        // the entries after the last overlapped phase, then join the side stream
+        {
+            ProfScope ps(q.profile, WN_KERNEL_NEAR, st);
+            e = launch_near(h->sg, pts, nq, sc.out, h->eps2, (int64_t)h->cu_count * h->bpc_near, Stats{nullptr},
+                            h->pt.seg_periodic, nullptr, st, sc.near_lo, nullptr);
+        }
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_join, 0);
+    } else if (e == hipSuccess) {
+        e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st);
+    }
     if (e == hipSuccess && h->num_periodic > 0) {
         // periodic queries that lost a near pair: recomputed in line over the
         // periodic item table (still the last one built), before finalize
@@ -812,7 +840,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
         return off;
     };
     const int G = binning_grid(h);
-    const size_t o_io = take(((size_t)F + 1) * 4), o_im = take((size_t)sc.max_items * 8), o_ct = take(16);
+    const size_t o_io = take(((size_t)F + 1) * 4), o_im = take((size_t)sc.max_items * 8), o_ct = take(128);
     const size_t o_nq = take((size_t)cap * 8), o_sh = take(periodic ? (size_t)cap * 16 : 0);
     const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
     const size_t o_q2 = take(binned ? (size_t)cap * 8 : 0), o_s2 = take(binned && periodic ? (size_t)cap * 16 : 0);
@@ -850,8 +878,65 @@ void scratch_free(Scratch& sc, hipStream_t st) {
 
 int binning_grid(const wn_faces* h) { return std::min(1024, std::max(1, h->cu_count * 4)); }
 
+// Far and near passes overlapped (batched FP64, planar flat scan).  The
+// planar faces (rank order: largest first) are split into kOverlapPhases runs
+// of about equal pair counts.  After the far pass over run k (on st) the
+// queue's count is marked, and the near pass over run k's entries runs on
+// the side stream while the far pass over run k + 1 runs on st.  The far
+// phases after the first and the side near passes take half the persistent
+// grid each, so that both are resident (a persistent kernel on the whole grid
+// would hold every slot).  The last run's entries, and those of any later far
+// pass, go to the final near pass on st (from sc.near_lo), which joins the
+// side stream.  The near passes read disjoint queue ranges and the phases
+// write disjoint queries, so the results are those of the serial passes.
+constexpr int kOverlapPhases = 3;
+
+static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, const Points& pts, int qpl, int64_t grid,
+                                      const int64_t* host_offs, Scratch& sc, wn_profile* prof, hipStream_t st) {
+    const std::vector<int32_t>& ord = h->h_ord_plan;
+    const int Fp = (int)ord.size();
+    auto pairs = [&](int r) {
+        const int f = ord[r];
+        const int64_t nq = std::max<int64_t>(0, host_offs[f + 1] - host_offs[f]);
+        return (int64_t)(h->h_seg_begin[f + 1] - h->h_seg_begin[f]) * nq;
+    };
+    int64_t tot = 0;
+    for (int r = 0; r < Fp; ++r) tot += pairs(r);
+    int rk[kOverlapPhases + 1];
+    rk[0] = 0;
+    int64_t acc = 0;
+    for (int k = 1, r = 0; k < kOverlapPhases; ++k) {
+        while (r < Fp - 1 && acc * kOverlapPhases < tot * k) acc += pairs(r++);
+        rk[k] = r;
+    }
+    rk[kOverlapPhases] = Fp;
+    unsigned long long* marks = reinterpret_cast<unsigned long long*>(sc.counters + 16);
+    const int64_t side_grid = std::max<int64_t>(1, (int64_t)h->cu_count * h->bpc_near / 2);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kOverlapPhases && e == hipSuccess; ++k) {
+        {
+            ProfScope ps(prof, WN_KERNEL_FAR, st);
+            e = launch_farq(qpl, h->sg, ft, pts, sc.item_offs, sc.item_map, sc.counters + 8 + k,
+                            k == 0 ? grid : std::max<int64_t>(1, grid / 2), sc.nq, sc.out, h->eps2, st, rk[k],
+                            rk[k + 1]);
+        }
+        if (k == kOverlapPhases - 1) break;
+        if (e == hipSuccess) e = launch_queue_mark(sc.nq.count, marks + k, st);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
+        if (e == hipSuccess) {
+            ProfScope ps(prof, WN_KERNEL_NEAR, h->side);
+            e = launch_near(h->sg, pts, sc.nq, sc.out, h->eps2, side_grid, Stats{nullptr}, h->pt.seg_periodic,
+                            nullptr, h->side, k == 0 ? nullptr : marks + k - 1, marks + k);
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->side);
+    if (e == hipSuccess) sc.near_lo = marks + kOverlapPhases - 2;
+    return e;
+}
+
 hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
-                      wn_profile* prof, hipStream_t st) {
+                      wn_profile* prof, hipStream_t st, const int64_t* host_offs) {
     hipError_t e = hipSuccess;
     bool zero_near = true;
     const bool persistent = policy != 2;
@@ -869,10 +954,13 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
                                    zero_near, st);
             zero_near = false;
         }
-        if (e == hipSuccess) {
-            const int* bp = h->bpc_far[mixed ? 1 : 0];
-            const int bpc = qpl > 1 ? h->bpc_farq[qpl] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
-            const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
+        const int* bp = h->bpc_far[mixed ? 1 : 0];
+        const int bpc = qpl > 1 ? h->bpc_farq[qpl] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
+        const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
+        if (e == hipSuccess && qpl > 1 && persistent && tree == 0 && host_offs && h->side &&
+            flat_ft.num_faces >= kOverlapPhases) {
+            e = far_near_overlapped(h, flat_ft, pts, qpl, grid, host_offs, sc, prof, st);
+        } else if (e == hipSuccess) {
             ProfScope ps(prof, WN_KERNEL_FAR, st);
             if (qpl > 1)
                 e = launch_farq(qpl, h->sg, flat_ft, pts, sc.item_offs, sc.item_map,

@@ -28,6 +28,11 @@ struct wn_faces {
     std::vector<int32_t> h_seg_begin;
     std::vector<int32_t> h_dom;
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
+    std::vector<int32_t> h_ord_plan;  // ft_plan.order on the host
+    // side stream of the overlapped far/near passes (default priority) and
+    // its fork / join events; null when they could not be created
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct wn_profile {
@@ -59,6 +64,7 @@ struct Scratch {
     int64_t max_items = 0;
     NearQueue nq{};
     Out out{};
+    const unsigned long long* near_lo = nullptr;  // set by an overlapped far pass: the final near pass starts here
     uint32_t* perm = nullptr;  // spatial order of the periodic faces' points (periodic face sets)
     // binned schedule
     uint2* qs2 = nullptr;
@@ -76,9 +82,11 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
                          uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st, bool stream_ordered);
 void scratch_free(Scratch& sc, hipStream_t st);
 
-// Item build + persistent far passes (planar, periodic) filling sc.nq.
+// Item build + persistent far passes (planar, periodic) filling sc.nq.  With
+// host_offs (the host copy of the points' face offsets) the planar flat pass
+// may overlap near passes on h->side and leave sc.near_lo for the final one.
 hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
-                      wn_profile* prof, hipStream_t st);
+                      wn_profile* prof, hipStream_t st, const int64_t* host_offs = nullptr);
 // Near pass over nq; entry_depth optional.
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
                      uint8_t* entry_depth, wn_profile* prof, hipStream_t st);

@@ -177,8 +177,11 @@ hipError_t launch_build_items(const FaceTab& ft, const Points& pts, int qpw, int
 hipError_t launch_far(bool inline_near, bool mixed, int qpw, const Segs& sg, const FaceTab& ft, const Points& pts,
                       const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
+// Near pass over queue entries [*q_lo, *q_hi) (nullptr: 0 / the queue's count).
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st);
+                       Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st,
+                       const unsigned long long* q_lo = nullptr, const unsigned long long* q_hi = nullptr);
+hipError_t launch_queue_mark(const unsigned long long* count, unsigned long long* mark, hipStream_t st);
 hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, int32_t nf, hipStream_t st);
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2,
                        const NearQueue& nq, int64_t max_grid, hipStream_t st);
@@ -188,10 +191,12 @@ hipError_t launch_far_tree(const PathTree& tr, const FaceTab& ft, const Points& 
                            const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
                            double eps2, hipStream_t st);
 int far_tree_blocks_per_cu();
-// Queued FP64 far pass with qpl (2 or 4) queries per lane (items of 256 qpl queries).
+// Queued FP64 far pass with qpl (2, 3 or 4) queries per lane (items of 256 qpl
+// queries), over the items of the faces of rank [rank_lo, rank_hi) of ft
+// (rank_hi < 0: all faces).
 hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                        const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out, double eps2,
-                       hipStream_t st);
+                       hipStream_t st, int rank_lo = 0, int rank_hi = -1);
 int farq_blocks_per_cu(int qpl);
 int near_blocks_per_cu();
 hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);

@@ -70,8 +70,9 @@ __global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, in
     const int chunk = (F + 1023) / 1024;
     const int r0 = min(F, tid * chunk), r1 = min(F, r0 + chunk);
     // [0] far item counter, [1] periodic redo item counter, [2..3] near-queue
-    // count (64-bit, reset by the first build of a query only)
-    if (tid < 2) counters[tid] = 0;
+    // count (64-bit, reset by the first build of a query only), [8..15] item
+    // counters of the phases of an overlapped far pass
+    if (tid < 2 || (tid >= 8 && tid < 16)) counters[tid] = 0;
     if (zero_near && (tid == 2 || tid == 3)) counters[tid] = 0;
     auto tiles_of = [&](int r) -> int64_t {
         const int f = ft.order[r];
@@ -432,7 +433,7 @@ struct FarqWaves<4> {
 template <int QPL>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<QPL>::w))) void k_farq(
     Segs sg, FaceTab ft, Points pts, const int32_t* item_offs, const int2* item_map, uint32_t* item_counter,
-    NearQueue nq, Out out, double eps2) {
+    NearQueue nq, Out out, double eps2, int rank_lo, int rank_hi) {
     constexpr int kQPL = QPL;
     constexpr int kQPWG2 = kWave * QPL * kWavesPerWG;  // queries per work item
     __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
@@ -442,17 +443,18 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
-    const int total = item_offs[ft.num_faces];
+    // items of the faces of rank [rank_lo, rank_hi)
+    const int lo = item_offs[rank_lo], total = item_offs[rank_hi];
     for (int iter = 0;; ++iter) {
         int item;
         if (item_counter) {
             __syncthreads();
-            if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
+            if (tid == 0) s_item = lo + (int)atomicAdd(item_counter, 1u);
             __syncthreads();
             item = __builtin_amdgcn_readfirstlane(s_item);
         } else {
             if (iter > 0) break;
-            item = blockIdx.x;
+            item = lo + blockIdx.x;
         }
         if (item >= total) break;
         const int2 mp = item_map[item];
@@ -855,17 +857,22 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 
 template <bool COUNT>
 __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats,
-                                              const uint8_t* seg_per, uint8_t* entry_depth) {
+                                              const uint8_t* seg_per, uint8_t* entry_depth,
+                                              const unsigned long long* q_lo, const unsigned long long* q_hi) {
     __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     double4* stk = s_stack + wave * kNearSlots * kWave + lane;
-    unsigned long long n = *nq.count;
+    // queue entries [q_lo, q_hi) (defaults: 0 and the queue's count), split
+    // evenly over the waves
+    unsigned long long n = q_hi ? *q_hi : *nq.count;
     n = n < nq.cap ? n : nq.cap;
+    unsigned long long base = q_lo ? *q_lo : 0ull;
+    base = base < n ? base : n;
     const unsigned long long nw = (unsigned long long)gridDim.x * kWavesPerWG;
     const unsigned long long gw = (unsigned long long)blockIdx.x * kWavesPerWG + wave;
-    const unsigned long long per = (n + nw - 1) / nw;
-    const unsigned long long c_begin = gw * per < n ? gw * per : n;
+    const unsigned long long per = (n - base + nw - 1) / nw;
+    const unsigned long long c_begin = base + gw * per < n ? base + gw * per : n;
     const unsigned long long c_end = c_begin + per < n ? c_begin + per : n;
     unsigned long long next = c_begin;  // wave-uniform
     NodeState st;
@@ -1071,14 +1078,24 @@ hipError_t launch_far(bool inline_near, bool mixed, int qpw, const Segs& sg, con
 }
 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
-                       Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st) {
+                       Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st,
+                       const unsigned long long* q_lo, const unsigned long long* q_hi) {
     if (grid <= 0) return hipSuccess;
     if (stats.c || entry_depth)
         hipLaunchKernelGGL(k_near<true>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
-                           seg_per, entry_depth);
+                           seg_per, entry_depth, q_lo, q_hi);
     else
         hipLaunchKernelGGL(k_near<false>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
-                           seg_per, entry_depth);
+                           seg_per, entry_depth, q_lo, q_hi);
+    return hipGetLastError();
+}
+
+// The queue's entry count at this point of the stream (the end of one far
+// phase's entries, the start of the next's).
+__global__ void k_queue_mark(const unsigned long long* count, unsigned long long* mark) { *mark = *count; }
+
+hipError_t launch_queue_mark(const unsigned long long* count, unsigned long long* mark, hipStream_t st) {
+    hipLaunchKernelGGL(k_queue_mark, dim3(1), dim3(1), 0, st, count, mark);
     return hipGetLastError();
 }
 
@@ -1112,17 +1129,19 @@ static hipError_t far_occupancy(int* nb, int qpw) {
 
 hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                        const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out, double eps2,
-                       hipStream_t st) {
+                       hipStream_t st, int rank_lo, int rank_hi) {
+    if (rank_hi < 0) rank_hi = ft.num_faces;
+    if (rank_lo < 0 || rank_lo > rank_hi || rank_hi > ft.num_faces) return hipErrorInvalidValue;
     if (grid <= 0) return hipSuccess;
     if (qpl == 2)
         hipLaunchKernelGGL(k_farq<2>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
-                           item_counter, nq, out, eps2);
+                           item_counter, nq, out, eps2, rank_lo, rank_hi);
     else if (qpl == 3)
         hipLaunchKernelGGL(k_farq<3>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
-                           item_counter, nq, out, eps2);
+                           item_counter, nq, out, eps2, rank_lo, rank_hi);
     else if (qpl == 4)
         hipLaunchKernelGGL(k_farq<4>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
-                           item_counter, nq, out, eps2);
+                           item_counter, nq, out, eps2, rank_lo, rank_hi);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

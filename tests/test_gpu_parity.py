@@ -313,3 +313,18 @@ def test_nurbs_faces(torch_cuda, oracle_lib):
         assert np.array_equal(lab2, lab)
     with pytest.raises(wn.WnError):  # a curve with too few control points
         wn.FaceSet.from_nurbs([0, 1], [0, 1], [3], [0, 3], np.zeros(7), [0, 1, 2], [0, 1, 0])
+
+
+@pytest.mark.parametrize("qpw", [512, 1024])
+def test_overlapped_far_near_match_serial(torch_cuda, c2_small, qpw):
+    """With host offsets the batched FP64 query overlaps near passes of early
+    face runs with the far pass of later ones (a side stream); without them it
+    runs the passes one after the other.  Same labels, omega within rounding
+    of the order of the near pass's additions, and both match the oracle."""
+    f, q, w_o, n_o = c2_small
+    w1, l1 = run_wn(f, q, schedule=1, queries_per_wg=qpw)  # host offsets: overlapped
+    w2, l2 = run_wn(f, q, schedule=1, queries_per_wg=qpw, offsets_host=False)  # serial
+    assert np.array_equal(l1, l2)
+    ok = l1 < 2
+    assert np.max(np.abs(w1[ok] - w2[ok])) <= 1e-12
+    compare(w1, l1, w_o, n_o)
