@@ -306,6 +306,10 @@ def main():
     ap.add_argument("--qpw", type=int, default=0)
     ap.add_argument("--policy", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true", help="skip the extra sections")
+    ap.add_argument("--serial-steps", type=int, default=5,
+                    help="timed steps without the far/near overlap, for per-kernel rooflines")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed batched steps and the work counters (profiling runs)")
     ap.add_argument("--sections", default="", help="comma list of the extra sections to run (default: all)")
     ap.add_argument("--serving-duration", type=float, default=10.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -373,58 +377,83 @@ def main():
     w_b = out_w.cpu().numpy()
     lab_b = out_l.cpu().numpy()
 
-    # batched schedule with the FP32 far-field admission (same results, see the header)
-    def step_mixed(profile=None):
-        fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, precision=1,
-                 queries_per_wg=args.qpw, queue_policy=args.policy, profile=profile, stream=stream)
+    # the same steps without the far/near overlap (no host offsets: the passes
+    # run one after the other), for rooflines of each kernel on its own
+    kern_serial, ms_serial = {}, None
+    if args.serial_steps > 0 and not args.headline_only:
+        def step_serial(profile=None):
+            fs.query(u, v, offs, None, out_w, out_l, schedule=args.schedule, queries_per_wg=args.qpw,
+                     queue_policy=args.policy, profile=profile, stream=stream)
 
-    step_mixed()
-    torch.cuda.synchronize()
-    pm = wn.Profile(capacity=8 * args.mixed_steps + 64)
-    tm1 = time.perf_counter()
-    for _ in range(args.mixed_steps):
-        step_mixed(pm)
-    torch.cuda.synchronize()
-    ms_mixed = (time.perf_counter() - tm1) * 1e3 / max(args.mixed_steps, 1)
-    kern_mixed = {k: t_ / max(n, 1) for k, (n, t_) in pm.collect().items()}
-    mixed_same = bool(np.array_equal(out_l.cpu().numpy(), lab_b))
-    log(f"batched mixed: {ms_mixed:.3f} ms/step; kernels {kern_mixed}; labels equal to FP64: {mixed_same}")
+        step_serial()
+        torch.cuda.synchronize()
+        ps_ = wn.Profile(capacity=16 * args.serial_steps + 64)
+        ts1 = time.perf_counter()
+        for _ in range(args.serial_steps):
+            step_serial(ps_)
+        torch.cuda.synchronize()
+        ms_serial = (time.perf_counter() - ts1) * 1e3 / args.serial_steps
+        kern_serial = ps_.collect()
+        log(f"batched, passes in series: {ms_serial:.3f} ms/step; kernels {kern_serial}")
 
-    # path hierarchy (Sec. 4.2): subpath ellipses prune whole subpaths, so fewer
-    # pairs are tested; reported on its own row (queries/s), not as evals/s
-    def step_tree(profile=None):
-        fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, queries_per_wg=args.qpw,
-                 queue_policy=args.policy, profile=profile, stream=stream, path_hierarchy=1)
+    ms_mixed = ms_tree = ms_plain = float("nan")
+    kern_mixed = kern_tree = {}
+    mixed_same = plain_agree = None
+    tree_diff = tree_onb = None
 
-    step_tree()
-    torch.cuda.synchronize()
-    ptree = wn.Profile(capacity=8 * args.tree_steps + 64)
-    tt1 = time.perf_counter()
-    for _ in range(args.tree_steps):
-        step_tree(ptree)
-    torch.cuda.synchronize()
-    ms_tree = (time.perf_counter() - tt1) * 1e3 / max(args.tree_steps, 1)
-    kern_tree = {k: t_ / max(n, 1) for k, (n, t_) in ptree.collect().items()}
-    lab_t = out_l.cpu().numpy()
-    both = (lab_t != 2) & (lab_b != 2)
-    tree_diff = int(np.sum(lab_t[both] != lab_b[both]))
-    tree_onb = int(np.sum((lab_t == 2) != (lab_b == 2)))
-    log(f"path hierarchy: {ms_tree:.3f} ms/step, {N / (ms_tree / 1e3):.3e} queries/s; kernels {kern_tree}; "
-        f"label differences vs flat {tree_diff}, on-boundary differences {tree_onb}")
+    if not args.headline_only:
+        # batched schedule with the FP32 far-field admission (same results, see the header)
+        def step_mixed(profile=None):
+            fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, precision=1,
+                     queries_per_wg=args.qpw, queue_policy=args.policy, profile=profile, stream=stream)
 
-    # plain schedule beside it (one launch per face, in-line recursion)
-    step(0)
-    torch.cuda.synchronize()
-    tp1 = time.perf_counter()
-    for _ in range(args.plain_steps):
+        step_mixed()
+        torch.cuda.synchronize()
+        pm = wn.Profile(capacity=8 * args.mixed_steps + 64)
+        tm1 = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            step_mixed(pm)
+        torch.cuda.synchronize()
+        ms_mixed = (time.perf_counter() - tm1) * 1e3 / max(args.mixed_steps, 1)
+        kern_mixed = {k: t_ / max(n, 1) for k, (n, t_) in pm.collect().items()}
+        mixed_same = bool(np.array_equal(out_l.cpu().numpy(), lab_b))
+        log(f"batched mixed: {ms_mixed:.3f} ms/step; kernels {kern_mixed}; labels equal to FP64: {mixed_same}")
+
+        # path hierarchy (Sec. 4.2): subpath ellipses prune whole subpaths, so fewer
+        # pairs are tested; reported on its own row (queries/s), not as evals/s
+        def step_tree(profile=None):
+            fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, queries_per_wg=args.qpw,
+                     queue_policy=args.policy, profile=profile, stream=stream, path_hierarchy=1)
+
+        step_tree()
+        torch.cuda.synchronize()
+        ptree = wn.Profile(capacity=8 * args.tree_steps + 64)
+        tt1 = time.perf_counter()
+        for _ in range(args.tree_steps):
+            step_tree(ptree)
+        torch.cuda.synchronize()
+        ms_tree = (time.perf_counter() - tt1) * 1e3 / max(args.tree_steps, 1)
+        kern_tree = {k: t_ / max(n, 1) for k, (n, t_) in ptree.collect().items()}
+        lab_t = out_l.cpu().numpy()
+        both = (lab_t != 2) & (lab_b != 2)
+        tree_diff = int(np.sum(lab_t[both] != lab_b[both]))
+        tree_onb = int(np.sum((lab_t == 2) != (lab_b == 2)))
+        log(f"path hierarchy: {ms_tree:.3f} ms/step, {N / (ms_tree / 1e3):.3e} queries/s; kernels {kern_tree}; "
+            f"label differences vs flat {tree_diff}, on-boundary differences {tree_onb}")
+
+        # plain schedule beside it (one launch per face, in-line recursion)
         step(0)
-    torch.cuda.synchronize()
-    tp2 = time.perf_counter()
-    ms_plain = (tp2 - tp1) * 1e3 / args.plain_steps
-    lab_p = out_l.cpu().numpy()
-    w_p = out_w.cpu().numpy()
-    log(f"plain: {ms_plain:.3f} ms/step, {pairs / (ms_plain / 1e3):.3e} evals/s")
-    plain_agree = bool(np.array_equal(lab_p, lab_b))
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(0)
+        torch.cuda.synchronize()
+        tp2 = time.perf_counter()
+        ms_plain = (tp2 - tp1) * 1e3 / args.plain_steps
+        lab_p = out_l.cpu().numpy()
+        w_p = out_w.cpu().numpy()
+        log(f"plain: {ms_plain:.3f} ms/step, {pairs / (ms_plain / 1e3):.3e} evals/s")
+        plain_agree = bool(np.array_equal(lab_p, lab_b))
 
     # work counters of one (untimed) instrumented pass
     stats = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device=dev)
@@ -454,11 +483,25 @@ def main():
                                "launches_per_step": per,
                                "work": f"{st['near_pairs']} near pairs, {st['splits']} splits x (6n+15) + "
                                        f"{st['leaves']} leaves x 11 = {st['near_flops']} flops per step"}
+    # the same kernels timed in steps without the overlap (each kernel alone on the GPU)
+    rooflines_serial = {}
+    if kern_serial:
+        ks = {k: {"launches": n, "avg_ms": t / max(n, 1)} for k, (n, t) in kern_serial.items()}
+        for k, work in (("k_far", FLOPS_PER_PAIR * pairs), ("k_near", st["near_flops"])):
+            if k in ks:
+                per = ks[k]["launches"] / args.serial_steps
+                ms = ks[k]["avg_ms"]
+                a = work / per / (ms / 1e3)
+                rooflines_serial[k] = {"achieved": a / 1e12, "frac": a / PEAK_FP64_VALU, "avg_launch_ms": ms,
+                                       "launches_per_step": per}
     traffic = measured_traffic()
     for k, r in rooflines.items():
         r["traffic"] = traffic.get(k)
     dom = max(rooflines, key=lambda k: rooflines[k]["avg_launch_ms"] * rooflines[k]["launches_per_step"])
     roofline = dict(rooflines[dom], kernel=dom)
+    roofline["note"] = ("launches of the timed steps; the near launches share the CUs with far phases (the "
+                        "overlapped passes), so each lasts longer than alone: roofline_serial times the same "
+                        "kernels in steps without the overlap")
 
     # CPU oracle on a bounded sample of the same workload; also the parity check
     cpu = None
@@ -532,6 +575,7 @@ def main():
         "work": st,
         "roofline": roofline,
         "rooflines": rooflines,
+        "roofline_serial": {"ms_per_step": ms_serial, "kernels": rooflines_serial},
         "cpu_baseline": cpu,
         "configs": sections,
     }
