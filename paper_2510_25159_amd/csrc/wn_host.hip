@@ -561,13 +561,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->pt.face = (const PFace*)(base + o_pface);
     }
     // side stream of the overlapped passes (none: no overlap)
-    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
-        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-        if (h->side) (void)hipStreamDestroy(h->side);
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
         h->side = nullptr;
-        h->ev_fork = h->ev_join = nullptr;
         (void)hipGetLastError();
     }
     *out = h;
@@ -576,8 +571,6 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
 
 void wn_destroy_faces(wn_faces* h) {
     if (!h) return;
-    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->dmem) (void)hipFree(h->dmem);
     delete h;
@@ -762,6 +755,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     // the far/near overlap is for the plain batched FP64 query (not binned, not
     // captured into a plan, no work counters)
     sc.near_lo = nullptr;
+    sc.near_join = nullptr;
     const int64_t* ovl = (!binned && !preset && !q.stats && prec == WN_PREC_FP64) ? p->face_point_offsets_host : nullptr;
     e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st, ovl);
     NearQueue nq = sc.nq;
@@ -788,9 +782,16 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
             e = launch_near(h->sg, pts, nq, sc.out, h->eps2, (int64_t)h->cu_count * h->bpc_near, Stats{nullptr},
                             h->pt.seg_periodic, nullptr, st, sc.near_lo, nullptr);
         }
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_join, 0);
     } else if (e == hipSuccess) {
         e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st);
+    }
+    if (sc.near_join) {
+        // join the side stream (errors included: the scratch is released on st)
+        const hipError_t ej = hipStreamWaitEvent(st, sc.near_join, 0);
+        if (ej != hipSuccess) (void)hipStreamSynchronize(h->side);
+        if (e == hipSuccess) e = ej;
+        (void)hipEventDestroy(sc.near_join);
+        sc.near_join = nullptr;
     }
     if (e == hipSuccess && h->num_periodic > 0) {
         // periodic queries that lost a near pair: recomputed in line over the
@@ -912,7 +913,11 @@ static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, cons
     rk[kOverlapPhases] = Fp;
     unsigned long long* marks = reinterpret_cast<unsigned long long*>(sc.counters + 16);
     const int64_t side_grid = std::max<int64_t>(1, (int64_t)h->cu_count * h->bpc_near / 2);
-    hipError_t e = hipSuccess;
+    // events of this call only (queries on one handle from several threads
+    // share the side stream, never an event)
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
     for (int k = 0; k < kOverlapPhases && e == hipSuccess; ++k) {
         {
             ProfScope ps(prof, WN_KERNEL_FAR, st);
@@ -922,15 +927,30 @@ static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, cons
         }
         if (k == kOverlapPhases - 1) break;
         if (e == hipSuccess) e = launch_queue_mark(sc.nq.count, marks + k, st);
-        if (e == hipSuccess) e = hipEventRecord(h->ev_fork, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
+        if (e == hipSuccess) e = hipEventRecord(fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, fork, 0);
         if (e == hipSuccess) {
             ProfScope ps(prof, WN_KERNEL_NEAR, h->side);
             e = launch_near(h->sg, pts, sc.nq, sc.out, h->eps2, side_grid, Stats{nullptr}, h->pt.seg_periodic,
                             nullptr, h->side, k == 0 ? nullptr : marks + k - 1, marks + k);
         }
     }
-    if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->side);
+    // The join is recorded whatever happened, so that the query stream always
+    // waits for the side stream's work before the scratch is released; if
+    // even that fails, the host waits for the side stream.
+    if (join) {
+        const hipError_t ej = hipEventRecord(join, h->side);
+        if (ej == hipSuccess) {
+            sc.near_join = join;
+        } else {
+            (void)hipStreamSynchronize(h->side);
+            (void)hipEventDestroy(join);
+        }
+        if (e == hipSuccess) e = ej;
+    }
+    // a destroyed event's recorded work still completes, and waits already
+    // enqueued on it still hold
+    if (fork) (void)hipEventDestroy(fork);
     if (e == hipSuccess) sc.near_lo = marks + kOverlapPhases - 2;
     return e;
 }

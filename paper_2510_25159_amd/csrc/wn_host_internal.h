@@ -29,10 +29,9 @@ struct wn_faces {
     std::vector<int32_t> h_dom;
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
     std::vector<int32_t> h_ord_plan;  // ft_plan.order on the host
-    // side stream of the overlapped far/near passes (default priority) and
-    // its fork / join events; null when they could not be created
+    // side stream of the overlapped far/near passes (default priority); null
+    // when it could not be created
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct wn_profile {
@@ -65,6 +64,7 @@ struct Scratch {
     NearQueue nq{};
     Out out{};
     const unsigned long long* near_lo = nullptr;  // set by an overlapped far pass: the final near pass starts here
+    hipEvent_t near_join = nullptr;               // ... and waits for this (the side stream's near passes)
     uint32_t* perm = nullptr;  // spatial order of the periodic faces' points (periodic face sets)
     // binned schedule
     uint2* qs2 = nullptr;

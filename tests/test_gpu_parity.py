@@ -328,3 +328,49 @@ def test_overlapped_far_near_match_serial(torch_cuda, c2_small, qpw):
     ok = l1 < 2
     assert np.max(np.abs(w1[ok] - w2[ok])) <= 1e-12
     compare(w1, l1, w_o, n_o)
+
+
+def test_concurrent_queries_share_a_handle(torch_cuda, c2_small):
+    """Two host threads run overlapped queries on one handle, each on its own
+    stream (the handle's side stream is shared, the fork / join events are
+    per call): every result equals the single-thread one."""
+    import threading
+
+    from paper_2510_25159_amd import wn
+
+    torch = torch_cuda
+    f, q, _, _ = c2_small
+    fs = wn.FaceSet(f)
+    dev = torch.device("cuda:0")
+    u = torch.from_numpy(q.u).to(dev)
+    v = torch.from_numpy(q.v).to(dev)
+    offs = torch.from_numpy(q.face_point_offsets).to(dev)
+    w_ref, l_ref = fs.query(u, v, offs, q.face_point_offsets, schedule=1, queries_per_wg=1024)
+    torch.cuda.synchronize()
+    w_ref, l_ref = w_ref.cpu().numpy(), l_ref.cpu().numpy()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    got, errors = [[], []], []
+
+    def work(i):
+        try:
+            s = streams[i]
+            with torch.cuda.stream(s):
+                outs = [fs.query(u, v, offs, q.face_point_offsets, schedule=1, queries_per_wg=1024, stream=s)
+                        for _ in range(4)]
+                s.synchronize()
+                got[i] = [(w.cpu().numpy(), lab.cpu().numpy()) for w, lab in outs]
+        except Exception as exc:  # reported by the main thread
+            errors.append(repr(exc))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    ok = l_ref < 2
+    for per in got:
+        assert len(per) == 4
+        for w, lab in per:
+            assert np.array_equal(lab, l_ref)
+            assert np.max(np.abs(w[ok] - w_ref[ok])) <= 1e-12
