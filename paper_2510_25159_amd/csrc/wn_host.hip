@@ -359,6 +359,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
             longest = std::max(longest, ((tree[r].skip & ~kTreeRoot) - r + 1) / 2);  // 2m - 1 nodes
         (longest >= kTreeAutoSegs ? ord_tree : ord_flat).push_back(f);
     }
+    h->h_ord_flat = ord_flat;
     std::stable_sort(ord_per.begin(), ord_per.end(), by_size);
     h->per_pos.assign((size_t)F, 0);
     for (size_t r = 0; r < ord_per.size(); ++r) h->per_pos[ord_per[r]] = (int32_t)r;
@@ -892,9 +893,9 @@ int binning_grid(const wn_faces* h) { return std::min(1024, std::max(1, h->cu_co
 // write disjoint queries, so the results are those of the serial passes.
 constexpr int kOverlapPhases = 3;
 
-static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, const Points& pts, int qpl, int64_t grid,
-                                      const int64_t* host_offs, Scratch& sc, wn_profile* prof, hipStream_t st) {
-    const std::vector<int32_t>& ord = h->h_ord_plan;
+static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, const std::vector<int32_t>& ord,
+                                      const Points& pts, int qpl, int64_t grid, const int64_t* host_offs, Scratch& sc,
+                                      wn_profile* prof, hipStream_t st) {
     const int Fp = (int)ord.size();
     auto pairs = [&](int r) {
         const int f = ord[r];
@@ -977,9 +978,10 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
         const int* bp = h->bpc_far[mixed ? 1 : 0];
         const int bpc = qpl > 1 ? h->bpc_farq[qpl] : (qg == 64 ? bp[0] : (qg == 128 ? bp[1] : bp[2]));
         const int64_t grid = persistent ? (int64_t)h->cu_count * bpc : sc.max_items;
-        if (e == hipSuccess && qpl > 1 && persistent && tree == 0 && host_offs && h->side &&
-            flat_ft.num_faces >= kOverlapPhases) {
-            e = far_near_overlapped(h, flat_ft, pts, qpl, grid, host_offs, sc, prof, st);
+        if (e == hipSuccess && qpl > 1 && persistent && host_offs && h->side && flat_ft.num_faces >= kOverlapPhases) {
+            // (tree == 2: the hierarchy faces' entries go to the final near pass)
+            e = far_near_overlapped(h, flat_ft, tree == 2 ? h->h_ord_flat : h->h_ord_plan, pts, qpl, grid,
+                                    host_offs, sc, prof, st);
         } else if (e == hipSuccess) {
             ProfScope ps(prof, WN_KERNEL_FAR, st);
             if (qpl > 1)

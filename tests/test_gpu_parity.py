@@ -330,6 +330,29 @@ def test_overlapped_far_near_match_serial(torch_cuda, c2_small, qpw):
     compare(w1, l1, w_o, n_o)
 
 
+def test_overlapped_with_auto_hierarchy(torch_cuda, oracle_lib):
+    """Automatic hierarchy with a 720-segment loop (tree walk) beside short
+    loops (flat scan): the flat faces' far pass overlaps its near passes, the
+    tree face's near entries go to the final near pass; same labels as the
+    serial passes, and both match the oracle."""
+    k = np.arange(720) * (2 * np.pi / 720)
+    r = 1.0 + 0.3 * np.cos(7 * k)
+    star = C.polygon(np.column_stack([r * np.cos(k), r * np.sin(k)]))
+    sq = C.polygon([[-1, -1], [1, -1], [1, 1], [-1, 1]])
+    faces = W.faces_from_loops([[C.circle_arcs(1.0)], [star], [sq], [C.circle_arcs(1.0), C.circle_arcs(0.4, cw=True)],
+                                [C.polygon(np.column_stack([np.cos(k[::18]), np.sin(k[::18])]))]])
+    rng = np.random.default_rng(21)
+    q = W.queries_for_faces([rng.uniform(-1.5, 1.5, (n, 2)) for n in (3000, 5000, 2500, 4000, 1500)])
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    w1, l1 = run_wn(faces, q, schedule=1, queries_per_wg=1024, path_hierarchy=2)
+    w2, l2 = run_wn(faces, q, schedule=1, queries_per_wg=1024, path_hierarchy=2, offsets_host=False)
+    assert np.array_equal(l1, l2)
+    ok = l1 < 2
+    assert np.max(np.abs(w1[ok] - w2[ok])) <= 1e-12
+    st = compare(w1, l1, w_o, n_o)
+    assert st["compared"] > 0.99 * q.num_points
+
+
 def test_concurrent_queries_share_a_handle(torch_cuda, c2_small):
     """Two host threads run overlapped queries on one handle, each on its own
     stream (the handle's side stream is shared, the fork / join events are
