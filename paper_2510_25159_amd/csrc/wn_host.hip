@@ -882,20 +882,22 @@ int binning_grid(const wn_faces* h) { return std::min(1024, std::max(1, h->cu_co
 
 // Far and near passes overlapped (batched FP64, planar flat scan).  The
 // planar faces (rank order: largest first) are split into kOverlapPhases runs
-// at the pair-count fractions kOverlapCut / 20: the first half of the pairs,
-// the next 45 % and the last 5 %.  The last run's near pass has no far pass
-// left to share the CUs with, so that run is kept small.  After the far pass
-// over run k (on st) the queue's count is marked, and the near pass over run
-// k's entries runs on the side stream while the far pass over run k + 1 runs
-// on st.  The far phases after the first and the side near passes take half
+// at the pair-count fractions kOverlapCut / 20: 45 %, 35 %, 10 % and 10 % of
+// the pairs.  The last run's near pass has no far pass left to share the CUs
+// with, so the last runs are small; the last far phase still has to be long
+// enough to cover the previous run's near pass (on a batch of 2,000 faces,
+// last runs of 3-5 % of the pairs were slower).  After the far pass over run
+// k (on st) the queue's count is marked, and the near pass over run k's
+// entries runs on the side stream while the far pass over run k + 1 runs on
+// st.  The far phases after the first and the side near passes take half
 // the persistent grid each, so that both are resident (a persistent kernel on
 // the whole grid would hold every slot).  The last run's entries, and those
 // of any later far pass, go to the final near pass on st (from sc.near_lo),
 // which joins the side stream.  The near passes read disjoint queue ranges
 // and the phases write disjoint queries, so the results are those of the
 // serial passes.
-constexpr int kOverlapPhases = 3;
-constexpr int kOverlapCut[kOverlapPhases - 1] = {10, 19};  // twentieths of the pairs
+constexpr int kOverlapPhases = 4;
+constexpr int kOverlapCut[kOverlapPhases - 1] = {9, 16, 18};  // twentieths of the pairs
 
 static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, const std::vector<int32_t>& ord,
                                       const Points& pts, int qpl, int64_t grid, const int64_t* host_offs, Scratch& sc,
