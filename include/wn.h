@@ -24,6 +24,12 @@
  *  - A wn_faces handle is immutable after creation: concurrent wn_query calls
  *    on different streams with the same handle are safe.  Each call allocates
  *    its own stream-ordered scratch memory.
+ *  - Given host offsets (face_point_offsets_host), the batched FP64 schedule
+ *    runs near passes of early face runs on a second stream that the handle
+ *    owns (default priority), forked from `stream` and joined back to it
+ *    before the call's work on `stream` ends, so ordering on `stream` holds as
+ *    for any other call.  Concurrent calls on one handle share that stream:
+ *    their side passes then run one after another, with the same results.
  */
 #ifndef WN_H
 #define WN_H
