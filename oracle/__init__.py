@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["wn_oracle.c", "wn_oracle_core.inc", "wn_oracle_periodic.inc"]
+_SOURCES = ["wn_oracle.c", "wn_oracle_core.inc", "wn_oracle_periodic.inc", "wn_oracle_alg1.inc"]
 _lib = None
 
 
@@ -44,6 +44,11 @@ def _load():
         lib.wno_segment_winding.restype = ctypes.c_double
         lib.wno_segment_winding.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_int32, P]
+        lib.wno_alg1_pairs.restype = ctypes.c_int
+        lib.wno_alg1_pairs.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_double,
+                                       ctypes.c_int32, P]
+        lib.wno_alg1_bound.restype = ctypes.c_double
+        lib.wno_alg1_bound.argtypes = [P, P, P, ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -110,3 +115,55 @@ def segment_winding(cp, w, x, y, long_double: bool = False):
     r = lib.wno_segment_winding(_ptr(cu), _ptr(cv), _ptr(cw), len(cp) - 1, float(x), float(y),
                                 1 if long_double else 0, ctypes.byref(near))
     return r, near.value
+
+
+def alg1_pairs(faces, seg, x, y, eps: float = 1e-10, nthreads: int | None = None):
+    """Alg. 1 (Sec. 4.1, sub-segment bound of Sec. 4.2) run recursively on
+    (query, segment) pairs: pair i is point (x[i], y[i]) against global
+    segment seg[i] of ``faces`` (planar coordinates).  Returns a dict of
+    arrays: depth (deepest tested level, root = 0), onb (an evaluated curve
+    point within eps), splits, leaves, margin_abs and margin_rel (the
+    smallest |d1 + d2 - B (b - a)| over the tested nodes, absolute and
+    relative to B (b - a))."""
+    lib = _load()
+    sco = np.ascontiguousarray(faces.seg_cp_offsets, dtype=np.int64)
+    cu = np.ascontiguousarray(faces.cp_u, dtype=np.float64)
+    cv = np.ascontiguousarray(faces.cp_v, dtype=np.float64)
+    cw = None if faces.cp_w is None else np.ascontiguousarray(faces.cp_w, dtype=np.float64)
+    sg = np.ascontiguousarray(seg, dtype=np.int32)
+    px = np.ascontiguousarray(x, dtype=np.float64)
+    py = np.ascontiguousarray(y, dtype=np.float64)
+    n = len(sg)
+    out = np.empty((n, 6), dtype=np.float64)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    st = lib.wno_alg1_pairs(len(sco) - 1, _ptr(sco), _ptr(cu), _ptr(cv), _ptr(cw), n, _ptr(sg), _ptr(px), _ptr(py),
+                            float(eps), int(nthreads), _ptr(out))
+    if st != 0:
+        raise OracleError(f"alg1 mirror returned status {st}")
+    return {"depth": out[:, 0].astype(np.int32), "onb": out[:, 1] != 0, "splits": out[:, 2].astype(np.int64),
+            "leaves": out[:, 3].astype(np.int64), "margin_abs": out[:, 4], "margin_rel": out[:, 5]}
+
+
+def alg1_segment(cp, w, x, y, eps: float = 1e-10):
+    """alg1_pairs for one segment given by its control points [n+1, 2] (and
+    weights or None) against the points x, y."""
+    from types import SimpleNamespace
+
+    cp = np.asarray(cp, dtype=np.float64)
+    n = len(cp) - 1
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    y = np.atleast_1d(np.asarray(y, dtype=np.float64))
+    f = SimpleNamespace(seg_cp_offsets=np.array([0, n + 1], dtype=np.int64), cp_u=cp[:, 0].copy(),
+                        cp_v=cp[:, 1].copy(), cp_w=None if w is None else np.asarray(w, dtype=np.float64))
+    return alg1_pairs(f, np.zeros(len(x), dtype=np.int32), x, y, eps, nthreads=1)
+
+
+def alg1_bound(cp, w=None) -> float:
+    """The bound B (Lemma 1, App. A.1) as the depth mirror computes it."""
+    lib = _load()
+    cp = np.asarray(cp, dtype=np.float64)
+    cu = np.ascontiguousarray(cp[:, 0])
+    cv = np.ascontiguousarray(cp[:, 1])
+    cw = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    return lib.wno_alg1_bound(_ptr(cu), _ptr(cv), _ptr(cw), len(cp) - 1)

@@ -20,6 +20,11 @@
  * branch and bound on de Casteljau pieces) or when that could not be decided;
  * 0 when its distance to every curve (copy) is certified >= near_tol.
  *
+ * Alg. 1 depth mirror (wn_oracle_alg1.inc): the recursion of Alg. 1 itself,
+ * run per (query, segment) pair in FP64 to report the depth, split and leaf
+ * counts the method reaches (pinned by exact rational arithmetic on small
+ * curves and by the distance bounds of the termination argument).
+ *
  * parity: the planar routine is pinned by closed forms, the long double
  * twin and quadrature; the periodic routine by closed-form straight bands on
  * cylinders and tori, lattice-translation, seam re-cutting and window
@@ -156,6 +161,7 @@ static int planar_near(const orc_faces* fc, int f, double x, double y, double to
 }
 
 #include "wn_oracle_periodic.inc"
+#include "wn_oracle_alg1.inc"
 
 /* ------------------------------------------------------------------------
  * Threaded driver
