@@ -441,6 +441,27 @@ wn_status wn_predictor_predict(const wn_predictor* p, const float* features, int
 wn_status wn_pair_features(const wn_faces* faces, const wn_points* points, const int32_t* pair_point,
                            const int32_t* pair_segment, int64_t n, float* out, void* stream);
 
+/* The near pairs of a query and the depth Alg. 1 reaches on each (Sec. 4.1,
+ * Alg. 1; depth as in wn_query_opts.depth_log: the deepest tested level,
+ * 0 = the whole segment).  Runs the batched FP64 far pass and the near pass
+ * of the batched schedule, with its passes in series, and copies out the
+ * near-pair queue: pair k is point pair_point[k] of `points` against global
+ * segment pair_segment[k], whose depth is pair_depth[k].  The queue's order
+ * follows the far pass's scheduling, not the points' order.
+ *   capacity       entries the outputs hold (>= 0)
+ *   pair_point, pair_segment  device int32 [capacity]; pair_depth device uint8
+ *                  [capacity]; pair_shift device double [capacity][2] or NULL:
+ *                  the translation subtracted from the point for a periodic
+ *                  copy (zero for planar pairs)
+ *   out_count      host: the number of near pairs (entries beyond capacity are
+ *                  not written)
+ * Diagnostics and training data: allocates its scratch and synchronizes
+ * `stream`.  WN_E_NOMEM when the near pairs exceed the internal queue
+ * (8 N + 65536 entries, or capacity if larger). */
+wn_status wn_near_pairs(const wn_faces* faces, const wn_points* points, int64_t capacity, int32_t* pair_point,
+                        int32_t* pair_segment, uint8_t* pair_depth, double* pair_shift, int64_t* out_count,
+                        void* stream);
+
 /* Plans: a preallocated batched query captured once into a HIP graph.  The
  * caller owns the point buffers (`points`: device u, v with stride, device
  * per-face offsets; points->num_points is the capacity) and the outputs

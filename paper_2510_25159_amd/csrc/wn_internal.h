@@ -182,6 +182,8 @@ hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out,
                        Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st,
                        const unsigned long long* q_lo = nullptr, const unsigned long long* q_hi = nullptr);
 hipError_t launch_queue_mark(const unsigned long long* count, unsigned long long* mark, hipStream_t st);
+// Queue entries [0, n) -> their query and segment indices (diagnostics).
+hipError_t launch_split_pairs(const uint2* qs, int64_t n, int32_t* point, int32_t* segment, hipStream_t st);
 hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, int32_t nf, hipStream_t st);
 hipError_t launch_redo(const Segs& sg, const FaceTab& ft, const Points& pts, Out out, double eps2,
                        const NearQueue& nq, int64_t max_grid, hipStream_t st);

@@ -1099,6 +1099,21 @@ hipError_t launch_queue_mark(const unsigned long long* count, unsigned long long
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kWG) void k_split_pairs(const uint2* qs, int64_t n, int32_t* point, int32_t* segment) {
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+        const uint2 e = qs[i];
+        point[i] = (int32_t)e.x;
+        segment[i] = (int32_t)e.y;
+    }
+}
+
+hipError_t launch_split_pairs(const uint2* qs, int64_t n, int32_t* point, int32_t* segment, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>((n + kWG - 1) / kWG, 65536);
+    hipLaunchKernelGGL(k_split_pairs, dim3((unsigned)g), dim3(kWG), 0, st, qs, n, point, segment);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const Points& pts, Out out, int64_t q0, int64_t q1, int32_t nf, hipStream_t st) {
     if (q1 <= q0) return hipSuccess;
     const int64_t g = (q1 - q0 + kWG - 1) / kWG;

@@ -143,6 +143,52 @@ wn_status wn_pair_features(const wn_faces* h, const wn_points* pts, const int32_
     return hip_status(launch_pair_features(h->sg, P, pp, ps, n, h->eps, out, (hipStream_t)stream));
 }
 
+wn_status wn_near_pairs(const wn_faces* h, const wn_points* p, int64_t capacity, int32_t* pair_point,
+                        int32_t* pair_segment, uint8_t* pair_depth, double* pair_shift, int64_t* out_count,
+                        void* stream) {
+    if (!h || !p || !out_count || capacity < 0) return WN_E_INVALID;
+    if (capacity > 0 && (!pair_point || !pair_segment || !pair_depth)) return WN_E_INVALID;
+    const int64_t N = p->num_points;
+    if (N < 0 || N >= 0x7fffffffll) return WN_E_INVALID;
+    *out_count = 0;
+    if (N == 0) return WN_OK;
+    if (!p->u || !p->v || p->stride < 1 || !p->face_point_offsets) return WN_E_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    const Points pts{p->u, p->v, p->stride, p->face_point_offsets, N};
+    // a queue that holds every near pair of these points (a pair that does not
+    // fit would be recomputed in line and never logged)
+    const int64_t cap = std::min<int64_t>(std::max<int64_t>(8 * N + 65536, capacity), (int64_t)1 << 34);
+    Scratch sc;
+    hipError_t e = scratch_alloc(h, N, cap, false, false, nullptr, nullptr, h->rule, sc, st, true);
+    if (e != hipSuccess) return hip_status(e);
+    uint8_t* d_depth = nullptr;
+    e = hipMallocAsync((void**)&d_depth, (size_t)cap, st);
+    if (e == hipSuccess) e = far_passes(h, pts, 256, 1, false, 0, sc, nullptr, st);
+    if (e == hipSuccess) e = near_pass(h, pts, sc.nq, sc.out, nullptr, d_depth, nullptr, st);
+    unsigned long long cnt = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&cnt, sc.nq.count, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const bool overflow = cnt > (unsigned long long)cap;
+    const int64_t n = std::min<int64_t>((int64_t)std::min<unsigned long long>(cnt, (unsigned long long)cap), capacity);
+    if (e == hipSuccess && n > 0) {
+        e = launch_split_pairs(sc.nq.qs, n, pair_point, pair_segment, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(pair_depth, d_depth, (size_t)n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && pair_shift) {
+            if (sc.nq.shift)
+                e = hipMemcpyAsync(pair_shift, sc.nq.shift, (size_t)n * 16, hipMemcpyDeviceToDevice, st);
+            else
+                e = hipMemsetAsync(pair_shift, 0, (size_t)n * 16, st);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFreeAsync(d_depth, st);
+    scratch_free(sc, st);
+    if (e != hipSuccess) return hip_status(e);
+    if (overflow) return WN_E_NOMEM;
+    *out_count = (int64_t)cnt;
+    return WN_OK;
+}
+
 wn_status wn_predictor_train(wn_predictor* pr, const wn_faces* h, const wn_points* p, const wn_train_opts* opts_in,
                              wn_train_report* report, void* stream) {
     if (!pr || !h || !p) return WN_E_INVALID;

@@ -48,7 +48,13 @@ def build_pool(n_star: int = 512, n_periodic: int = 512, seed: int = W.SEED_C5):
 
 
 def run(rate: float = 2000.0, duration: float = 10.0, budget_gib: float = 4.0, capacity: int = 1 << 23,
-        seed: int = W.SEED_C5, pool_points: int = 1 << 24, verbose: bool = False) -> dict:
+        seed: int = W.SEED_C5, pool_points: int = 1 << 24, verbose: bool = False, sample_every: int = 0,
+        sample_points: int = 4096) -> dict:
+    """Run the serving loop.  With sample_every = k > 0, one seeded request of
+    every k-th batch is kept for checking: its face, its first sample_points
+    points and the served winding numbers and labels, copied back once the
+    batch has completed (before the next replay overwrites them); they are
+    returned under "samples" (host arrays, not part of the timing report)."""
     import torch
 
     dev = torch.device("cuda:0")
@@ -92,6 +98,8 @@ def run(rate: float = 2000.0, duration: float = 10.0, budget_gib: float = 4.0, c
 
     lat = np.full(n_req, np.nan)
     batches = []
+    samples = []
+    srng = np.random.default_rng(seed + 17)
     pending, admitted = deque(), deque()
     used = 0
     nxt = 0
@@ -110,8 +118,14 @@ def run(rate: float = 2000.0, duration: float = 10.0, budget_gib: float = 4.0, c
             used += Q[i] * BYTES_PER_POINT
             admitted.append(i)
         if busy is not None and busy[0].query():
-            ev, ids, nbytes = busy
+            ev, ids, nbytes, pick = busy
             t_done = t0_ev.elapsed_time(ev) / 1e3
+            if pick is not None:
+                i, pos, k = pick
+                pu, pv = pools[kinds[face[i]]]
+                samples.append({"face": int(face[i]), "u": pu[start[i]:start[i] + k].copy(),
+                                "v": pv[start[i]:start[i] + k].copy(),
+                                "w": ow[pos:pos + k].cpu().numpy(), "lab": ol[pos:pos + k].cpu().numpy()})
             lat[ids] = t_done - t_arr[ids]
             used -= nbytes
             done += len(ids)
@@ -126,8 +140,12 @@ def run(rate: float = 2000.0, duration: float = 10.0, budget_gib: float = 4.0, c
                 raise RuntimeError("request exceeds plan capacity")
             ids = np.array(ids)
             order = ids[np.argsort(face[ids], kind="stable")]
+            pick = None
+            pick_req = order[srng.integers(0, len(order))] if sample_every and len(batches) % sample_every == 0 else -1
             pos = 0
             for i in order:
+                if i == pick_req:
+                    pick = (int(i), pos, int(min(Q[i], sample_points)))
                 pu, pv = pools[kinds[face[i]]]
                 su[pos:pos + Q[i]] = pu[start[i]:start[i] + Q[i]]
                 sv[pos:pos + Q[i]] = pv[start[i]:start[i] + Q[i]]
@@ -141,7 +159,7 @@ def run(rate: float = 2000.0, duration: float = 10.0, budget_gib: float = 4.0, c
             plan.launch(stream)
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(stream)
-            busy = (ev, order, int(np.sum(Q[order])) * BYTES_PER_POINT)
+            busy = (ev, order, int(np.sum(Q[order])) * BYTES_PER_POINT, pick)
             batches.append((len(order), pos))
             continue
         if busy is None and not admitted and nxt < n_req:
@@ -166,6 +184,9 @@ def run(rate: float = 2000.0, duration: float = 10.0, budget_gib: float = 4.0, c
     }
     if verbose:
         print(json.dumps(res), flush=True)
+    if sample_every:
+        res["samples"] = samples
+        res["pool_faces"] = faces
     return res
 
 

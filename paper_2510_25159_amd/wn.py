@@ -28,7 +28,7 @@ EXPORTS = [
     "wn_predictor_create", "wn_predictor_destroy", "wn_predictor_train", "wn_predictor_get_params",
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
     "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy", "wn_nurbs_to_bezier",
-    "wn_classify_grid", "wn_classify_surfaces", "wn_create_faces_nurbs",
+    "wn_classify_grid", "wn_classify_surfaces", "wn_create_faces_nurbs", "wn_near_pairs",
 ]
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -170,6 +170,9 @@ def lib():
         L.wn_classify_surfaces.restype = ctypes.c_int
         L.wn_classify_surfaces.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(wn_points), _P, _P,
                                            ctypes.POINTER(wn_query_opts), _P]
+        L.wn_near_pairs.restype = ctypes.c_int
+        L.wn_near_pairs.argtypes = [_P, ctypes.POINTER(wn_points), ctypes.c_int64, _P, _P, _P, _P,
+                                    ctypes.POINTER(ctypes.c_int64), _P]
         L.wn_get_faces_info.restype = ctypes.c_int
         L.wn_get_faces_info.argtypes = [_P, ctypes.POINTER(wn_faces_info)]
         _lib = L
@@ -523,6 +526,27 @@ class Predictor:
         if st != WN_OK:
             raise WnError(st, "wn_predictor_predict")
         return out
+
+
+def near_pairs(faceset: "FaceSet", u, v, offsets, capacity: int, stream=None):
+    """Near pairs of a query and the depth the near pass reached on each:
+    (point int32 [n], segment int32 [n], depth uint8 [n], shift float64 [n, 2])
+    torch cuda tensors, n = min(count, capacity)."""
+    import torch
+
+    dev = u.device
+    pp = torch.empty(capacity, dtype=torch.int32, device=dev)
+    ps = torch.empty(capacity, dtype=torch.int32, device=dev)
+    pd = torch.empty(capacity, dtype=torch.uint8, device=dev)
+    sh = torch.empty((capacity, 2), dtype=torch.float64, device=dev)
+    cnt = ctypes.c_int64(0)
+    p = _points(u, v, offsets)
+    st = lib().wn_near_pairs(faceset._h, ctypes.byref(p), capacity, pp.data_ptr(), ps.data_ptr(), pd.data_ptr(),
+                             sh.data_ptr(), ctypes.byref(cnt), _stream_ptr(stream))
+    if st != WN_OK:
+        raise WnError(st, "wn_near_pairs")
+    n = min(cnt.value, capacity)
+    return pp[:n], ps[:n], pd[:n], sh[:n]
 
 
 def pair_features(faceset: "FaceSet", u, v, offsets, pair_point, pair_segment, stream=None):
