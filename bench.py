@@ -9,8 +9,13 @@ of a curve.  Inputs sit in HBM before the timed region starts.
 Prints one JSON line (rank 0).  `value` is point x segment pair evaluations
 per second of the batched schedule; the plain schedule (one launch per face,
 in-line recursion) is reported beside it, together with queries/s, the
-dominant kernel's roofline position (HIP-event durations on the query
-stream) and the CPU oracle's throughput on a bounded sample.
+CPU oracle's throughput on a bounded sample (and single-threaded on config
+1), and per-kernel roofline positions.  `roofline` is the dominant kernel
+of the path with every kernel alone on the GPU (steps whose far and near
+passes run in series): algorithmic flops per launch over its HIP-event
+launch duration on the stream it runs on, against the FP64 VALU peak, and
+its measured HBM bytes per launch against 8 TB/s.  The same kernels'
+launches inside the overlapped timed steps are under rooflines_overlapped.
 """
 from __future__ import annotations
 
@@ -76,6 +81,20 @@ def measured_traffic() -> dict:
         if k.startswith("traffic_bytes_per_launch "):
             out[k.split()[1]] = float(v)
     return out
+
+
+def host_cpu() -> dict:
+    """CPU model and logical CPU count of the host (from /proc/cpuinfo)."""
+    model, n = None, 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    n += 1
+                    model = model or ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"model": model, "nproc": n or os.cpu_count()}
 
 
 def _dev_queries(torch, q):
@@ -306,8 +325,12 @@ def main():
     ap.add_argument("--qpw", type=int, default=0)
     ap.add_argument("--policy", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true", help="skip the extra sections")
-    ap.add_argument("--serial-steps", type=int, default=5,
-                    help="timed steps without the far/near overlap, for per-kernel rooflines")
+    ap.add_argument("--serial-steps", type=int, default=10,
+                    help="timed steps with the far and near passes in series (each kernel alone on the GPU): "
+                         "the per-kernel rooflines")
+    ap.add_argument("--overlap", type=int, default=1,
+                    help="1: the timed steps overlap near and far passes of different face runs (default); "
+                         "0: the timed steps run the passes in series (profiling the kernels alone)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed batched steps and the work counters (profiling runs)")
     ap.add_argument("--sections", default="", help="comma list of the extra sections to run (default: all)")
@@ -345,8 +368,12 @@ def main():
     stream = torch.cuda.current_stream()
     prof = wn.Profile(capacity=16 * (args.steps + args.warmup) + 64)
 
+    # host offsets let the library overlap the near passes of early face runs
+    # with the far pass of later ones; without them the passes run in series
+    offs_overlap = q.face_point_offsets if args.overlap else None
+
     def step(schedule, profile=None):
-        fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=schedule, queries_per_wg=args.qpw,
+        fs.query(u, v, offs, offs_overlap, out_w, out_l, schedule=schedule, queries_per_wg=args.qpw,
                  queue_policy=args.policy, profile=profile, stream=stream)
 
     if args.copy_calibration_mib > 0:
@@ -380,7 +407,7 @@ def main():
     # the same steps without the far/near overlap (no host offsets: the passes
     # run one after the other), for rooflines of each kernel on its own
     kern_serial, ms_serial = {}, None
-    if args.serial_steps > 0 and not args.headline_only:
+    if args.serial_steps > 0 and not args.headline_only and args.overlap:
         def step_serial(profile=None):
             fs.query(u, v, offs, None, out_w, out_l, schedule=args.schedule, queries_per_wg=args.qpw,
                      queue_policy=args.policy, profile=profile, stream=stream)
@@ -464,44 +491,48 @@ def main():
     log(f"work counters: {st}")
 
     kernels = {k: {"launches": n, "avg_ms": t / max(n, 1)} for k, (n, t) in kern.items()}
-    rooflines = {}
-    # a step may launch a kernel several times (the overlapped far/near phases):
-    # work per launch = work per step / launches per step
-    if "k_far" in kernels:
-        ms = kernels["k_far"]["avg_ms"]
-        per = kernels["k_far"]["launches"] / args.steps
-        a = FLOPS_PER_PAIR * pairs / per / (ms / 1e3)
-        rooflines["k_far"] = {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-                              "frac": a / PEAK_FP64_VALU, "traffic": None, "avg_launch_ms": ms, "launches_per_step": per,
-                              "work": f"{pairs} pairs x {FLOPS_PER_PAIR} flops (root test + chord) per step"}
-    if "k_near" in kernels:
-        ms = kernels["k_near"]["avg_ms"]
-        per = kernels["k_near"]["launches"] / args.steps
-        a = st["near_flops"] / per / (ms / 1e3)
-        rooflines["k_near"] = {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                               "unit": "TFLOP/s", "frac": a / PEAK_FP64_VALU, "traffic": None, "avg_launch_ms": ms,
-                               "launches_per_step": per,
-                               "work": f"{st['near_pairs']} near pairs, {st['splits']} splits x (6n+15) + "
-                                       f"{st['leaves']} leaves x 11 = {st['near_flops']} flops per step"}
-    # the same kernels timed in steps without the overlap (each kernel alone on the GPU)
-    rooflines_serial = {}
-    if kern_serial:
-        ks = {k: {"launches": n, "avg_ms": t / max(n, 1)} for k, (n, t) in kern_serial.items()}
-        for k, work in (("k_far", FLOPS_PER_PAIR * pairs), ("k_near", st["near_flops"])):
-            if k in ks:
-                per = ks[k]["launches"] / args.serial_steps
-                ms = ks[k]["avg_ms"]
-                a = work / per / (ms / 1e3)
-                rooflines_serial[k] = {"achieved": a / 1e12, "frac": a / PEAK_FP64_VALU, "avg_launch_ms": ms,
-                                       "launches_per_step": per}
     traffic = measured_traffic()
-    for k, r in rooflines.items():
-        r["traffic"] = traffic.get(k)
-    dom = max(rooflines, key=lambda k: rooflines[k]["avg_launch_ms"] * rooflines[k]["launches_per_step"])
-    roofline = dict(rooflines[dom], kernel=dom)
-    roofline["note"] = ("launches of the timed steps; the near launches share the CUs with far phases (the "
-                        "overlapped passes), so each lasts longer than alone: roofline_serial times the same "
-                        "kernels in steps without the overlap")
+    work = {"k_far": (FLOPS_PER_PAIR * pairs, f"{pairs} pairs x {FLOPS_PER_PAIR} flops (root test + chord) per step"),
+            "k_near": (st["near_flops"], f"{st['near_pairs']} near pairs, {st['splits']} splits x (6n+15) + "
+                                         f"{st['leaves']} leaves x 11 = {st['near_flops']} flops per step")}
+
+    def rooflines_of(kern_avg, nsteps):
+        """Per-kernel roofline entries: algorithmic flops per launch (the
+        step's work / launches per step) over the average HIP-event launch
+        duration; HBM bytes per launch from the committed counters."""
+        res = {}
+        for k, (flops, desc) in work.items():
+            if k not in kern_avg:
+                continue
+            n, t = kern_avg[k]
+            ms = t / max(n, 1)
+            per = n / nsteps
+            a = flops / per / (ms / 1e3)
+            tb = traffic.get(k)
+            res[k] = {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                      "frac": a / PEAK_FP64_VALU, "traffic": tb,
+                      "hbm_achieved_GBps": None if tb is None else tb / (ms / 1e3) / 1e9,
+                      "hbm_frac": None if tb is None else tb / (ms / 1e3) / PEAK_HBM,
+                      "avg_launch_ms": ms, "launches_per_step": per, "ms_per_step": ms * per, "work": desc}
+        return res
+
+    # Each kernel alone on the GPU: the steps with the passes in series (with
+    # --overlap 0 these are the timed steps themselves).  The headline entry
+    # is the kernel with the most time per such step, so its launches never
+    # share the GPU with another kernel of the path.
+    if args.overlap:
+        rooflines_serial = rooflines_of(kern_serial, args.serial_steps) if kern_serial else {}
+        rooflines_overlapped = rooflines_of(kern, args.steps)
+    else:
+        rooflines_serial = rooflines_of(kern, args.steps)
+        rooflines_overlapped = {}
+        ms_serial = ms_step
+    roofline = None
+    if rooflines_serial:
+        dom = max(rooflines_serial, key=lambda k: rooflines_serial[k]["ms_per_step"])
+        roofline = dict(rooflines_serial[dom], kernel=dom)
+        roofline["note"] = ("kernel alone on the GPU (far and near passes in series); its launches in the "
+                            "overlapped timed steps are under rooflines_overlapped")
 
     # CPU oracle on a bounded sample of the same workload; also the parity check
     cpu = None
@@ -513,14 +544,27 @@ def main():
         ns = min(args.cpu_sample, N)
         idx = np.sort(rng.choice(N, ns, replace=False))
         pf, su, sv = W.subset_queries(q, idx)
-        cores = min(16, os.cpu_count() or 1)
+        # the process's CPU set, at most the 16 cores one GPU's share of a host has
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        cores = min(16, avail)
         tc = time.perf_counter()
         w_o, near = oracle.query(faces, pf, su, sv, nthreads=cores)
         tcpu = time.perf_counter() - tc
         sample_pairs = int(np.sum(S_f[pf]))
         cpu = {"value": sample_pairs / tcpu, "unit": "evals/s", "cores": cores, "kind": "oracle",
                "sample": f"{ns} points drawn uniformly from the timed set ({sample_pairs:.3e} pairs), "
-                         f"{tcpu:.1f} s"}
+                         f"{tcpu:.1f} s",
+               "host": host_cpu(), "cpus_available": avail}
+        # single thread on config 1 (one face of 64 cubics, 65,536 points): the
+        # paper's per-shape costs (Sec. 5, Table 2) are single-thread timings
+        # of 65,536 samples per shape, on other shapes and another CPU
+        f1, q1 = W.config1()
+        tc = time.perf_counter()
+        oracle.query_faces(f1, q1, nthreads=1)
+        t1 = time.perf_counter() - tc
+        cpu["single_thread_config1"] = {"s_per_shape": t1, "points": q1.num_points, "segments": f1.num_segments,
+                                        "evals_per_s": q1.num_points * f1.num_segments / t1,
+                                        "paper_table2_s_per_shape": {"BG A": 0.095, "OpenClipArt20K": 0.407}}
         far = near == 0
         want = (np.abs(w_o) > 0.5).astype(np.uint8)
         mism = int(np.sum(lab_b[idx][far] != want[far]))
@@ -560,7 +604,8 @@ def main():
                                "(degree 1-5, rational weights U[0.5,2]), 1k-64k points/face, 30% within 1e-3 "
                                "of a curve",
                    "faces": args.faces, "segments": faces.num_segments, "points": N, "pairs": pairs,
-                   "schedule": {0: "plain", 1: "batched"}.get(args.schedule, str(args.schedule)), "eps": 1e-10},
+                   "schedule": {0: "plain", 1: "batched"}.get(args.schedule, str(args.schedule)), "eps": 1e-10,
+                   "overlap": bool(args.overlap)},
         "queries_per_s": N / (ms_step / 1e3),
         "plain": {"ms_per_step": ms_plain, "evals_per_s": pairs / (ms_plain / 1e3),
                   "queries_per_s": N / (ms_plain / 1e3), "labels_equal_batched": plain_agree},
@@ -574,8 +619,8 @@ def main():
         "kernels": kernels,
         "work": st,
         "roofline": roofline,
-        "rooflines": rooflines,
-        "roofline_serial": {"ms_per_step": ms_serial, "kernels": rooflines_serial},
+        "rooflines_serial": {"ms_per_step": ms_serial, "kernels": rooflines_serial},
+        "rooflines_overlapped": {"ms_per_step": ms_step if args.overlap else None, "kernels": rooflines_overlapped},
         "cpu_baseline": cpu,
         "configs": sections,
     }
