@@ -696,16 +696,30 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
 
 // Near-pair state.  The current interval [a, a + 2^-k] is always one that
 // failed its ellipse test (the root is queued for exactly that reason).
+//
+// Deferred intervals.  The traversal goes left first and defers the right
+// half of a split whose halves both failed, so the deferred intervals form a
+// stack whose levels increase from bottom to top, and the one to resume is
+// always the top (the deepest).  An entry holds the deferred interval's two
+// end points (32 B); its level is a bit of `pend`, its left end parameter
+// follows from the current one (deferred_left).  The entries sit in an LDS
+// ring of kNearSlots slots per lane, entry i in slot i mod kNearSlots, so a
+// slot is only reused when more than kNearSlots intervals are pending: a push
+// over a pending entry marks every entry below `lost` as overwritten, and such
+// an entry's end points are evaluated again when it resumes (same parameters,
+// same code, same values).
 struct NodeState {
     Coef c;  // translated by -q: evaluates gamma(t) - q directly
     double B, eta;
-    double a, ax, ay, ra, bx, by, rb;  // current interval: left end, end points relative to q, |.|^2
-    uint64_t pend, stored;             // levels with a deferred right sibling / whose slot still holds it
+    double a, ax, ay, bx, by;  // current interval: left end parameter, end points relative to q
+    uint64_t pend;             // levels of the deferred intervals
     int k;
     int n;         // far children's ray crossings minus the segment chord's (see near_pair)
     int pmax;      // deepest level of this pair
-    int mode;      // 0: split; 1, 2: evaluate the left, right end of a resumed evicted interval
-    uint32_t seg;  // segment (its end point is reloaded when an evicted interval ends at t = 1)
+    int sp;        // deferred intervals on the stack
+    int lost;      // entries below this index were overwritten in the ring
+    int mode;      // 0: split; 1, 2: evaluate the left, right end of a resumed overwritten interval
+    uint32_t seg;  // segment (its end point is reloaded when a resumed interval ends at t = 1)
 };
 
 __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_t s, double qx, double qy) {
@@ -722,15 +736,15 @@ __device__ __forceinline__ void node_init(NodeState& st, const Segs& sg, uint32_
     st.seg = s;
     st.ax = g.p0x - qx;
     st.ay = g.p0y - qy;
-    st.ra = st.ax * st.ax + st.ay * st.ay;
     st.bx = g.pnx - qx;
     st.by = g.pny - qy;
-    st.rb = st.bx * st.bx + st.by * st.by;
     st.n = -ray_cross(st.ax, st.ay, st.bx, st.by);
     st.a = 0.0;
     st.k = 0;
-    st.pend = st.stored = 0;
+    st.pend = 0;
     st.pmax = 0;
+    st.sp = 0;
+    st.lost = 0;
     st.mode = 0;
 }
 
@@ -744,48 +758,46 @@ struct NodeCount {
 // BOTH halves are tested.  A half that passes is a leaf: its chord's ray
 // crossing is taken at once (the sum does not depend on the order).  A half
 // that fails becomes the current interval; when both fail, the right one is
-// deferred.  When neither fails, the deepest deferred interval resumes (it
-// failed its test when its parent was split).  Every step is therefore one
-// curve evaluation: a pair costs as many steps as Alg. 1 has split nodes,
-// and the set of tested nodes, splits and leaves is exactly Alg. 1's.
-// State changes are selects; the memory accesses and the evaluations sit
-// under branches.  Returns true when the pair is finished.
+// deferred.  When neither fails, the top deferred interval resumes (it failed
+// its test when its parent was split).  Every step is therefore one curve
+// evaluation: a pair costs as many steps as Alg. 1 has split nodes (plus two
+// per resumed interval whose entry was overwritten), and the set of tested
+// nodes, splits and leaves is exactly Alg. 1's.  State changes are selects;
+// the memory accesses and the evaluation sit under branches.  `stk` is this
+// lane's slot 0 (slot stride kWave).  Returns true when the pair is finished.
 template <bool COUNT>
 __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* stk, bool& onb, NodeCount& nc,
                                           const Segs& sg, double qx, double qy, bool has) {
-    // The one curve evaluation of the step: the midpoint for a split, or an
-    // end point of a resumed interval whose slot was reused (such a lane
-    // spends two steps re-evaluating them, instead of making the whole wave
-    // run two extra evaluations).
-    const bool m0 = has & (st.mode == 0);
-    const bool capped = m0 & (st.k >= kDepthCap);  // cannot happen for a validated eps
-    const bool sp = m0 & !capped;
+    // The step's one evaluation: the midpoint a + 2^-(k+1) for a split, or an
+    // end point (a, then a + 2^-k) of a resumed overwritten interval.
+    const bool sp = has & (st.mode == 0);
     const bool fl = has & (st.mode == 1), fr = has & (st.mode == 2);
+    const bool capped = sp & (st.k >= kDepthCap);  // cannot happen for a validated eps
     const int k1 = st.k + 1;
-    const double tm = st.a + ldexp(1.0, -k1);
-    const double te = sp ? tm : (fl ? st.a : st.a + ldexp(1.0, -st.k));
+    const double te = fl ? st.a : st.a + ldexp(1.0, fr ? -st.k : -k1);
     const bool at_end = fr & (te == 1.0);
     double mx = 0.0, my = 0.0;
-    if (sp | fl | (fr & !at_end)) bez_eval(st.c, te, mx, my);
+    if ((sp & !capped) | fl | (fr & !at_end)) bez_eval(st.c, te, mx, my);
     if (at_end) {
         const double2 e = seg_end_point(sg, (int)st.seg);
         mx = e.x - qx;
         my = e.y - qy;
     }
+    // squared distances of the end points (recomputed: cheaper than carrying them)
     const double rm = fma(mx, mx, my * my);
+    const double ra = fma(st.ax, st.ax, st.ay * st.ay);
+    const double rb = fma(st.bx, st.bx, st.by * st.by);
     if (COUNT) nc.reeval += (fl | fr) ? 1 : 0;
-    // a resumed interval's re-evaluated end point is installed with the
-    // split's updates below (such a lane does not split in this step)
-    st.mode = fl ? 2 : (fr ? 0 : st.mode);
+    st.mode = fl ? 2 : 0;
     // split
-    const bool hit = sp & (rm < eps2);
+    const bool hit = sp & !capped & (rm < eps2);
     onb |= capped | hit;
     bool fin = capped | hit;
-    const bool go = sp & !hit;
+    const bool go = sp & !capped & !hit;
     // the two halves [a, m] and [m, b] at level k + 1
     const double hb = half_axis2(st.B, st.eta, k1);
-    const bool lfar = outside_ellipse(st.ra, rm, hb);
-    const bool rfar = outside_ellipse(rm, st.rb, hb);
+    const bool lfar = outside_ellipse(ra, rm, hb);
+    const bool rfar = outside_ellipse(rm, rb, hb);
     // n += ray_cross(a, m) for a far left half, ray_cross(m, b) for a far right
     // half, on lane masks: a half's orientation is only computed when some
     // lane's half changes side of the ray's line
@@ -804,39 +816,42 @@ __device__ __forceinline__ bool node_step(NodeState& st, double eps2, double4* s
     const bool both = go & !lfar & !rfar;  // defer the right half, continue left
     const bool left = go & !lfar;          // continue with the left half
     const bool right = go & lfar & !rfar;  // continue with the right half
-    const bool none = go & lfar & rfar;    // resume the deepest deferred interval
-    const uint64_t k1bit = 1ull << k1;
-    if (both) stk[(k1 & (kNearSlots - 1)) * kWave] = make_double4(mx, my, st.bx, st.by);
-    const uint64_t evict = slot_evict_mask(k1);
-    st.stored = both ? ((st.stored & ~evict) | k1bit) : st.stored;
-    st.pend = both ? (st.pend | k1bit) : st.pend;
+    const bool none = go & lfar & rfar;    // resume the top deferred interval
+    // push the right half's end points
+    if (both) stk[(st.sp & (kNearSlots - 1)) * kWave] = make_double4(mx, my, st.bx, st.by);
+    const int lost_push = max(min(st.lost, st.sp), st.sp - (kNearSlots - 1));
+    st.lost = both ? lost_push : st.lost;
+    st.pend = both ? (st.pend | (1ull << k1)) : st.pend;
+    st.sp += both ? 1 : 0;
     st.pmax = (go & (k1 > st.pmax)) ? k1 : st.pmax;
-    st.a = right ? tm : st.a;
-    st.k = (left | right) ? k1 : st.k;
     fin |= none & (st.pend == 0);
     const bool pop = none & (st.pend != 0);
     const int kk = 63 - __clzll(st.pend | 1ull);
-    const uint64_t kbit = 1ull << kk;
-    const bool kept = (st.stored & kbit) != 0;
+    const int top = st.sp - 1;
+    const bool kept = top >= st.lost;
     double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (pop & kept) p = stk[(kk & (kNearSlots - 1)) * kWave];
-    st.pend = pop ? (st.pend & ~kbit) : st.pend;
-    st.stored = pop ? (st.stored & ~kbit) : st.stored;
-    st.a = pop ? deferred_left(st.a, kk) : st.a;
-    st.k = pop ? kk : st.k;
-    st.mode = (pop & !kept) ? 1 : st.mode;  // end points to evaluate again in the next two steps
-    // end points of the next interval: m for a re-evaluated end, for the left
-    // end when continuing right and the right end when continuing left; the
-    // stored pair of a resumed interval; else unchanged (the cases exclude
-    // each other, so each field takes two selects)
+    if (pop & kept) p = stk[(top & (kNearSlots - 1)) * kWave];
+    st.pend = pop ? (st.pend & ~(1ull << kk)) : st.pend;
+    st.sp -= pop ? 1 : 0;
+    st.mode = (pop & !kept) ? 1 : st.mode;
+    st.a = right ? te : (pop ? deferred_left(st.a, kk) : st.a);
+    st.k = (left | right) ? k1 : (pop ? kk : st.k);
+    // end points of the next interval: m for a re-evaluated left end or when
+    // continuing right (left end) / left (right end); the entry on a pop; else
+    // unchanged (the cases exclude each other, so each field takes two selects)
     const bool take_a = fl | right, take_b = fr | left, pk = pop & kept;
     st.ax = take_a ? mx : (pk ? p.x : st.ax);
     st.ay = take_a ? my : (pk ? p.y : st.ay);
-    st.ra = take_a ? rm : (pk ? fma(p.x, p.x, p.y * p.y) : st.ra);
     st.bx = take_b ? mx : (pk ? p.z : st.bx);
     st.by = take_b ? my : (pk ? p.w : st.by);
-    st.rb = take_b ? rm : (pk ? fma(p.z, p.z, p.w * p.w) : st.rb);
     return fin;
+}
+
+// A wave-uniform 64-bit value made visibly uniform (scalar registers).
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 template <typename T_>
@@ -856,9 +871,9 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats,
-                                              const uint8_t* seg_per, uint8_t* entry_depth,
-                                              const unsigned long long* q_lo, const unsigned long long* q_hi) {
+__global__ __launch_bounds__(kWG) void k_near(
+    Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats, const uint8_t* seg_per,
+    uint8_t* entry_depth, const unsigned long long* q_lo, const unsigned long long* q_hi) {
     __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
@@ -872,9 +887,10 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
     const unsigned long long nw = (unsigned long long)gridDim.x * kWavesPerWG;
     const unsigned long long gw = (unsigned long long)blockIdx.x * kWavesPerWG + wave;
     const unsigned long long per = (n - base + nw - 1) / nw;
-    const unsigned long long c_begin = base + gw * per < n ? base + gw * per : n;
-    const unsigned long long c_end = c_begin + per < n ? c_begin + per : n;
-    unsigned long long next = c_begin;  // wave-uniform
+    // wave-uniform bounds and cursor, kept in scalar registers
+    const unsigned long long c_begin = uniform_u64(base + gw * per < n ? base + gw * per : n);
+    const unsigned long long c_end = uniform_u64(c_begin + per < n ? c_begin + per : n);
+    unsigned long long next = c_begin;
     NodeState st;
     bool onb = false, has = false;
     uint32_t q = 0;
@@ -889,7 +905,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
         // refill idle lanes once kRefillMin of them are idle (each refill
         // waits for the gathers of the new pairs' data)
         if (idle && next < c_end && (__popcll(idle) >= kRefillMin || idle == ~0ull)) {
-            const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+            const int rank = lanes_below(idle);
             uint2 e;  // all lanes active here: entry next + rank comes from lane rank of the window
             e.x = (uint32_t)__shfl((int)win.x, rank);
             e.y = (uint32_t)__shfl((int)win.y, rank);
@@ -909,7 +925,7 @@ __global__ __launch_bounds__(kWG) void k_near(Segs sg, Points pts, NearQueue nq,
                     has = true;
                 }
             }
-            next += (unsigned long long)__popcll(idle);
+            next = uniform_u64(next + (unsigned long long)__popcll(idle));
             if (next + lane < c_end) win = nq.qs[next + lane];
         }
         if (!__any(has)) {
