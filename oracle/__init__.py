@@ -46,7 +46,7 @@ def _load():
                                             ctypes.c_int32, P]
         lib.wno_alg1_pairs.restype = ctypes.c_int
         lib.wno_alg1_pairs.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_double,
-                                       ctypes.c_int32, P]
+                                       ctypes.c_int32, ctypes.c_int32, P]
         lib.wno_alg1_bound.restype = ctypes.c_double
         lib.wno_alg1_bound.argtypes = [P, P, P, ctypes.c_int32]
         _lib = lib
@@ -117,14 +117,16 @@ def segment_winding(cp, w, x, y, long_double: bool = False):
     return r, near.value
 
 
-def alg1_pairs(faces, seg, x, y, eps: float = 1e-10, nthreads: int | None = None):
+def alg1_pairs(faces, seg, x, y, eps: float = 1e-10, nthreads: int | None = None, cp_bound: bool = False):
     """Alg. 1 (Sec. 4.1, sub-segment bound of Sec. 4.2) run recursively on
     (query, segment) pairs: pair i is point (x[i], y[i]) against global
     segment seg[i] of ``faces`` (planar coordinates).  Returns a dict of
     arrays: depth (deepest tested level, root = 0), onb (an evaluated curve
     point within eps), splits, leaves, margin_abs and margin_rel (the
-    smallest |d1 + d2 - B (b - a)| over the tested nodes, absolute and
-    relative to B (b - a))."""
+    smallest |d1 + d2 - axis| over the tested nodes, absolute and relative
+    to the axis).  cp_bound: the axis of a node is the smaller of B (b - a)
+    and the bound of its own (subdivided) control points (the variant that
+    Sec. 4.2 / Table 1 contrast with the ellipse bound)."""
     lib = _load()
     sco = np.ascontiguousarray(faces.seg_cp_offsets, dtype=np.int64)
     cu = np.ascontiguousarray(faces.cp_u, dtype=np.float64)
@@ -138,14 +140,14 @@ def alg1_pairs(faces, seg, x, y, eps: float = 1e-10, nthreads: int | None = None
     if nthreads is None:
         nthreads = os.cpu_count() or 1
     st = lib.wno_alg1_pairs(len(sco) - 1, _ptr(sco), _ptr(cu), _ptr(cv), _ptr(cw), n, _ptr(sg), _ptr(px), _ptr(py),
-                            float(eps), int(nthreads), _ptr(out))
+                            float(eps), 1 if cp_bound else 0, int(nthreads), _ptr(out))
     if st != 0:
         raise OracleError(f"alg1 mirror returned status {st}")
     return {"depth": out[:, 0].astype(np.int32), "onb": out[:, 1] != 0, "splits": out[:, 2].astype(np.int64),
             "leaves": out[:, 3].astype(np.int64), "margin_abs": out[:, 4], "margin_rel": out[:, 5]}
 
 
-def alg1_segment(cp, w, x, y, eps: float = 1e-10):
+def alg1_segment(cp, w, x, y, eps: float = 1e-10, cp_bound: bool = False):
     """alg1_pairs for one segment given by its control points [n+1, 2] (and
     weights or None) against the points x, y."""
     from types import SimpleNamespace
@@ -156,7 +158,7 @@ def alg1_segment(cp, w, x, y, eps: float = 1e-10):
     y = np.atleast_1d(np.asarray(y, dtype=np.float64))
     f = SimpleNamespace(seg_cp_offsets=np.array([0, n + 1], dtype=np.int64), cp_u=cp[:, 0].copy(),
                         cp_v=cp[:, 1].copy(), cp_w=None if w is None else np.asarray(w, dtype=np.float64))
-    return alg1_pairs(f, np.zeros(len(x), dtype=np.int32), x, y, eps, nthreads=1)
+    return alg1_pairs(f, np.zeros(len(x), dtype=np.int32), x, y, eps, nthreads=1, cp_bound=cp_bound)
 
 
 def alg1_bound(cp, w=None) -> float:

@@ -11,7 +11,9 @@ Sec. 4.2) compares can be decided exactly:
   * the ellipse test sqrt(A) + sqrt(C) <= sqrt(G), with A, C the squared
     distances to the node's end points and G = B^2 4^-k, holds iff
     G - A - C >= 0 and 4 A C <= (G - A - C)^2 (squaring twice);
-  * the eps test d < eps is A < eps^2.
+  * the eps test d < eps is A < eps^2;
+  * with cp_bound, a node's own control points are exact halvings of its
+    parent's (rational), so its control-point bound squared is rational too.
 
 The nodes are enumerated level by level (breadth first), the reverse of the
 recursion's order: a node of level k + 1 is tested iff its parent failed
@@ -56,20 +58,40 @@ def _sqrt(q: Fraction) -> Decimal:
     return (Decimal(q.numerator) / Decimal(q.denominator)).sqrt()
 
 
-def depth(cps, ws, x, eps, max_level=40):
+def _halves(hom):
+    """De Casteljau at 1/2 of homogeneous control points [(wx, wy, w)]."""
+    n = len(hom) - 1
+    t = list(hom)
+    left, right = [t[0]], [t[n]]
+    for r in range(1, n + 1):
+        t = [tuple((p + q) / 2 for p, q in zip(t[i], t[i + 1])) for i in range(n - r + 1)] + t[n - r + 1:]
+        left.append(t[0])
+        right.append(t[n - r])
+    return left, right[::-1]
+
+
+def _piece_bound_squared(hom, rational):
+    cps = [(X / W, Y / W) for X, Y, W in hom]
+    return bound_squared(cps, [W for _, _, W in hom] if rational else None)
+
+
+def depth(cps, ws, x, eps, max_level=40, cp_bound=False):
     """Exact Alg. 1 on one pair.  cps: [(Fraction, Fraction)], ws: weights or
-    None, x: query (Fraction, Fraction), eps: Fraction.
+    None, x: query (Fraction, Fraction), eps: Fraction.  cp_bound: the axis
+    of a node is the smaller of B (b - a) and the bound of the node's own
+    control points (exact de Casteljau halving of its parent's).
 
     Returns (depth, on_boundary, splits, leaves, min_abs_margin,
-    min_rel_margin): the smallest |d1 + d2 - B (b - a)| over the tested nodes,
-    absolute and relative to B (b - a), evaluated to 50 digits."""
+    min_rel_margin): the smallest |d1 + d2 - axis| over the tested nodes,
+    absolute and relative to the axis, evaluated to 50 digits."""
     getcontext().prec = 50
     cps = [(Fraction(a), Fraction(b)) for a, b in cps]
     ws_ = [Fraction(1)] * len(cps) if ws is None else [Fraction(w) for w in ws]
     x = (Fraction(x[0]), Fraction(x[1]))
     B2 = bound_squared(cps, None if ws is None else ws_)
     eps2 = Fraction(eps) ** 2
-    level_nodes = [(Fraction(0), Fraction(1), cps[0], cps[-1])]
+    root = [(w * px, w * py, w) for (px, py), w in zip(cps, ws_)]
+    level_nodes = [(Fraction(0), Fraction(1), cps[0], cps[-1], root)]
     deepest, splits, leaves = 0, 0, 0
     min_rel = min_abs = Decimal("Infinity")
     for k in range(max_level + 1):
@@ -78,15 +100,16 @@ def depth(cps, ws, x, eps, max_level=40):
         deepest = k
         G = B2 / Fraction(4) ** k
         nxt = []
-        for a, b, pa, pb in level_nodes:
+        for a, b, pa, pb, hom in level_nodes:
             A, C = _d2(pa, x), _d2(pb, x)
             if A < eps2 or C < eps2:
                 return deepest, True, splits, leaves, min_abs, min_rel
-            axis = _sqrt(G)
+            Gn = min(G, _piece_bound_squared(hom, ws is not None)) if cp_bound else G
+            axis = _sqrt(Gn)
             gap = abs(_sqrt(A) + _sqrt(C) - axis)
             min_abs = min(min_abs, gap)
             min_rel = min(min_rel, gap / axis)
-            R = G - A - C
+            R = Gn - A - C
             inside = R >= 0 and 4 * A * C <= R * R
             if not inside:
                 leaves += 1
@@ -94,8 +117,9 @@ def depth(cps, ws, x, eps, max_level=40):
             splits += 1
             m = (a + b) / 2
             pm = _point(cps, ws_, m)
-            nxt.append((a, m, pa, pm))
-            nxt.append((m, b, pm, pb))
+            lh, rh = _halves(hom) if cp_bound else (None, None)
+            nxt.append((a, m, pa, pm, lh))
+            nxt.append((m, b, pm, pb, rh))
         level_nodes = nxt
     if level_nodes:
         raise RuntimeError("exact recursion passed max_level")

@@ -250,9 +250,16 @@ MUTATIONS = {
     "children one level too deep": ("alg1_node(c, a, t, level + 1,", "alg1_node(c, a, t, level + 2,"),
     "axis of the whole segment at every level": ("double axis = c->B * (b - a);", "double axis = c->B;"),
 }
+# ... and in the control-point bound variant (checked against its own exact pin)
+CP_MUTATIONS = {
+    "control-point bound ignored": ("fmin(c->B * (b - a), bcp)", "c->B * (b - a)"),
+    "halves swapped": ("alg1_node_cp(c, a, tm, level + 1, lx, ly, lw,", "alg1_node_cp(c, a, tm, level + 1, rx, ry, rw,"),
+    "weights dropped from the piece bound": ("c->rational ? W : NULL", "NULL"),
+    "apex not divided by its weight": ("mx = tx[0] / tw[0]", "mx = tx[0]"),
+}
 
 
-def _mutant_segment(lib, cp, w, x, y, eps):
+def _mutant_segment(lib, cp, w, x, y, eps, cp_bound=0):
     import ctypes
 
     cp = np.asarray(cp, dtype=np.float64)
@@ -267,12 +274,11 @@ def _mutant_segment(lib, cp, w, x, y, eps):
     P = ctypes.c_void_p
     ptr = lambda a: None if a is None else a.ctypes.data_as(P)
     lib.wno_alg1_pairs(1, ptr(sco), ptr(cu), ptr(cv), ptr(cw), len(x), ptr(seg), ptr(x), ptr(y), ctypes.c_double(eps),
-                       1, ptr(out))
+                       cp_bound, 1, ptr(out))
     return out
 
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_planted_mistakes_fail_the_pins(tmp_path, name):
+def _build_mutant(tmp_path, old, new):
     import ctypes
     import os
     import shutil
@@ -283,15 +289,45 @@ def test_planted_mistakes_fail_the_pins(tmp_path, name):
     src = os.path.dirname(oracle.__file__)
     for f in ("wn_oracle.c", "wn_oracle_core.inc", "wn_oracle_periodic.inc", "wn_oracle_alg1.inc"):
         shutil.copy(os.path.join(src, f), tmp_path / f)
-    old, new = MUTATIONS[name]
     text = (tmp_path / "wn_oracle_alg1.inc").read_text()
-    assert text.count(old) == 1, name
+    assert text.count(old) == 1, old
     (tmp_path / "wn_oracle_alg1.inc").write_text(text.replace(old, new))
     so = tmp_path / "mutant.so"
     subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", str(so), str(tmp_path / "wn_oracle.c"),
                     "-lpthread", "-lm"], check=True)
     lib = ctypes.CDLL(str(so))
     lib.wno_alg1_pairs.restype = ctypes.c_int
+    return lib
+
+
+@pytest.mark.parametrize("name", sorted(CP_MUTATIONS))
+def test_planted_mistakes_fail_the_cp_pin(tmp_path, name):
+    lib = _build_mutant(tmp_path, *CP_MUTATIONS[name])
+    rng = np.random.default_rng(123)
+    failed = False
+    for case in range(60):
+        if failed:
+            break
+        cps, ws = _random_curve(rng, rational=bool(case % 2))
+        t0 = Fraction(int(rng.integers(1, 1 << 12)), 1 << 12)
+        px, py = _exact_point(cps, ws, t0)
+        e = int(rng.integers(4, 18))
+        qx = float(px) + float(rng.uniform(-1, 1)) * 2.0 ** -e
+        qy = float(py) + float(rng.uniform(-1, 1)) * 2.0 ** -e
+        d, onb, sp, lf, mabs, mrel = alg1_exact.depth(cps, ws, (Fraction(qx), Fraction(qy)), Fraction(EPS),
+                                                      cp_bound=True)
+        if onb or mabs < BORDER_ABS or mrel < BORDER_REL:
+            continue
+        cp = np.array([[float(a), float(b)] for a, b in cps])
+        w = None if ws is None else np.array([float(x) for x in ws])
+        r = _mutant_segment(lib, cp, w, qx, qy, EPS, cp_bound=1)
+        failed |= int(r[0, 0]) != d or int(r[0, 2]) != sp or int(r[0, 3]) != lf
+    assert failed, f"planted mistake '{name}' passed the control-point pin"
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistakes_fail_the_pins(tmp_path, name):
+    lib = _build_mutant(tmp_path, *MUTATIONS[name])
     failed = False
     # the arc closed forms
     for deg in (30, 60, 80):
@@ -324,3 +360,82 @@ def test_planted_mistakes_fail_the_pins(tmp_path, name):
         r = _mutant_segment(lib, cp, w, qx, qy, EPS)
         failed |= int(r[0, 0]) != d or int(r[0, 2]) != sp or int(r[0, 3]) != lf
     assert failed, f"planted mistake '{name}' passed the pins"
+
+
+# --- the subdivided control-point bound variant (Sec. 4.2 / Table 1 contrast)
+
+def test_cp_mirror_matches_exact_arithmetic(oracle_lib):
+    """The FP64 mirror's control-point bound mode against exact rational
+    arithmetic (exact halvings, exact squared bounds): every output agrees
+    wherever every tested node's exact margin is clear of rounding."""
+    rng = np.random.default_rng(20251103)
+    compared = border = 0
+    depths = []
+    for case in range(160):
+        cps, ws = _random_curve(rng, rational=bool(case % 2))
+        t0 = Fraction(int(rng.integers(1, 1 << 12)), 1 << 12)
+        px, py = _exact_point(cps, ws, t0)
+        e = int(rng.integers(4, 22))
+        off = (float(rng.uniform(-1, 1)) * 2.0 ** -e, float(rng.uniform(-1, 1)) * 2.0 ** -e)
+        qx, qy = float(px) + off[0], float(py) + off[1]
+        ex = alg1_exact.depth(cps, ws, (Fraction(qx), Fraction(qy)), Fraction(EPS), cp_bound=True)
+        cp = np.array([[float(a), float(b)] for a, b in cps])
+        w = None if ws is None else np.array([float(x) for x in ws])
+        m = oracle_lib.alg1_segment(cp, w, qx, qy, eps=EPS, cp_bound=True)
+        d, onb, sp, lf, mabs, mrel = ex
+        if (mabs < BORDER_ABS or mrel < BORDER_REL) and not onb:
+            border += 1
+            continue
+        compared += 1
+        depths.append(d)
+        assert bool(m["onb"][0]) == onb, (case, ex, m)
+        if not onb:
+            assert int(m["depth"][0]) == d, (case, ex, m)
+            assert int(m["splits"][0]) == sp and int(m["leaves"][0]) == lf, (case, ex, m)
+    assert compared >= 140 and border <= 20
+    assert max(depths) >= 12
+
+
+def test_cp_bound_prunes_a_subtree_of_the_global_tree():
+    """Exact arithmetic: a node's control-point bound never exceeds B (b - a)
+    for polynomial curves (the restricted hodograph's control points are
+    convex combinations of the whole one's), and the variant takes the
+    smaller of the two, so every node it tests is tested by the global-bound
+    recursion too: depth, splits and leaves can only shrink, and they do on
+    curved segments."""
+    rng = np.random.default_rng(77)
+    shrunk = 0
+    for case in range(60):
+        cps, ws = _random_curve(rng, rational=bool(case % 3 == 0))
+        t0 = Fraction(int(rng.integers(1, 1 << 10)), 1 << 10)
+        px, py = _exact_point(cps, ws, t0)
+        q = (px + Fraction(int(rng.integers(-64, 65)), 1 << 14), py + Fraction(int(rng.integers(-64, 65)), 1 << 14))
+        g = alg1_exact.depth(cps, ws, q, Fraction(1, 1 << 40))
+        c = alg1_exact.depth(cps, ws, q, Fraction(1, 1 << 40), cp_bound=True)
+        if g[1] or c[1]:
+            continue
+        assert c[0] <= g[0] and c[2] <= g[2] and c[3] <= g[3], (case, g, c)
+        shrunk += c[2] < g[2]
+        if ws is None:
+            hom = [(x, y, Fraction(1)) for x, y in cps]
+            B2 = alg1_exact.bound_squared(cps)
+            for lvl in range(1, 5):
+                hom = alg1_exact._halves(hom)[int(rng.integers(0, 2))]
+                assert alg1_exact._piece_bound_squared(hom, False) <= B2 / Fraction(4) ** lvl
+    assert shrunk >= 10
+
+
+def test_cp_bound_on_straight_segments_changes_nothing(oracle_lib):
+    """A straight segment's sub-pieces have control-point bound = their length
+    = B (b - a): both modes give the same counts (closed form)."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        a, b = rng.uniform(-1, 1, 2), rng.uniform(-1, 1, 2)
+        n = int(rng.integers(1, 6))
+        t = np.linspace(0, 1, n + 1)[:, None]
+        cp = a + t * (b - a)  # evenly spaced: a degree-n parametrisation of the segment at constant speed
+        q = a + rng.uniform(0.2, 0.8) * (b - a) + rng.normal(0, 1e-3, 2)
+        g = oracle_lib.alg1_segment(cp, None, q[0], q[1], eps=EPS)
+        c = oracle_lib.alg1_segment(cp, None, q[0], q[1], eps=EPS, cp_bound=True)
+        for k in ("depth", "splits", "leaves"):
+            assert int(g[k][0]) == int(c[k][0]), (k, g, c)
