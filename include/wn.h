@@ -241,6 +241,30 @@ wn_status wn_query(const wn_faces* faces, const wn_points* points, double* out_w
 wn_status wn_query_ex(const wn_faces* faces, const wn_points* points, double* out_winding, uint8_t* out_inside,
                       const wn_query_opts* q, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): wn_query_ex
+ * with the batched schedule, whose scratch (work items, counters, near queue,
+ * spatial order of periodic points) lives in a fixed device array of
+ * wn_query_noalloc_scratch_bytes() bytes (64 MiB) that the library holds on
+ * each device it runs on until the process ends.  No allocation of any kind
+ * is made.  The near queue gets whatever the array has left; pairs that do
+ * not fit are recomputed in line, so results equal wn_query_ex's.
+ *   out_winding, out_inside  device outputs, both required (not NULL)
+ *   limits                   num_points <= WN_NOALLOC_MAX_POINTS and the
+ *                            handle's faces <= WN_NOALLOC_MAX_FACES, else
+ *                            WN_E_INVALID; a schedule other than batched
+ *                            (q->schedule or the handle's) gives
+ *                            WN_E_UNSUPPORTED
+ * Every call on a device shares that device's array (it keeps the last call's
+ * contents, and nothing in it has to start at zero): calls that overlap in
+ * time on one device race, so issue them on one stream per device.  The
+ * device is the handle's.  Asynchronous on `stream`. */
+#define WN_NOALLOC_MAX_POINTS (1 << 22)
+#define WN_NOALLOC_MAX_FACES (1 << 18)
+wn_status wn_query_noalloc(const wn_faces* faces, const wn_points* points, double* out_winding, uint8_t* out_inside,
+                           const wn_query_opts* q, void* stream);
+int64_t wn_query_noalloc_scratch_bytes(void);
+
 /* Release a handle (waits for nothing: the caller must not destroy a handle
  * that queued work still uses).  NULL is ignored. */
 void wn_destroy_faces(wn_faces* faces);

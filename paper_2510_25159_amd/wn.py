@@ -29,7 +29,9 @@ EXPORTS = [
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
     "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy", "wn_nurbs_to_bezier",
     "wn_classify_grid", "wn_classify_surfaces", "wn_create_faces_nurbs", "wn_near_pairs",
+    "wn_query_noalloc", "wn_query_noalloc_scratch_bytes",
 ]
+NOALLOC_MAX_POINTS, NOALLOC_MAX_FACES = 1 << 22, 1 << 18
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 BIN_PREDICTOR, BIN_HEURISTIC, BIN_MEASURED, BIN_NONE = 0, 1, 2, 3
@@ -127,6 +129,10 @@ def lib():
         L.wn_query.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, _P]
         L.wn_query_ex.restype = ctypes.c_int
         L.wn_query_ex.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.POINTER(wn_query_opts), _P]
+        L.wn_query_noalloc.restype = ctypes.c_int
+        L.wn_query_noalloc.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.POINTER(wn_query_opts), _P]
+        L.wn_query_noalloc_scratch_bytes.restype = ctypes.c_int64
+        L.wn_query_noalloc_scratch_bytes.argtypes = []
         L.wn_destroy_faces.argtypes = [_P]
         L.wn_segment_bound.restype = ctypes.c_int
         L.wn_segment_bound.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
@@ -380,6 +386,24 @@ class FaceSet:
                                _stream_ptr(stream))
         if st != WN_OK:
             raise WnError(st, "wn_query_ex")
+        return out_w, out_lab
+
+    def query_noalloc(self, u, v, offsets, out_w, out_lab, *, offsets_host=None, stride: int = 1, stream=None,
+                      **opts):
+        """wn_query_noalloc on torch CUDA tensors: the batched query with the
+        library's fixed device scratch (the caller provides both outputs)."""
+        import torch
+
+        n = u.numel() if stride == 1 else u.numel() // stride + (1 if u.numel() % stride else 0)
+        assert u.is_cuda and v.is_cuda and offsets.is_cuda
+        assert u.dtype == torch.float64 and v.dtype == torch.float64 and offsets.dtype == torch.int64
+        hoffs = None if offsets_host is None else np.ascontiguousarray(offsets_host, dtype=np.int64)
+        p = wn_points(n, u.data_ptr(), v.data_ptr(), stride, offsets.data_ptr(), _np_ptr(hoffs))
+        q = _query_opts(**opts)
+        st = lib().wn_query_noalloc(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
+                                    _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_query_noalloc")
         return out_w, out_lab
 
     def classify_grid(self, grids, *, out_uv: bool = True, stream=None, **opts):
