@@ -19,8 +19,11 @@
  *    (for instance torch tensors); the library never frees them.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Query work is enqueued on it and is asynchronous: outputs are valid once
- *    the stream reaches that point.  Only wn_create_faces synchronizes (it
- *    reads back the covering-space lift of periodic faces).
+ *    the stream reaches that point.  wn_create_faces synchronizes (it reads
+ *    back the covering-space lift of periodic faces); so do the calls that
+ *    say so below (the application drivers, which upload their tables once,
+ *    and the diagnostics).  The queries themselves (wn_query, wn_query_ex,
+ *    wn_query_noalloc, plan replays) never synchronize.
  *  - A wn_faces handle is immutable after creation: concurrent wn_query calls
  *    on different streams with the same handle are safe.  Each call allocates
  *    its own stream-ordered scratch memory.
@@ -122,8 +125,17 @@ typedef struct {
     int32_t rule;      /* wn_rule (default WN_RULE_NONZERO)                                 */
     int32_t schedule;  /* wn_schedule (default WN_SCHED_BATCHED)                            */
     int32_t stack_cap; /* largest accepted depth bound ceil(log2(B/eps))+3 (default 52, max 52) */
-    int32_t flags;     /* reserved, 0                                                       */
+    int32_t flags;     /* WN_FLAG_* bits (default 0)                                         */
 } wn_options;
+
+/* wn_options.flags */
+enum {
+    /* Pair the loops of torus faces on the host instead of the GPU (the same
+     * pairing rule, App. C; kept for comparison).  By default the pairing
+     * runs on the GPU, one wave per torus face (faces with more than 64
+     * loops in B always pair on the host). */
+    WN_FLAG_HOST_PAIRING = 1
+};
 
 /* Query points, grouped by face: the points of face f are
  * [face_point_offsets[f], face_point_offsets[f+1]). */
@@ -134,7 +146,8 @@ typedef struct {
     int64_t stride;                        /* >= 1; 1 = separate arrays, 2 = interleaved (u,v) */
     const int64_t* face_point_offsets;     /* device [num_faces+1], non-decreasing, last = num_points */
     const int64_t* face_point_offsets_host;/* host copy of the same, or NULL (then the plain
-                                              schedule reads the device copy back, synchronously) */
+                                              schedule builds its face tiles on the device
+                                              and the batched one runs its passes in series) */
 } wn_points;
 
 typedef struct wn_faces wn_faces; /* opaque; owns all device copies */
@@ -230,14 +243,23 @@ void wn_default_query_opts(wn_query_opts* q);
  * `stream`. */
 wn_status wn_create_faces(const wn_faces_desc* desc, const wn_options* opt, void* stream, wn_faces** out);
 
-/* omega and label for every query point.  out_winding: device double
- * [num_points] (NaN for on-boundary and invalid points); out_inside: device
- * uint8 [num_points], one of WN_OUTSIDE/INSIDE/ON_BOUNDARY/INVALID_POINT.
- * Either output may be NULL.  Asynchronous on `stream`. */
+/* The containment query of Sec. 4.1 (Alg. 1 per point-segment pair, with
+ * the root ellipse test of Lemma 1 and the sub-segment bound of Sec. 4.2;
+ * the periodic sums of Sec. 4.3-4.5 for periodic faces): omega and label for
+ * every query point against the loops of its face (points grouped by face,
+ * wn_points.face_point_offsets).  out_winding: device double [num_points]
+ * (NaN for on-boundary and invalid points); out_inside: device uint8
+ * [num_points], one of WN_OUTSIDE/INSIDE/ON_BOUNDARY/INVALID_POINT (inside
+ * means |omega| > 1/2, or omega > 1/2 under WN_RULE_POSITIVE).  Either output
+ * may be NULL.  Asynchronous on `stream`; per-call scratch is stream-ordered
+ * (hipMallocAsync / hipFreeAsync on `stream`).  WN_E_INVALID for malformed
+ * points or offsets (checked on the host when host offsets are given). */
 wn_status wn_query(const wn_faces* faces, const wn_points* points, double* out_winding, uint8_t* out_inside,
                    void* stream);
 
-/* wn_query with per-call overrides (`q` may be NULL). */
+/* wn_query (Sec. 4.1, Alg. 1) with per-call overrides of the handle's
+ * schedule, precision and rule, work counters, profiling and the plain
+ * schedule's depth log (`q` may be NULL: the handle's defaults). */
 wn_status wn_query_ex(const wn_faces* faces, const wn_points* points, double* out_winding, uint8_t* out_inside,
                       const wn_query_opts* q, void* stream);
 
@@ -521,6 +543,16 @@ typedef struct {
     int64_t device_bytes;      /* device memory held by the handle */
 } wn_faces_info;
 wn_status wn_get_faces_info(const wn_faces* faces, wn_faces_info* info);
+
+/* Pair table of torus face `face` (Sec. 4.5, App. C: each loop alpha of A
+ * with the loop beta of B whose copy beta + shift lies nearest on alpha's
+ * left).  Host-only read of the handle.  Writes up to `cap` pairs: alpha[i],
+ * beta[i] (face-set loop indices) and shift[2i], shift[2i+1] (the copy's
+ * translation); *count = the face's number of pairs (0 for a face without
+ * torus pairs).  WN_E_INVALID for a bad face index or NULL pointers with
+ * cap > 0. */
+wn_status wn_torus_pairs(const wn_faces* faces, int32_t face, int32_t cap, int32_t* alpha, int32_t* beta,
+                         double* shift, int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -128,6 +128,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     if (opt.precision < 0 || opt.precision > WN_PREC_MIXED) return WN_E_INVALID;
     if (opt.rule < 0 || opt.rule > WN_RULE_POSITIVE) return WN_E_INVALID;
     if (opt.schedule < 0 || opt.schedule > WN_SCHED_BINNED) return WN_E_INVALID;
+    if (opt.flags & ~(int32_t)WN_FLAG_HOST_PAIRING) return WN_E_INVALID;
     const int32_t F = d->num_faces, L = d->num_loops, S = d->num_segments;
     if (F < 0 || L < 0 || S < 0) return WN_E_INVALID;
     if (!d->face_loop_offsets || !d->loop_seg_offsets || !d->seg_cp_offsets) return WN_E_INVALID;
@@ -513,19 +514,78 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
                 }
             }
         }
+        // rounding margin for the magnitudes met by translated copies
+        auto face_margin = [&](int32_t f, double t1x, double t1y) {
+            double reach = fabs(t1x) + fabs(t1y) + 2.0 * (d->face_period[2 * f] + d->face_period[2 * f + 1]);
+            for (int32_t l = d->face_loop_offsets[f]; l < d->face_loop_offsets[f + 1]; ++l)
+                reach = std::max(reach, 3.0 * ploop[l].lv + 4.0 * (fabs(ploop[l].bb[0]) + fabs(ploop[l].bb[1]) +
+                                                                   fabs(ploop[l].bb[2]) + fabs(ploop[l].bb[3])));
+            return 8.0 * 1.1102230246251565e-16 * (1.0 + face_scale[f] + reach);
+        };
+        // loop classes and homology (host), torus pairing (GPU by default)
+        std::vector<TorusSetup> tsu((size_t)F);
+        for (int32_t f = 0; f < F; ++f) {
+            if (dom[f] == WN_DOMAIN_PLANE) continue;
+            if (torus_setup(dom[f], d->face_period[2 * f], d->face_period[2 * f + 1], d->face_loop_offsets[f],
+                            d->face_loop_offsets[f + 1], ploop, tsu[f]) != 0)
+                return fail(WN_E_TOPOLOGY);
+        }
+        std::vector<int2> choice;
+        std::vector<int32_t> choice_at((size_t)F, -1);
+        if (!(opt.flags & WN_FLAG_HOST_PAIRING)) {
+            std::vector<PairJob> jobs;
+            std::vector<int32_t> lists;
+            for (int32_t f = 0; f < F; ++f) {
+                const TorusSetup& t = tsu[f];
+                if (dom[f] != WN_DOMAIN_TORUS || t.A.empty() || t.B.size() > 64) continue;  // (larger: host)
+                PairJob J{};
+                J.a0 = (int32_t)lists.size();
+                J.na = (int32_t)t.A.size();
+                lists.insert(lists.end(), t.A.begin(), t.A.end());
+                J.b0 = (int32_t)lists.size();
+                J.nb = (int32_t)t.B.size();
+                lists.insert(lists.end(), t.B.begin(), t.B.end());
+                J.out0 = (int32_t)choice.size();
+                J.t1x = t.t1x;
+                J.t1y = t.t1y;
+                J.nx = t.nx;
+                J.ny = t.ny;
+                J.Delta = t.Delta;
+                J.eta = face_margin(f, t.t1x, t.t1y);
+                choice_at[f] = J.out0;
+                choice.resize(choice.size() + t.A.size(), make_int2(-1, 0));
+                jobs.push_back(J);
+            }
+            if (!jobs.empty()) {
+                const size_t b_jobs = ((jobs.size() * sizeof(PairJob)) + 255) & ~(size_t)255;
+                const size_t b_lists = ((lists.size() * 4) + 255) & ~(size_t)255;
+                void* ptmp = nullptr;
+                e = hipMalloc(&ptmp, b_jobs + b_lists + choice.size() * sizeof(int2));
+                if (e != hipSuccess) return fail(hip_status(e));
+                char* pb = (char*)ptmp;
+                e = hipMemcpyAsync(pb, jobs.data(), jobs.size() * sizeof(PairJob), hipMemcpyHostToDevice, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(pb + b_jobs, lists.data(), lists.size() * 4, hipMemcpyHostToDevice, st);
+                if (e == hipSuccess)
+                    e = launch_pair_torus(h->sg, d_ploop, (const PairJob*)pb, (int)jobs.size(),
+                                          (const int32_t*)(pb + b_jobs), (int2*)(pb + b_jobs + b_lists), h->eps2, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(choice.data(), pb + b_jobs + b_lists, choice.size() * sizeof(int2),
+                                       hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                (void)hipFree(ptmp);
+                if (e != hipSuccess) return fail(hip_status(e));
+            }
+        }
         std::vector<PUnit> units;
         std::vector<PFace> pface((size_t)F);
         for (int32_t f = 0; f < F; ++f) {
             if (dom[f] == WN_DOMAIN_PLANE) continue;
+            const int2* ch = choice_at[f] >= 0 ? choice.data() + choice_at[f] : nullptr;
             if (build_periodic_face(dom[f], d->face_period[2 * f], d->face_period[2 * f + 1], d->face_loop_offsets[f],
-                                    d->face_loop_offsets[f + 1], hsegs, ploop, units, pface[f]) != 0)
+                                    d->face_loop_offsets[f + 1], hsegs, ploop, &tsu[f], ch, units, pface[f]) != 0)
                 return fail(WN_E_TOPOLOGY);
-            // rounding margin for the magnitudes met by translated copies
-            double reach = fabs(pface[f].t1x) + fabs(pface[f].t1y) + 2.0 * (d->face_period[2 * f] + d->face_period[2 * f + 1]);
-            for (int32_t l = d->face_loop_offsets[f]; l < d->face_loop_offsets[f + 1]; ++l)
-                reach = std::max(reach, 3.0 * ploop[l].lv + 4.0 * (fabs(ploop[l].bb[0]) + fabs(ploop[l].bb[1]) +
-                                                                   fabs(ploop[l].bb[2]) + fabs(ploop[l].bb[3])));
-            const double em = 8.0 * 1.1102230246251565e-16 * (1.0 + face_scale[f] + reach);
+            const double em = face_margin(f, pface[f].t1x, pface[f].t1y);
             for (int32_t s = h->h_seg_begin[f]; s < h->h_seg_begin[f + 1]; ++s) {
                 eta[s] = em;
                 const double Be = Bv[s] * (1.0 + kAxisInflate) + em;
@@ -551,12 +611,19 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         e = hipMemcpyAsync(base + o_frec, frec.data(), (size_t)S * sizeof(FarRec), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return fail(hip_status(e));
         e = hipMemcpyAsync(base + o_eta, eta.data(), (size_t)S * 8, hipMemcpyHostToDevice, st);
+        // ... and the near pass's copy of eta in each coefficient record (the
+        // records themselves were lifted on the device)
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(base + o_coef + (kPadEta * 4 + 3) * 8, kCoef * 4 * 8, eta.data(), 8, 8, (size_t)S,
+                                 hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(base + o_hb2, hb2.data(), (size_t)S * 8, hipMemcpyHostToDevice, st);
         if (e == hipSuccess && !units.empty())
             e = hipMemcpyAsync(base + o_punit, units.data(), units.size() * sizeof(PUnit), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(base + o_pface, pface.data(), (size_t)F * sizeof(PFace), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return fail(hip_status(e));
+        h->h_units = units;
+        h->h_pface = pface;
         h->pt.loop = d_ploop;
         h->pt.unit = (const PUnit*)(base + o_punit);
         h->pt.face = (const PFace*)(base + o_pface);
@@ -567,6 +634,29 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         (void)hipGetLastError();
     }
     *out = h;
+    return WN_OK;
+}
+
+wn_status wn_torus_pairs(const wn_faces* h, int32_t face, int32_t cap, int32_t* alpha, int32_t* beta, double* shift,
+                         int32_t* count) {
+    if (!h || !count || face < 0 || face >= h->num_faces || cap < 0) return WN_E_INVALID;
+    if (cap > 0 && (!alpha || !beta || !shift)) return WN_E_INVALID;
+    *count = 0;
+    if (h->h_pface.empty() || h->h_dom[face] == WN_DOMAIN_PLANE) return WN_OK;
+    const PFace& pf = h->h_pface[face];
+    int32_t k = 0;
+    for (int u = pf.u0; u < pf.u1; ++u) {
+        const PUnit& U = h->h_units[u];
+        if (U.kind != kUnitPair) continue;
+        if (k < cap) {
+            alpha[k] = U.la;
+            beta[k] = U.lb;
+            shift[2 * k] = U.pshx;
+            shift[2 * k + 1] = U.pshy;
+        }
+        ++k;
+    }
+    *count = k;
     return WN_OK;
 }
 
@@ -711,28 +801,42 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     }
 
     if (plain) {
-        std::vector<int64_t> offs;
         const int64_t* ho = p->face_point_offsets_host;
-        if (!ho) {
-            offs.resize((size_t)F + 1);
-            e = hipMemcpyAsync(offs.data(), p->face_point_offsets, offs.size() * 8, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            bool ok = e == hipSuccess && offs[0] == 0 && offs[F] == N;
-            for (int32_t f = 0; ok && f < F; ++f) ok = offs[f + 1] >= offs[f];
-            if (!ok) {
-                if (!preset) scratch_free(sc, st);
-                return e != hipSuccess ? hip_status(e) : WN_E_INVALID;
-            }
-            ho = offs.data();
-        }
         const Out pout{sc.out.w, sc.out.lab, q.depth_log, h->max_spf, rule};
+        const int qg = qpw > 256 ? 256 : qpw;  // in-line recursion: one query per lane
+        if (!ho) {
+            // Device offsets only (nothing is read back): the faces' tiles come
+            // from item tables built on the device, one in-line launch per
+            // domain kind.  The periodic pass and the finalize of every point
+            // run first; the planar in-line pass then writes its final values
+            // over whatever that finalize left on planar points.
+            if (h->num_periodic > 0) {
+                ProfScope ps(q.profile, WN_KERNEL_FAR_PERIODIC, st);
+                e = launch_build_items(h->ft_per, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
+                                       true, st);
+                if (e == hipSuccess) e = launch_spatial_order(h->ft_per, pts, sc.perm, st);
+                if (e == hipSuccess)
+                    e = launch_far_periodic(kPerInline, h->sg, h->ft_per, pts, sc.item_offs, sc.item_map, nullptr,
+                                            sc.max_items, sc.nq, sc.out, h->eps2, h->pt, sc.perm, st);
+                if (e == hipSuccess) e = launch_finalize(pts, sc.out, 0, N, -1, st);
+            }
+            if (e == hipSuccess && h->num_planar > 0) {
+                ProfScope ps(q.profile, WN_KERNEL_FAR, st);
+                e = launch_build_items(h->ft_plan, pts, qg, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
+                                       true, st);
+                if (e == hipSuccess)
+                    e = launch_far(true, prec == WN_PREC_MIXED, qg, h->sg, h->ft_plan, pts, sc.item_offs,
+                                   sc.item_map, nullptr, -1, sc.max_items, NearQueue{}, pout, h->eps2, st);
+            }
+            if (!preset) scratch_free(sc, st);
+            return hip_status(e);
+        }
         bool zero_near = true;
         for (int32_t f = 0; f < F && e == hipSuccess; ++f) {
             const int64_t nf = ho[f + 1] - ho[f];
             if (nf == 0) continue;
             ProfScope ps(q.profile, WN_KERNEL_FAR, st);
             if (h->h_dom[f] == WN_DOMAIN_PLANE) {
-                const int qg = qpw > 256 ? 256 : qpw;  // in-line recursion: one query per lane
                 e = launch_far(true, prec == WN_PREC_MIXED, qg, h->sg, h->ft_plan, pts, nullptr, nullptr, nullptr, f,
                                (nf + qg - 1) / qg, NearQueue{}, pout, h->eps2, st);
             } else {

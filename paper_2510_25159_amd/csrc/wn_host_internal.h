@@ -30,6 +30,8 @@ struct wn_faces {
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
     std::vector<int32_t> h_ord_plan;  // ft_plan.order on the host
     std::vector<int32_t> h_ord_flat;  // ft_flat.order on the host
+    std::vector<wn::PUnit> h_units;   // periodic units (torus pairs included) on the host
+    std::vector<wn::PFace> h_pface;   // [F] periodic face records on the host (planar: zero)
     // side stream of the overlapped far/near passes (default priority); null
     // when it could not be created
     hipStream_t side = nullptr;

@@ -202,6 +202,17 @@ hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points&
 int farq_blocks_per_cu(int qpl);
 int near_blocks_per_cu();
 hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);
+
+// One torus face for the pairing kernel: A = lists[a0 .. a0 + na), B =
+// lists[b0 .. b0 + nb) (loop indices, nb <= 64), choices written to
+// out[out0 .. out0 + na) as (index into B or -1, family m of the shift m t_1).
+struct PairJob {
+    int32_t a0, na, b0, nb, out0, pad;
+    double t1x, t1y, nx, ny, Delta;
+    double eta;  // axis inflation of the probes' ellipse tests
+};
+hipError_t launch_pair_torus(const Segs& sg, const PLoop* loops, const PairJob* jobs, int njobs, const int32_t* lists,
+                             int2* out, double eps2, hipStream_t st);
 // Periodic far pass variants: near pairs queued (overflow -> label kRedo),
 // recursed in line, or recursed in line for the kRedo-labelled queries only.
 enum : int { kPerQueue = 0, kPerInline = 1, kPerRedo = 2 };

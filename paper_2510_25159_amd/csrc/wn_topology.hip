@@ -168,13 +168,8 @@ void bezout(long a, long b, long& x, long& y) {
 
 }  // namespace
 
-int build_periodic_face(int dom, double Tu, double Tv, int l0, int l1, const std::vector<HostSeg>& segs,
-                        const std::vector<PLoop>& loops, std::vector<PUnit>& units, PFace& pf) {
-    pf = PFace{};
-    pf.dom = dom;
-    pf.Tu = Tu;
-    pf.Tv = Tv;
-    pf.u0 = (int)units.size();
+int torus_setup(int dom, double Tu, double Tv, int l0, int l1, const std::vector<PLoop>& loops, TorusSetup& ts) {
+    ts = TorusSetup{};
     // common homology of the non-contractible loops
     int hs0 = 0, hs1 = 0;
     for (int l = l0; l < l1; ++l) {
@@ -191,6 +186,95 @@ int build_periodic_face(int dom, double Tu, double Tv, int l0, int l1, const std
         }
         if (g0 != hs0 || g1 != hs1) return 1;  // two different homology classes
     }
+    ts.hs0 = hs0;
+    ts.hs1 = hs1;
+    if (dom != 2 || (hs0 == 0 && hs1 == 0)) return 0;
+    if (gcd_l(hs0, hs1) != 1) return 1;
+    for (int l = l0; l < l1; ++l) {
+        const PLoop& L = loops[l];
+        if (L.s1 == L.s0) continue;
+        if (L.h0 == hs0 && L.h1 == hs1) ts.A.push_back(l);
+        else if (L.h0 == -hs0 && L.h1 == -hs1) ts.B.push_back(l);
+    }
+    if (ts.A.size() != ts.B.size()) return 1;
+    long ea, eb;
+    bezout(labs(hs0), labs(hs1), ea, eb);
+    if (hs0 < 0) ea = -ea;
+    if (hs1 < 0) eb = -eb;
+    ts.t1x = -(double)eb * Tu;
+    ts.t1y = (double)ea * Tv;
+    const double vx = hs0 * Tu, vy = hs1 * Tv;
+    const double lv = hypot(vx, vy);
+    ts.nx = -vy / lv;
+    ts.ny = vx / lv;
+    ts.Delta = Tu * Tv / lv;
+    return 0;
+}
+
+int torus_pair_host(const std::vector<HostSeg>& segs, const std::vector<PLoop>& loops, const TorusSetup& ts,
+                    std::vector<int2>& choice) {
+    choice.assign(ts.A.size(), make_int2(-1, 0));
+    std::vector<char> used(ts.B.size(), 0);
+    for (size_t ia = 0; ia < ts.A.size(); ++ia) {
+        const PLoop& La = loops[ts.A[ia]];
+        int best = -1;
+        long bms = 0;
+        double bshx = 0.0, bshy = 0.0;
+        for (size_t j = 0; j < ts.B.size(); ++j) {
+            if (used[j]) continue;
+            const PLoop& Lb = loops[ts.B[j]];
+            double px, py;
+            loop_point(segs, Lb, px, py);
+            const double eta = ts.nx * (px - La.b0x) + ts.ny * (py - La.b0y);
+            const long m0 = (long)floor(-eta / ts.Delta);
+            bool found = false;
+            long ms = 0;
+            for (long m = m0 - 3; m <= m0 + 4 && !found; ++m) {
+                if (host_extended(segs, La, px + (double)m * ts.t1x, py + (double)m * ts.t1y) > 0.0) {
+                    ms = m;
+                    found = true;
+                }
+            }
+            if (!found) continue;
+            const double shx = (double)ms * ts.t1x, shy = (double)ms * ts.t1y;
+            if (best < 0) {
+                best = (int)j;
+                bms = ms;
+                bshx = shx;
+                bshy = shy;
+            } else {
+                // the candidate replaces the best when it lies on the best's
+                // left (App. C.2, PairLoops): the beta copies face alpha with
+                // their left sides, so it is then the nearer one
+                if (host_extended(segs, loops[ts.B[best]], px + shx - bshx, py + shy - bshy) > 0.0) {
+                    best = (int)j;
+                    bms = ms;
+                    bshx = shx;
+                    bshy = shy;
+                }
+            }
+        }
+        if (best < 0) return 1;
+        used[best] = 1;
+        choice[ia] = make_int2(best, (int)bms);
+    }
+    return 0;
+}
+
+int build_periodic_face(int dom, double Tu, double Tv, int l0, int l1, const std::vector<HostSeg>& segs,
+                        const std::vector<PLoop>& loops, const TorusSetup* ts, const int2* choice,
+                        std::vector<PUnit>& units, PFace& pf) {
+    pf = PFace{};
+    pf.dom = dom;
+    pf.Tu = Tu;
+    pf.Tv = Tv;
+    pf.u0 = (int)units.size();
+    TorusSetup local;
+    if (!ts) {
+        if (torus_setup(dom, Tu, Tv, l0, l1, loops, local) != 0) return 1;
+        ts = &local;
+    }
+    const int hs0 = ts->hs0;
     for (int l = l0; l < l1; ++l) {
         const PLoop& L = loops[l];
         if (L.s1 == L.s0) continue;
@@ -208,75 +292,34 @@ int build_periodic_face(int dom, double Tu, double Tv, int l0, int l1, const std
         }
     }
     if ((dom == 3 || dom == 4) && puncture_offset(segs, loops, l0, l1, pf.offset) != 0) return 1;
-    if (dom == 2 && (hs0 != 0 || hs1 != 0)) {
-        if (gcd_l(hs0, hs1) != 1) return 1;
-        std::vector<int> A, B;
-        for (int l = l0; l < l1; ++l) {
-            const PLoop& L = loops[l];
-            if (L.s1 == L.s0) continue;
-            if (L.h0 == hs0 && L.h1 == hs1) A.push_back(l);
-            else if (L.h0 == -hs0 && L.h1 == -hs1) B.push_back(l);
+    if (dom == 2 && (ts->hs0 != 0 || ts->hs1 != 0)) {
+        pf.t1x = ts->t1x;
+        pf.t1y = ts->t1y;
+        pf.nx = ts->nx;
+        pf.ny = ts->ny;
+        pf.Delta = ts->Delta;
+        std::vector<int2> host_choice;
+        if (!choice) {
+            if (torus_pair_host(segs, loops, *ts, host_choice) != 0) return 1;
+            choice = host_choice.data();
         }
-        if (A.size() != B.size()) return 1;
-        long ea, eb;
-        bezout(labs(hs0), labs(hs1), ea, eb);
-        if (hs0 < 0) ea = -ea;
-        if (hs1 < 0) eb = -eb;
-        pf.t1x = -(double)eb * Tu;
-        pf.t1y = (double)ea * Tv;
-        const double vx = hs0 * Tu, vy = hs1 * Tv;
-        const double lv = hypot(vx, vy);
-        pf.nx = -vy / lv;
-        pf.ny = vx / lv;
-        pf.Delta = Tu * Tv / lv;
-        std::vector<char> used(B.size(), 0);
-        for (int a : A) {
+        std::vector<char> used(ts->B.size(), 0);
+        for (size_t ia = 0; ia < ts->A.size(); ++ia) {
+            const int a = ts->A[ia];
             const PLoop& La = loops[a];
-            int best = -1;
-            double bshx = 0.0, bshy = 0.0;
-            for (size_t j = 0; j < B.size(); ++j) {
-                if (used[j]) continue;
-                const PLoop& Lb = loops[B[j]];
-                double px, py;
-                loop_point(segs, Lb, px, py);
-                const double eta = pf.nx * (px - La.b0x) + pf.ny * (py - La.b0y);
-                const long m0 = (long)floor(-eta / pf.Delta);
-                bool found = false;
-                long ms = 0;
-                for (long m = m0 - 3; m <= m0 + 4 && !found; ++m) {
-                    if (host_extended(segs, La, px + (double)m * pf.t1x, py + (double)m * pf.t1y) > 0.0) {
-                        ms = m;
-                        found = true;
-                    }
-                }
-                if (!found) continue;
-                const double shx = (double)ms * pf.t1x, shy = (double)ms * pf.t1y;
-                if (best < 0) {
-                    best = (int)j;
-                    bshx = shx;
-                    bshy = shy;
-                } else {
-                    // the candidate replaces the best when it lies on the best's
-                    // left (App. C.2, PairLoops): the beta copies face alpha with
-                    // their left sides, so it is then the nearer one
-                    if (host_extended(segs, loops[B[best]], px + shx - bshx, py + shy - bshy) > 0.0) {
-                        best = (int)j;
-                        bshx = shx;
-                        bshy = shy;
-                    }
-                }
-            }
-            if (best < 0) return 1;
+            const int best = choice[ia].x;
+            if (best < 0 || best >= (int)ts->B.size() || used[best]) return 1;
             used[best] = 1;
+            const double bshx = (double)choice[ia].y * ts->t1x, bshy = (double)choice[ia].y * ts->t1y;
             PUnit U{};
             U.kind = kUnitPair;
             U.la = a;
-            U.lb = B[best];
+            U.lb = ts->B[best];
             U.pshx = bshx;
             U.pshy = bshy;
             double lo = INFINITY, hi = -INFINITY;
             for (int w = 0; w < 2; ++w) {
-                const PLoop& L = loops[w == 0 ? a : B[best]];
+                const PLoop& L = loops[w == 0 ? a : ts->B[best]];
                 const double sx = w == 0 ? 0.0 : bshx, sy = w == 0 ? 0.0 : bshy;
                 for (int s = L.s0; s < L.s1; ++s) {
                     const HostSeg& g = segs[s];

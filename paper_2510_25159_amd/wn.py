@@ -29,8 +29,9 @@ EXPORTS = [
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
     "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy", "wn_nurbs_to_bezier",
     "wn_classify_grid", "wn_classify_surfaces", "wn_create_faces_nurbs", "wn_near_pairs",
-    "wn_query_noalloc", "wn_query_noalloc_scratch_bytes",
+    "wn_query_noalloc", "wn_query_noalloc_scratch_bytes", "wn_torus_pairs",
 ]
+FLAG_HOST_PAIRING = 1
 NOALLOC_MAX_POINTS, NOALLOC_MAX_FACES = 1 << 22, 1 << 18
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -133,6 +134,8 @@ def lib():
         L.wn_query_noalloc.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.POINTER(wn_query_opts), _P]
         L.wn_query_noalloc_scratch_bytes.restype = ctypes.c_int64
         L.wn_query_noalloc_scratch_bytes.argtypes = []
+        L.wn_torus_pairs.restype = ctypes.c_int
+        L.wn_torus_pairs.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]
         L.wn_destroy_faces.argtypes = [_P]
         L.wn_segment_bound.restype = ctypes.c_int
         L.wn_segment_bound.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
@@ -387,6 +390,22 @@ class FaceSet:
         if st != WN_OK:
             raise WnError(st, "wn_query_ex")
         return out_w, out_lab
+
+    def torus_pairs(self, face: int):
+        """Pair table of a torus face: (alpha int32 [P], beta int32 [P], shift float64 [P, 2])."""
+        cnt = ctypes.c_int32(0)
+        st = lib().wn_torus_pairs(self._h, face, 0, None, None, None, ctypes.byref(cnt))
+        if st != WN_OK:
+            raise WnError(st, "wn_torus_pairs")
+        n = cnt.value
+        a = np.zeros(n, dtype=np.int32)
+        b = np.zeros(n, dtype=np.int32)
+        sh = np.zeros((n, 2), dtype=np.float64)
+        if n:
+            st = lib().wn_torus_pairs(self._h, face, n, _np_ptr(a), _np_ptr(b), _np_ptr(sh), ctypes.byref(cnt))
+            if st != WN_OK:
+                raise WnError(st, "wn_torus_pairs")
+        return a, b, sh
 
     def query_noalloc(self, u, v, offsets, out_w, out_lab, *, offsets_host=None, stride: int = 1, stream=None,
                       **opts):

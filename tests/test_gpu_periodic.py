@@ -90,6 +90,10 @@ def test_mixed_planar_and_periodic_faces(torch_cuda, oracle_lib):
     for sched in (0, 1):
         w, lab = run_wn(faces, q, schedule=sched)
         compare(w, lab, w_o, n_o)
+        # device offsets only: the plain schedule builds its face tiles on the
+        # device (one in-line launch per domain kind, nothing read back)
+        w, lab = run_wn(faces, q, schedule=sched, offsets_host=False)
+        compare(w, lab, w_o, n_o)
     w, lab = run_wn(faces, q, schedule=1, near_capacity=300)  # both redo kernels
     compare(w, lab, w_o, n_o)
 
