@@ -310,6 +310,11 @@ def section_config5(args):
     return serving.run(duration=args.serving_duration)
 
 
+SECTIONS = (("config1", section_config1), ("long_path", section_long_path), ("config3", section_config3),
+            ("config4", section_config4), ("config5", section_config5), ("spheres", section_spheres),
+            ("tessellation", section_tessellation), ("multipatch", section_multipatch))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +339,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed batched steps and the work counters (profiling runs)")
     ap.add_argument("--sections", default="", help="comma list of the extra sections to run (default: all)")
+    ap.add_argument("--sections-only", action="store_true",
+                    help="run only the extra sections named by --sections (profiling runs of other workloads)")
     ap.add_argument("--serving-duration", type=float, default=10.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration under rocprofv3)")
@@ -350,6 +357,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.sections_only:
+        only = {x for x in args.sections.split(",") if x}
+        res = {}
+        for name, fn in SECTIONS:
+            if name in only:
+                t = time.time()
+                res[name] = fn(args)
+                log(f"{name}: {time.time() - t:.1f}s")
+        print(json.dumps({"sections": res}), flush=True)
+        return
     t0 = time.time()
     faces, q = W.config2(face_ids=range(args.faces))
     S_f = faces.face_segment_counts()
@@ -574,10 +591,7 @@ def main():
     sections = {}
     if not args.no_extra:
         only = {x for x in args.sections.split(",") if x}
-        for name, fn in (("config1", section_config1), ("long_path", section_long_path), ("config3", section_config3),
-                         ("config4", section_config4), ("config5", section_config5),
-                         ("spheres", section_spheres), ("tessellation", section_tessellation),
-                         ("multipatch", section_multipatch)):
+        for name, fn in SECTIONS:
             if only and name not in only:
                 continue
             t = time.time()

@@ -342,6 +342,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->bpc_far_per = far_periodic_blocks_per_cu(kPerQueue);
     h->bpc_redo_per = far_periodic_blocks_per_cu(kPerRedo);
     h->bpc_near = near_blocks_per_cu();
+    h->bpc_near_cp = near_cp_blocks_per_cu();
 
     // faces ordered by segment count (largest first) for the work queues
     std::vector<int32_t> ord_plan, ord_per;
@@ -785,6 +786,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
                         !(q.bin_source == WN_BIN_PREDICTOR && !q.predictor);
     if (q.bin_source < 0 || q.bin_source > WN_BIN_NONE) return WN_E_INVALID;
     if (q.path_hierarchy < 0 || q.path_hierarchy > 2) return WN_E_INVALID;
+    if (q.bound != WN_BOUND_GLOBAL && q.bound != WN_BOUND_SUBDIVIDED) return WN_E_INVALID;
+    const bool cp = q.bound == WN_BOUND_SUBDIVIDED;
     int64_t cap = q.near_capacity > 0 ? q.near_capacity : 8 * N + 65536;
     cap = std::min<int64_t>(cap, (int64_t)1 << 34);
     if (plain) cap = 0;  // periodic faces of the plain schedule recurse in line
@@ -861,7 +864,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     // captured into a plan, no work counters)
     sc.near_lo = nullptr;
     sc.near_join = nullptr;
-    const int64_t* ovl = (!binned && !preset && !q.stats && prec == WN_PREC_FP64) ? p->face_point_offsets_host : nullptr;
+    const int64_t* ovl =
+        (!binned && !preset && !q.stats && !cp && prec == WN_PREC_FP64) ? p->face_point_offsets_host : nullptr;
     e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st, ovl);
     NearQueue nq = sc.nq;
     if (e == hipSuccess && binned) {
@@ -869,7 +873,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
         if (q.bin_source == WN_BIN_MEASURED) {
             // first near pass into throw-away outputs, logging each entry's depth
             const Out tmp{sc.w_tmp, sc.lab_tmp, nullptr, 0, rule};
-            e = near_pass(h, pts, sc.nq, tmp, nullptr, sc.depth, nullptr, st);
+            e = near_pass(h, pts, sc.nq, tmp, nullptr, sc.depth, nullptr, st, near_cursor(sc, 1), cp);
         }
         if (e == hipSuccess) {
             ProfScope ps(q.profile, WN_KERNEL_BIN, st);
@@ -885,10 +889,10 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
         {
             ProfScope ps(q.profile, WN_KERNEL_NEAR, st);
             e = launch_near(h->sg, pts, nq, sc.out, h->eps2, (int64_t)h->cu_count * h->bpc_near, Stats{nullptr},
-                            h->pt.seg_periodic, nullptr, st, sc.near_lo, nullptr);
+                            h->pt.seg_periodic, nullptr, st, sc.near_lo, nullptr, near_cursor(sc, 3));
         }
     } else if (e == hipSuccess) {
-        e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st);
+        e = near_pass(h, pts, nq, sc.out, q.stats, nullptr, q.profile, st, near_cursor(sc, 0), cp);
     }
     if (sc.near_join) {
         // join the side stream (errors included: the scratch is released on st)
@@ -1043,7 +1047,7 @@ static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, cons
         if (e == hipSuccess) {
             ProfScope ps(prof, WN_KERNEL_NEAR, h->side);
             e = launch_near(h->sg, pts, sc.nq, sc.out, h->eps2, side_grid, Stats{nullptr}, h->pt.seg_periodic,
-                            nullptr, h->side, k == 0 ? nullptr : marks + k - 1, marks + k);
+                            nullptr, h->side, k == 0 ? nullptr : marks + k - 1, marks + k, near_cursor(sc, k));
         }
     }
     // The join is recorded whatever happened, so that the query stream always
@@ -1136,10 +1140,14 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
 }
 
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
-                     uint8_t* entry_depth, wn_profile* prof, hipStream_t st) {
+                     uint8_t* entry_depth, wn_profile* prof, hipStream_t st, unsigned long long* cursor,
+                     bool cp_bound) {
     ProfScope ps(prof, WN_KERNEL_NEAR, st);
+    if (cp_bound)
+        return launch_near_cp(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * h->bpc_near_cp, Stats{stats},
+                              h->pt.seg_periodic, entry_depth, st, nullptr, nullptr, cursor);
     return launch_near(h->sg, pts, nq, out, h->eps2, (int64_t)h->cu_count * h->bpc_near, Stats{stats},
-                       h->pt.seg_periodic, entry_depth, st);
+                       h->pt.seg_periodic, entry_depth, st, nullptr, nullptr, cursor);
 }
 
 }  // namespace wn

@@ -25,6 +25,7 @@ struct wn_faces {
     int cu_count = 0;
     int bpc_far[2][3] = {{1, 1, 1}, {1, 1, 1}};  // resident workgroups per CU, k_far batched: [FP64, MIXED][64/128/256 points per workgroup]
     int bpc_farq[5] = {1, 1, 1, 1, 1}, bpc_far_tree = 1, bpc_far_per = 1, bpc_redo_per = 1, bpc_near = 1;
+    int bpc_near_cp = 1;
     std::vector<int32_t> h_seg_begin;
     std::vector<int32_t> h_dom;
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
@@ -92,7 +93,14 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
                       wn_profile* prof, hipStream_t st, const int64_t* host_offs = nullptr);
 // Near pass over nq; entry_depth optional.
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
-                     uint8_t* entry_depth, wn_profile* prof, hipStream_t st);
+                     uint8_t* entry_depth, wn_profile* prof, hipStream_t st, unsigned long long* cursor,
+                     bool cp_bound = false);
+
+// Chunk cursor i (0..3) of a query's near passes, in the scratch counters
+// (zeroed by the query's first item build).
+inline unsigned long long* near_cursor(const Scratch& sc, int i) {
+    return reinterpret_cast<unsigned long long*>(sc.counters + 24) + i;
+}
 int binning_grid(const wn_faces* h);
 
 wn_status hip_status(hipError_t e);

@@ -178,9 +178,17 @@ hipError_t launch_far(bool inline_near, bool mixed, int qpw, const Segs& sg, con
                       const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int32_t single_face,
                       int64_t grid, NearQueue nq, Out out, double eps2, hipStream_t st);
 // Near pass over queue entries [*q_lo, *q_hi) (nullptr: 0 / the queue's count).
+// Near pass over queue entries [q_lo, q_hi) (defaults: 0 and the queue's
+// count).  cursor (nullable, zero at launch): waves take chunks of entries
+// from it (dynamic balance); without it each wave takes one equal share.
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
                        Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st,
-                       const unsigned long long* q_lo = nullptr, const unsigned long long* q_hi = nullptr);
+                       const unsigned long long* q_lo = nullptr, const unsigned long long* q_hi = nullptr,
+                       unsigned long long* cursor = nullptr);
+// The same pass with the subdivided control-point bound (WN_BOUND_SUBDIVIDED).
+hipError_t launch_near_cp(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
+                          Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st,
+                          const unsigned long long* q_lo, const unsigned long long* q_hi, unsigned long long* cursor);
 hipError_t launch_queue_mark(const unsigned long long* count, unsigned long long* mark, hipStream_t st);
 // Queue entries [0, n) -> their query and segment indices (diagnostics).
 hipError_t launch_split_pairs(const uint2* qs, int64_t n, int32_t* point, int32_t* segment, hipStream_t st);
@@ -201,6 +209,7 @@ hipError_t launch_farq(int qpl, const Segs& sg, const FaceTab& ft, const Points&
                        hipStream_t st, int rank_lo = 0, int rank_hi = -1);
 int farq_blocks_per_cu(int qpl);
 int near_blocks_per_cu();
+int near_cp_blocks_per_cu();
 hipError_t launch_lift(const LiftArgs& a, Segs sg_mut, hipStream_t st);
 
 // One torus face for the pairing kernel: A = lists[a0 .. a0 + na), B =

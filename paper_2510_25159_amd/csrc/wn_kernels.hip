@@ -70,10 +70,12 @@ __global__ __launch_bounds__(1024) void k_build_items(FaceTab ft, Points pts, in
     const int chunk = (F + 1023) / 1024;
     const int r0 = min(F, tid * chunk), r1 = min(F, r0 + chunk);
     // [0] far item counter, [1] periodic redo item counter, [2..3] near-queue
-    // count (64-bit, reset by the first build of a query only), [8..15] item
-    // counters of the phases of an overlapped far pass
+    // count (64-bit), [8..15] item counters of the phases of an overlapped far
+    // pass, [16..23] queue marks of those phases, [24..31] chunk cursors of up
+    // to four near passes (64-bit).  The near count and the cursors are reset
+    // by the first build of a query only.
     if (tid < 2 || (tid >= 8 && tid < 16)) counters[tid] = 0;
-    if (zero_near && (tid == 2 || tid == 3)) counters[tid] = 0;
+    if (zero_near && (tid == 2 || tid == 3 || (tid >= 24 && tid < 32))) counters[tid] = 0;
     auto tiles_of = [&](int r) -> int64_t {
         const int f = ft.order[r];
         int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
@@ -870,27 +872,31 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
+// Queue entries per chunk taken by a wave from the pass's cursor.
+constexpr unsigned long long kNearChunk = 512;
+
 template <bool COUNT>
 __global__ __launch_bounds__(kWG) void k_near(
     Segs sg, Points pts, NearQueue nq, Out out, double eps2, Stats stats, const uint8_t* seg_per,
-    uint8_t* entry_depth, const unsigned long long* q_lo, const unsigned long long* q_hi) {
+    uint8_t* entry_depth, const unsigned long long* q_lo, const unsigned long long* q_hi,
+    unsigned long long* cursor) {
     __shared__ double4 s_stack[kWavesPerWG * kNearSlots * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     double4* stk = s_stack + wave * kNearSlots * kWave + lane;
-    // queue entries [q_lo, q_hi) (defaults: 0 and the queue's count), split
-    // evenly over the waves
+    // Queue entries [q_lo, q_hi) (defaults: 0 and the queue's count).  With a
+    // cursor (zero at launch), a wave that runs dry takes the next chunk of
+    // kNearChunk entries from it, so the pass ends when the work does rather
+    // than when the slowest of equal shares does; without one, each wave takes
+    // one equal share.
     unsigned long long n = q_hi ? *q_hi : *nq.count;
     n = n < nq.cap ? n : nq.cap;
     unsigned long long base = q_lo ? *q_lo : 0ull;
     base = base < n ? base : n;
-    const unsigned long long nw = (unsigned long long)gridDim.x * kWavesPerWG;
     const unsigned long long gw = (unsigned long long)blockIdx.x * kWavesPerWG + wave;
-    const unsigned long long per = (n - base + nw - 1) / nw;
-    // wave-uniform bounds and cursor, kept in scalar registers
-    const unsigned long long c_begin = uniform_u64(base + gw * per < n ? base + gw * per : n);
-    const unsigned long long c_end = uniform_u64(c_begin + per < n ? c_begin + per : n);
-    unsigned long long next = c_begin;
+    // wave-uniform chunk [next, c_end), kept in scalar registers
+    unsigned long long next = 0, c_end = 0;
+    bool more = true, shared_once = false;
     NodeState st;
     bool onb = false, has = false;
     uint32_t q = 0;
@@ -899,37 +905,60 @@ __global__ __launch_bounds__(kWG) void k_near(
     NodeCount nc;
     // window of the next 64 queue entries, one per lane, loaded one refill ahead
     uint2 win = make_uint2(0xffffffffu, 0u);
-    if (next + lane < c_end) win = nq.qs[next + lane];
+    auto grab = [&]() {
+        if (cursor) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(cursor, kNearChunk);
+            c = uniform_u64(c);  // lane 0's
+            next = uniform_u64(base + c < n ? base + c : n);
+            c_end = uniform_u64(next + kNearChunk < n ? next + kNearChunk : n);
+        } else if (!shared_once) {
+            const unsigned long long nw = (unsigned long long)gridDim.x * kWavesPerWG;
+            const unsigned long long per = (n - base + nw - 1) / nw;
+            next = uniform_u64(base + gw * per < n ? base + gw * per : n);
+            c_end = uniform_u64(next + per < n ? next + per : n);
+            shared_once = true;
+        } else {
+            next = c_end = n;
+        }
+        more = next < c_end;
+        if (next + lane < c_end) win = nq.qs[next + lane];
+    };
+    grab();
     for (;;) {
         const uint64_t idle = __ballot(!has);
         // refill idle lanes once kRefillMin of them are idle (each refill
         // waits for the gathers of the new pairs' data)
-        if (idle && next < c_end && (__popcll(idle) >= kRefillMin || idle == ~0ull)) {
-            const int rank = lanes_below(idle);
-            uint2 e;  // all lanes active here: entry next + rank comes from lane rank of the window
-            e.x = (uint32_t)__shfl((int)win.x, rank);
-            e.y = (uint32_t)__shfl((int)win.y, rank);
-            if (!has && next + rank < c_end) {
-                q = e.x;
-                cur = next + rank;
-                if ((int64_t)q < pts.n) {
-                    qx = pts.u[(int64_t)q * pts.stride];
-                    qy = pts.v[(int64_t)q * pts.stride];
-                    if (nq.shift && seg_per[e.y]) {  // periodic copy: translate the query (App. C.1)
-                        const double2 sh = nq.shift[next + rank];
-                        qx -= sh.x;
-                        qy -= sh.y;
+        if (idle && more && (__popcll(idle) >= kRefillMin || idle == ~0ull)) {
+            if (next >= c_end) grab();
+            if (more) {
+                const int rank = lanes_below(idle);
+                uint2 e;  // all lanes active here: entry next + rank comes from lane rank of the window
+                e.x = (uint32_t)__shfl((int)win.x, rank);
+                e.y = (uint32_t)__shfl((int)win.y, rank);
+                if (!has && next + rank < c_end) {
+                    q = e.x;
+                    cur = next + rank;
+                    if ((int64_t)q < pts.n) {
+                        qx = pts.u[(int64_t)q * pts.stride];
+                        qy = pts.v[(int64_t)q * pts.stride];
+                        if (nq.shift && seg_per[e.y]) {  // periodic copy: translate the query (App. C.1)
+                            const double2 sh = nq.shift[next + rank];
+                            qx -= sh.x;
+                            qy -= sh.y;
+                        }
+                        node_init(st, sg, e.y, qx, qy);
+                        onb = false;
+                        has = true;
                     }
-                    node_init(st, sg, e.y, qx, qy);
-                    onb = false;
-                    has = true;
                 }
+                const unsigned long long took = (unsigned long long)__popcll(idle);
+                next = uniform_u64(next + took < c_end ? next + took : c_end);
+                if (next + lane < c_end) win = nq.qs[next + lane];
             }
-            next = uniform_u64(next + (unsigned long long)__popcll(idle));
-            if (next + lane < c_end) win = nq.qs[next + lane];
         }
         if (!__any(has)) {
-            if (next >= c_end) break;
+            if (!more) break;
             continue;
         }
         if (COUNT) {
@@ -1095,14 +1124,14 @@ hipError_t launch_far(bool inline_near, bool mixed, int qpw, const Segs& sg, con
 
 hipError_t launch_near(const Segs& sg, const Points& pts, NearQueue nq, Out out, double eps2, int64_t grid,
                        Stats stats, const uint8_t* seg_per, uint8_t* entry_depth, hipStream_t st,
-                       const unsigned long long* q_lo, const unsigned long long* q_hi) {
+                       const unsigned long long* q_lo, const unsigned long long* q_hi, unsigned long long* cursor) {
     if (grid <= 0) return hipSuccess;
     if (stats.c || entry_depth)
         hipLaunchKernelGGL(k_near<true>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
-                           seg_per, entry_depth, q_lo, q_hi);
+                           seg_per, entry_depth, q_lo, q_hi, cursor);
     else
         hipLaunchKernelGGL(k_near<false>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, pts, nq, out, eps2, stats,
-                           seg_per, entry_depth, q_lo, q_hi);
+                           seg_per, entry_depth, q_lo, q_hi, cursor);
     return hipGetLastError();
 }
 

@@ -145,8 +145,9 @@ wn_status wn_pair_features(const wn_faces* h, const wn_points* pts, const int32_
 
 wn_status wn_near_pairs(const wn_faces* h, const wn_points* p, int64_t capacity, int32_t* pair_point,
                         int32_t* pair_segment, uint8_t* pair_depth, double* pair_shift, int64_t* out_count,
-                        void* stream) {
+                        int32_t bound, void* stream) {
     if (!h || !p || !out_count || capacity < 0) return WN_E_INVALID;
+    if (bound != WN_BOUND_GLOBAL && bound != WN_BOUND_SUBDIVIDED) return WN_E_INVALID;
     if (capacity > 0 && (!pair_point || !pair_segment || !pair_depth)) return WN_E_INVALID;
     const int64_t N = p->num_points;
     if (N < 0 || N >= 0x7fffffffll) return WN_E_INVALID;
@@ -164,7 +165,8 @@ wn_status wn_near_pairs(const wn_faces* h, const wn_points* p, int64_t capacity,
     uint8_t* d_depth = nullptr;
     e = hipMallocAsync((void**)&d_depth, (size_t)cap, st);
     if (e == hipSuccess) e = far_passes(h, pts, 256, 1, false, 0, sc, nullptr, st);
-    if (e == hipSuccess) e = near_pass(h, pts, sc.nq, sc.out, nullptr, d_depth, nullptr, st);
+    if (e == hipSuccess) e = near_pass(h, pts, sc.nq, sc.out, nullptr, d_depth, nullptr, st, near_cursor(sc, 0),
+                                                  bound == WN_BOUND_SUBDIVIDED);
     unsigned long long cnt = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&cnt, sc.nq.count, 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -216,7 +218,7 @@ wn_status wn_predictor_train(wn_predictor* pr, const wn_faces* h, const wn_point
     uint8_t* d_depth = nullptr;
     e = hipMallocAsync((void**)&d_depth, (size_t)cap, st);
     if (e == hipSuccess) e = far_passes(h, pts, 256, 1, false, 0, sc, nullptr, st);
-    if (e == hipSuccess) e = near_pass(h, pts, sc.nq, sc.out, nullptr, d_depth, nullptr, st);
+    if (e == hipSuccess) e = near_pass(h, pts, sc.nq, sc.out, nullptr, d_depth, nullptr, st, near_cursor(sc, 0));
     unsigned long long cnt = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&cnt, sc.nq.count, 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
