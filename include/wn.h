@@ -211,7 +211,16 @@ typedef struct {
                                 subpath are classified instead of reported on-boundary);
                                 2 = automatic: the hierarchy for faces with a chain of at
                                 least 512 joined segments, the flat scan for the others   */
+    int32_t bound;           /* WN_BOUND_GLOBAL (default): a node [a, b] of Alg. 1 has the
+                                axis B (b - a) (Sec. 4.2); WN_BOUND_SUBDIVIDED: the smaller of
+                                that and the Lemma 1 / App. A.1 bound of the node's own
+                                control points (de Casteljau halving, the control-point bound
+                                Table 1 contrasts): fewer or equal splits, the same omega.
+                                Applies to the near pass of the batched and binned schedules
+                                (in-line recursions keep the global bound)                  */
 } wn_query_opts;
+
+enum { WN_BOUND_GLOBAL = 0, WN_BOUND_SUBDIVIDED = 1 };
 
 /* Work counters of the batched schedules (wn_query_opts.stats). */
 enum {
@@ -501,12 +510,14 @@ wn_status wn_pair_features(const wn_faces* faces, const wn_points* points, const
  *                  copy (zero for planar pairs)
  *   out_count      host: the number of near pairs (entries beyond capacity are
  *                  not written)
+ *   bound          WN_BOUND_GLOBAL or WN_BOUND_SUBDIVIDED: the near pass's node
+ *                  bound (wn_query_opts.bound)
  * Diagnostics and training data: allocates its scratch and synchronizes
  * `stream`.  WN_E_NOMEM when the near pairs exceed the internal queue
  * (8 N + 65536 entries, or capacity if larger). */
 wn_status wn_near_pairs(const wn_faces* faces, const wn_points* points, int64_t capacity, int32_t* pair_point,
                         int32_t* pair_segment, uint8_t* pair_depth, double* pair_shift, int64_t* out_count,
-                        void* stream);
+                        int32_t bound, void* stream);
 
 /* Plans: a preallocated batched query captured once into a HIP graph.  The
  * caller owns the point buffers (`points`: device u, v with stride, device

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwn.so")
 SOURCES = ["wn_host.hip", "wn_kernels.hip", "wn_periodic.hip", "wn_topology.hip", "wn_learn.hip",
-           "wn_predictor.hip", "wn_plan.hip", "wn_nurbs.hip", "wn_patches.hip", "wn_noalloc.hip", "wn_pairing.hip"]
+           "wn_predictor.hip", "wn_plan.hip", "wn_nurbs.hip", "wn_patches.hip", "wn_noalloc.hip", "wn_pairing.hip", "wn_near_cp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

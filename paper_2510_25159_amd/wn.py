@@ -36,6 +36,7 @@ NOALLOC_MAX_POINTS, NOALLOC_MAX_FACES = 1 << 22, 1 << 18
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 BIN_PREDICTOR, BIN_HEURISTIC, BIN_MEASURED, BIN_NONE = 0, 1, 2, 3
+BOUND_GLOBAL, BOUND_SUBDIVIDED = 0, 1
 KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO, KERNEL_FAR_PERIODIC = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo", 5: "k_far_periodic",
                 6: "k_bin"}
@@ -81,7 +82,8 @@ class wn_query_opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("queries_per_wg", ctypes.c_int32), ("queue_policy", ctypes.c_int32),
                 ("near_capacity", ctypes.c_int64), ("depth_log", _P), ("profile", _P), ("stats", _P),
-                ("predictor", _P), ("bin_source", ctypes.c_int32), ("path_hierarchy", ctypes.c_int32)]
+                ("predictor", _P), ("bin_source", ctypes.c_int32), ("path_hierarchy", ctypes.c_int32),
+                ("bound", ctypes.c_int32)]
 
 
 class wn_train_opts(ctypes.Structure):
@@ -181,7 +183,7 @@ def lib():
                                            ctypes.POINTER(wn_query_opts), _P]
         L.wn_near_pairs.restype = ctypes.c_int
         L.wn_near_pairs.argtypes = [_P, ctypes.POINTER(wn_points), ctypes.c_int64, _P, _P, _P, _P,
-                                    ctypes.POINTER(ctypes.c_int64), _P]
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _P]
         L.wn_get_faces_info.restype = ctypes.c_int
         L.wn_get_faces_info.argtypes = [_P, ctypes.POINTER(wn_faces_info)]
         _lib = L
@@ -365,7 +367,7 @@ class FaceSet:
               schedule: Optional[int] = None, precision: Optional[int] = None, rule: Optional[int] = None,
               queries_per_wg: int = 0, queue_policy: int = 0, near_capacity: int = 0, depth_log=None,
               profile: Optional[Profile] = None, stats=None, predictor=None, bin_source: int = 0,
-              path_hierarchy: int = 0, stream=None):
+              path_hierarchy: int = 0, bound: int = 0, stream=None):
         """Run the query on torch CUDA tensors (float64 u, v; int64 offsets).
 
         Returns (out_w, out_lab) torch tensors (allocated when not given)."""
@@ -384,7 +386,8 @@ class FaceSet:
         p = wn_points(n, u.data_ptr(), v.data_ptr(), stride, offsets.data_ptr(), _np_ptr(hoffs))
         q = _query_opts(schedule=schedule, precision=precision, rule=rule, queries_per_wg=queries_per_wg,
                         queue_policy=queue_policy, near_capacity=near_capacity, depth_log=depth_log, profile=profile,
-                        stats=stats, predictor=predictor, bin_source=bin_source, path_hierarchy=path_hierarchy)
+                        stats=stats, predictor=predictor, bin_source=bin_source, path_hierarchy=path_hierarchy,
+                        bound=bound)
         st = lib().wn_query_ex(self._h, ctypes.byref(p), out_w.data_ptr(), out_lab.data_ptr(), ctypes.byref(q),
                                _stream_ptr(stream))
         if st != WN_OK:
@@ -474,7 +477,7 @@ class FaceSet:
 
 
 def _query_opts(schedule=None, precision=None, rule=None, queries_per_wg=0, queue_policy=0, near_capacity=0,
-                depth_log=None, profile=None, stats=None, predictor=None, bin_source=0, path_hierarchy=0):
+                depth_log=None, profile=None, stats=None, predictor=None, bin_source=0, path_hierarchy=0, bound=0):
     """wn_query_opts from keyword overrides (None / 0 = default)."""
     q = wn_query_opts()
     lib().wn_default_query_opts(ctypes.byref(q))
@@ -493,6 +496,7 @@ def _query_opts(schedule=None, precision=None, rule=None, queries_per_wg=0, queu
     q.predictor = None if predictor is None else predictor.handle
     q.bin_source = bin_source
     q.path_hierarchy = path_hierarchy
+    q.bound = bound
     return q
 
 
@@ -571,7 +575,7 @@ class Predictor:
         return out
 
 
-def near_pairs(faceset: "FaceSet", u, v, offsets, capacity: int, stream=None):
+def near_pairs(faceset: "FaceSet", u, v, offsets, capacity: int, stream=None, bound: int = 0):
     """Near pairs of a query and the depth the near pass reached on each:
     (point int32 [n], segment int32 [n], depth uint8 [n], shift float64 [n, 2])
     torch cuda tensors, n = min(count, capacity)."""
@@ -585,7 +589,7 @@ def near_pairs(faceset: "FaceSet", u, v, offsets, capacity: int, stream=None):
     cnt = ctypes.c_int64(0)
     p = _points(u, v, offsets)
     st = lib().wn_near_pairs(faceset._h, ctypes.byref(p), capacity, pp.data_ptr(), ps.data_ptr(), pd.data_ptr(),
-                             sh.data_ptr(), ctypes.byref(cnt), _stream_ptr(stream))
+                             sh.data_ptr(), ctypes.byref(cnt), bound, _stream_ptr(stream))
     if st != WN_OK:
         raise WnError(st, "wn_near_pairs")
     n = min(cnt.value, capacity)
