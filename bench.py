@@ -324,6 +324,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--mixed-steps", type=int, default=5)
     ap.add_argument("--tree-steps", type=int, default=10, help="timed steps with the path hierarchy")
+    ap.add_argument("--cp-steps", type=int, default=3, help="timed steps with the subdivided control-point bound")
     ap.add_argument("--cpu-sample", type=int, default=15000000, help="points of the oracle sample (about 15 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=int, default=1)
@@ -440,8 +441,9 @@ def main():
         kern_serial = ps_.collect()
         log(f"batched, passes in series: {ms_serial:.3f} ms/step; kernels {kern_serial}")
 
-    ms_mixed = ms_tree = ms_plain = float("nan")
-    kern_mixed = kern_tree = {}
+    ms_mixed = ms_tree = ms_plain = ms_cp = float("nan")
+    kern_mixed = kern_tree = kern_cp = work_cp = {}
+    cp_diff = cp_onb = None
     mixed_same = plain_agree = None
     tree_diff = tree_onb = None
 
@@ -484,6 +486,33 @@ def main():
         tree_onb = int(np.sum((lab_t == 2) != (lab_b == 2)))
         log(f"path hierarchy: {ms_tree:.3f} ms/step, {N / (ms_tree / 1e3):.3e} queries/s; kernels {kern_tree}; "
             f"label differences vs flat {tree_diff}, on-boundary differences {tree_onb}")
+
+        # the subdivided control-point bound in the near pass (Sec. 4.2 / Table 1
+        # contrast): fewer splits, the same results, O(n^2) per split
+        def step_cp(profile=None, stats=None):
+            fs.query(u, v, offs, None, out_w, out_l, schedule=args.schedule, queries_per_wg=args.qpw,
+                     queue_policy=args.policy, profile=profile, stats=stats, stream=stream,
+                     bound=wn.BOUND_SUBDIVIDED)
+
+        step_cp()
+        torch.cuda.synchronize()
+        pc = wn.Profile(capacity=8 * args.cp_steps + 64)
+        tc1 = time.perf_counter()
+        for _ in range(args.cp_steps):
+            step_cp(pc)
+        torch.cuda.synchronize()
+        ms_cp = (time.perf_counter() - tc1) * 1e3 / max(args.cp_steps, 1)
+        kern_cp = {k: t_ / max(n, 1) for k, (n, t_) in pc.collect().items()}
+        lab_c = out_l.cpu().numpy()
+        both_c = (lab_c != 2) & (lab_b != 2)
+        cp_diff = int(np.sum(lab_c[both_c] != lab_b[both_c]))
+        cp_onb = int(np.sum((lab_c == 2) != (lab_b == 2)))
+        st_cp = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device=dev)
+        step_cp(stats=st_cp)
+        torch.cuda.synchronize()
+        work_cp = dict(zip(wn.STAT_NAMES, (int(x) for x in st_cp.cpu().numpy())))
+        log(f"subdivided control-point bound: {ms_cp:.3f} ms/step; kernels {kern_cp}; label differences {cp_diff}, "
+            f"on-boundary differences {cp_onb}; work {work_cp}")
 
         # plain schedule beside it (one launch per face, in-line recursion)
         step(0)
@@ -629,6 +658,12 @@ def main():
         "path_hierarchy": {"ms_per_step": ms_tree, "queries_per_s": N / (ms_tree / 1e3), "kernel_ms": kern_tree,
                            "speedup_vs_flat": ms_step / ms_tree, "label_differences_vs_flat": tree_diff,
                            "on_boundary_differences_vs_flat": tree_onb},
+        "subdivided_bound": {"ms_per_step": ms_cp, "kernel_ms": kern_cp, "label_differences_vs_global": cp_diff,
+                             "on_boundary_differences_vs_global": cp_onb,
+                             "splits": work_cp.get("splits"), "leaves": work_cp.get("leaves"),
+                             "max_depth": work_cp.get("max_depth"),
+                             "note": "near pass with the smaller of B 2^-k and the node's control-point bound "
+                                     "(passes in series); compare roofline_serial's k_near and work.splits"},
         "mismatches": mism,
         "kernels": kernels,
         "work": st,
