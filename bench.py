@@ -294,12 +294,29 @@ def section_config4(args):
         fs = wn.FaceSet(fe)
         tens = _dev_queries(torch, qe)
         res = {"train": rep}
-        for name, sched, src in (("unbinned", 1, 3), ("mlp_binned", 2, 0), ("heuristic_binned", 2, 1),
-                                 ("measured_binned", 2, 2)):
+        for name, sched, src in (("unbinned", 1, 3), ("mlp_binned", 2, 0), ("mlp_valu_binned", 2, 4),
+                                 ("heuristic_binned", 2, 1), ("measured_binned", 2, 2)):
             ms, k = _time_query(torch, fs, tens, qe.face_point_offsets, 20, schedule=sched, predictor=pr,
                                 bin_source=src)
             res[name] = {"ms_per_step": ms, "k_near_ms": k.get("k_near"), "k_bin_ms": k.get("k_bin")}
         out[variant] = res
+    # the network alone: 8M standardised feature rows, matrix cores vs VALU
+    n = 8 << 20
+    X = torch.randn(n, wn.MLP_IN, dtype=torch.float32, device="cuda:0")
+    fwd = {}
+    for name, fn in (("mfma", pr.predict_mfma), ("valu", pr.predict)):
+        fn(X)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(20):
+            fn(X)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 20
+        flop = 2.0 * n * (wn.MLP_IN * wn.MLP_HIDDEN + wn.MLP_HIDDEN * wn.MLP_HIDDEN + wn.MLP_HIDDEN)
+        fwd[name] = {"ms": ms, "rows_per_s": n / (ms / 1e3), "tflops": flop / (ms / 1e3) / 1e12}
+    out["mlp_forward_8M_rows"] = fwd
     return out
 
 

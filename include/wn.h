@@ -177,10 +177,14 @@ typedef struct wn_predictor wn_predictor;
 #define WN_MLP_PARAMS (WN_MLP_IN * WN_MLP_HIDDEN + WN_MLP_HIDDEN + WN_MLP_HIDDEN * WN_MLP_HIDDEN + WN_MLP_HIDDEN + WN_MLP_HIDDEN + 1)
 /* Where WN_SCHED_BINNED takes the depth of each near pair from. */
 enum {
-    WN_BIN_PREDICTOR = 0, /* the MLP (falls back to WN_BIN_NONE without a predictor) */
+    WN_BIN_PREDICTOR = 0, /* the MLP on the matrix cores: BF16 weights, inputs and hidden
+                             activations, FP32 accumulation (v_mfma_f32_16x16x32_bf16);
+                             falls back to WN_BIN_NONE without a predictor              */
     WN_BIN_HEURISTIC = 1, /* ceil(log2(B / max(eps, distance from the query to the chord))) */
     WN_BIN_MEASURED = 2,  /* depths measured by a first, discarded near pass (upper bound) */
-    WN_BIN_NONE = 3       /* no reordering (the unbinned queue) */
+    WN_BIN_NONE = 3,      /* no reordering (the unbinned queue) */
+    WN_BIN_PREDICTOR_VALU = 4 /* the MLP as FP32 VALU dot products on BF16-rounded weights
+                                 (the comparison version of WN_BIN_PREDICTOR)           */
 };
 
 /* Per-call overrides and diagnostics (all fields optional: 0/NULL = default). */
@@ -482,8 +486,16 @@ wn_status wn_predictor_set_params(wn_predictor* p, const float* params, const fl
 wn_status wn_predictor_loss_grad(const wn_predictor* p, const float* features, const float* labels, int64_t n,
                                  float huber_delta, float* loss, float* grad, void* stream);
 
-/* Predicted depth for n standardised feature rows (device in/out). */
+/* Predicted depth for n standardised feature rows (device in/out): FP32
+ * VALU dot products on the BF16-rounded weights. */
 wn_status wn_predictor_predict(const wn_predictor* p, const float* features, int64_t n, float* out, void* stream);
+
+/* The same on the matrix cores: the inputs and the layer-1 activations are
+ * rounded to BF16 on their way into v_mfma_f32_16x16x32_bf16 (weights stored
+ * as BF16), accumulation in FP32; persistent waves of 64 rows per step.
+ * features must be 16-byte aligned (WN_E_INVALID otherwise). */
+wn_status wn_predictor_predict_mfma(const wn_predictor* p, const float* features, int64_t n, float* out,
+                                    void* stream);
 
 /* Raw (unstandardised) features of given (point, segment) pairs: pair k is
  * point pair_point[k] of `points` against segment pair_segment[k] (global

@@ -6,6 +6,12 @@ weights to BF16 (round to nearest even) in the forward pass, as the GPU
 kernels do; the gradient is then taken with respect to the unrounded
 parameters with the rounding treated as the identity.  Pinned by central
 finite differences in the tests (``bf16=False``).
+
+``predict(..., bf16_act=True)`` also rounds the inputs and the layer-1
+activations to BF16 before they are multiplied, as the matrix-core version of
+the kernels does (BF16 operands, wide accumulation).  Pinned on small-integer
+networks whose activations are BF16-exact (no change) or fall between two
+BF16 values (round to nearest even).
 """
 import numpy as np
 
@@ -59,9 +65,18 @@ def loss_grad(params, X, Y, delta=1.0, bf16=False):
     return loss, grad
 
 
-def predict(params, X, bf16=True):
+def predict(params, X, bf16=True, bf16_act=False, return_hidden=False):
+    """Network output per row of X (FP64 arithmetic).  bf16: weights rounded
+    to BF16; bf16_act: inputs and layer-1 activations rounded to BF16 too.
+    return_hidden: also the layer-1 activations (after any rounding)."""
     p = np.asarray(params, dtype=np.float64)
     q = unpack(bf16_round(p) if bf16 else p)
-    h1 = np.maximum(np.asarray(X, dtype=np.float64) @ q["W1"].T + q["b1"], 0.0)
+    X = np.asarray(X, dtype=np.float64)
+    if bf16_act:
+        X = bf16_round(X)
+    h1 = np.maximum(X @ q["W1"].T + q["b1"], 0.0)
+    if bf16_act:
+        h1 = bf16_round(h1)
     h2 = np.maximum(h1 @ q["W2"].T + q["b2"], 0.0)
-    return h2 @ q["w3"] + q["b3"][0]
+    y = h2 @ q["w3"] + q["b3"][0]
+    return (y, h1) if return_hidden else y

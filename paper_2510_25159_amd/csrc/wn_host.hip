@@ -783,8 +783,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
 
     const bool plain = sched == WN_SCHED_PLAIN;
     const bool binned = sched == WN_SCHED_BINNED && q.bin_source != WN_BIN_NONE &&
-                        !(q.bin_source == WN_BIN_PREDICTOR && !q.predictor);
-    if (q.bin_source < 0 || q.bin_source > WN_BIN_NONE) return WN_E_INVALID;
+                        !((q.bin_source == WN_BIN_PREDICTOR || q.bin_source == WN_BIN_PREDICTOR_VALU) && !q.predictor);
+    if (q.bin_source < 0 || q.bin_source > WN_BIN_PREDICTOR_VALU) return WN_E_INVALID;
     if (q.path_hierarchy < 0 || q.path_hierarchy > 2) return WN_E_INVALID;
     if (q.bound != WN_BOUND_GLOBAL && q.bound != WN_BOUND_SUBDIVIDED) return WN_E_INVALID;
     const bool cp = q.bound == WN_BOUND_SUBDIVIDED;
@@ -877,9 +877,14 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
         }
         if (e == hipSuccess) {
             ProfScope ps(q.profile, WN_KERNEL_BIN, st);
-            e = launch_binning(h->sg, pts, sc.nq, h->pt.seg_periodic, h->eps, q.bin_source,
-                               pr ? pr->d_wbf : nullptr, pr ? pr->d_norm : nullptr, sc.depth, sc.bins, sc.wg_hist,
-                               binning_grid(h), sc.qs2, sc.sh2, st);
+            // the MLP runs on the matrix cores (BF16 weights) unless the VALU
+            // version is asked for
+            const bool valu = q.bin_source == WN_BIN_PREDICTOR_VALU;
+            const int mode = valu ? WN_BIN_PREDICTOR : q.bin_source;
+            const uint16_t* w16 = (mode == WN_BIN_PREDICTOR && !valu && pr) ? pr->d_w16 : nullptr;
+            e = launch_binning(h->sg, pts, sc.nq, h->pt.seg_periodic, h->eps, mode, pr ? pr->d_wbf : nullptr, w16,
+                               pr ? pr->d_norm : nullptr, sc.depth, sc.bins, sc.wg_hist, binning_grid(h), sc.qs2,
+                               sc.sh2, st);
         }
         nq.qs = sc.qs2;
         nq.shift = sc.sh2;

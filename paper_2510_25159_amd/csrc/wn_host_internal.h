@@ -47,11 +47,13 @@ struct wn_profile {
 
 struct wn_predictor {
     int device = 0;
+    int cu_count = 256;
     float* d_master = nullptr;  // [P] FP32 master parameters
     float* d_m = nullptr;       // [P] AdamW first moment
     float* d_v = nullptr;       // [P] AdamW second moment
     float* d_wbf = nullptr;     // [P] BF16-rounded parameters used by the kernels
     float* d_norm = nullptr;    // [32] feature means, standard deviations
+    uint16_t* d_w16 = nullptr;  // [kMlpFragSlots] W1, W2 as BF16 in matrix-core fragment order
     void* dmem = nullptr;
     int step = 0;
 };

@@ -24,6 +24,36 @@ __host__ __device__ inline float bf16_round(float x) {
     return r;
 }
 
+// The BF16 value of x (round to nearest even) as its 16-bit pattern.
+__host__ __device__ inline uint16_t bf16_bits(float x) {
+    const float r = bf16_round(x);
+    uint32_t u;
+    memcpy(&u, &r, 4);
+    return (uint16_t)(u >> 16);
+}
+
+// Hidden unit that element e of lane group g's layer-2 operand takes in K
+// step ks on the matrix cores (the order of the layer-1 accumulators; see
+// the matrix-core inference below).
+__host__ __device__ constexpr int l2_unit(int ks, int g, int e) { return 16 * (2 * ks + e / 4) + 4 * g + e % 4; }
+
+// Fragment slot of parameter p in the BF16 fragment-order copy, or -1 (the
+// biases and w3 are read as FP32).  Layer-1 tile t, lane i + 16 g, element e
+// holds W1[16 t + i][8 g + e] (g < 2); layer-2 tile t, K step ks holds
+// W2[16 t + i][l2_unit(ks, g, e)].
+__host__ __device__ inline int frag_slot(int p) {
+    if (p < kOffB1) {
+        const int r = p / kMlpIn, k = p % kMlpIn;
+        return ((r / 16) * 64 + r % 16 + 16 * (k / 8)) * 8 + k % 8;
+    }
+    if (p >= kOffW2 && p < kOffB2) {
+        const int r = (p - kOffW2) / kMlpH, u = (p - kOffW2) % kMlpH;
+        const int ks = (u / 16) / 2, g = (u % 16) / 4, e = 4 * ((u / 16) % 2) + u % 4;
+        return 4 * 64 * 8 + (((r / 16) * 2 + ks) * 64 + r % 16 + 16 * g) * 8 + e;
+    }
+    return -1;
+}
+
 // ---------------------------------------------------------------------------
 // features of one (query, segment) pair (raw, unstandardised)
 // ---------------------------------------------------------------------------
@@ -228,7 +258,7 @@ __global__ __launch_bounds__(256) void k_grad(const float* X, const int32_t* idx
 
 __global__ __launch_bounds__(256) void k_adamw(float* master, float* m, float* v, const float* grad, float lr,
                                                float beta1, float beta2, float eps, float wd, float bc1, float bc2,
-                                               float* wbf) {
+                                               float* wbf, uint16_t* w16) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= kMlpParams) return;
     const float g = grad[p];
@@ -241,11 +271,15 @@ __global__ __launch_bounds__(256) void k_adamw(float* master, float* m, float* v
     x -= lr * ((mm / bc1) / (sqrtf(vv / bc2) + eps) + (is_weight ? wd * x : 0.f));
     master[p] = x;
     wbf[p] = bf16_round(x);
+    if (w16 && frag_slot(p) >= 0) w16[frag_slot(p)] = bf16_bits(x);
 }
 
-__global__ __launch_bounds__(256) void k_round_params(const float* master, float* wbf) {
+__global__ __launch_bounds__(256) void k_round_params(const float* master, float* wbf, uint16_t* w16) {
     const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p < kMlpParams) wbf[p] = bf16_round(master[p]);
+    if (p < kMlpParams) {
+        wbf[p] = bf16_round(master[p]);
+        if (w16 && frag_slot(p) >= 0) w16[frag_slot(p)] = bf16_bits(master[p]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -292,6 +326,181 @@ __global__ __launch_bounds__(256) void k_bin_count(Segs sg, Points pts, NearQueu
     }
     __syncthreads();
     if (threadIdx.x < kBins) wg_hist[(size_t)blockIdx.x * kBins + threadIdx.x] = s_hist[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// MLP inference on the matrix cores (v_mfma_f32_16x16x32_bf16: a 16 x 32 BF16
+// tile times a 32 x 16 BF16 tile into a 16 x 16 FP32 tile).  Fragment layouts
+// (lane l, element e):
+//   A[i][k]  lane i + 16 (k / 8), element k % 8   (16 x 32)
+//   B[k][j]  lane j + 16 (k / 8), element k % 8   (32 x 16)
+//   C[i][j]  lane j + 16 (i / 4), element i % 4   (16 x 16)
+// The network runs transposed, 16 rows (pairs) at a time: the weights are the
+// A operands and the rows the N dimension, h1^T = W1 x^T (four 16-unit tiles,
+// K = 16 inputs padded to 32) and h2^T = W2 h1^T (four tiles, two K steps).
+// Lane (j, g) = j + 16 g then holds, for row j, hidden units 16 t + 4 g + e
+// (e < 4) of every layer-1 tile t: eight of them per K step of layer 2.  As a
+// contraction may take its K terms in any order, the layer-2 K step ks takes
+// the lane's own units of tiles 2 ks and 2 ks + 1 (B element 4 (t % 2) + e)
+// and W2's fragment columns are permuted alike, so the layer-1 accumulators
+// (bias, ReLU, rounded to BF16) are layer 2's B operand without leaving the
+// registers.  Layer 3 (one output) is a VALU dot product on the layer-2
+// accumulators and a sum over the four lane groups.  Inputs, weights and
+// layer-1 activations enter the matrix cores as BF16, accumulation in FP32.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct MlpFrags {
+    bf16x8 a1[4];     // W1 tile t: lane (i, g) holds W1[16 t + i][8 g .. 8 g + 7] (zero for g >= 2)
+    bf16x8 a2[4][2];  // W2 tile t, K step ks: lane (i, g) holds W2[16 t + i][l2_unit(ks, g, e)]
+    f32x4 bias1[4], bias2[4], w3[4];  // element e of tile t: unit 16 t + 4 g + e
+    float b3;
+};
+
+// w16: the fragment-order copy (frag_slot), 16-byte aligned.
+__device__ inline void load_frags(const uint16_t* __restrict__ w16, const float* __restrict__ w, int lane,
+                                  MlpFrags& F) {
+    const int g = lane >> 4;
+    const bf16x8* fr = reinterpret_cast<const bf16x8*>(w16);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        F.a1[t] = fr[t * 64 + lane];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) F.a2[t][ks] = fr[(4 + 2 * t + ks) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int u = 16 * t + 4 * g + e;
+            F.bias1[t][e] = w[kOffB1 + u];
+            F.bias2[t][e] = w[kOffB2 + u];
+            F.w3[t][e] = w[kOffW3 + u];
+        }
+    }
+    F.b3 = w[kOffB3];
+}
+
+// y of 16 rows: xb is lane (j, g)'s layer-1 B operand (row j's inputs
+// 8 g .. 8 g + 7, zero for g >= 2).  Every lane of column j returns row j's y.
+__device__ inline float mlp16(const MlpFrags& F, bf16x8 xb) {
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    bf16x8 hb[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[t], xb, zero, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hb[t >> 1][4 * (t & 1) + e] = (__bf16)fmaxf(c[e] + F.bias1[t][e], 0.f);
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[t][0], hb[0], zero, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[t][1], hb[1], c, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) part = fmaf(F.w3[t][e], fmaxf(c[e] + F.bias2[t][e], 0.f), part);
+    }
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    return part + F.b3;
+}
+
+// One wave, 64 rows: lane p's row (its 16 standardised features f) is row
+// p % 16 of block p / 16; the features cross lanes through sx (64 rows of
+// 16 BF16, this wave's own LDS; LDS operations of a wave complete in order).
+__device__ inline float mlp_wave(const MlpFrags& F, const float* f, bf16x8* sx, int lane) {
+    bf16x8 lo, hi;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        lo[k] = (__bf16)f[k];
+        hi[k] = (__bf16)f[8 + k];
+    }
+    sx[2 * lane] = lo;
+    sx[2 * lane + 1] = hi;
+    __builtin_amdgcn_wave_barrier();
+    const int j = lane & 15, g = lane >> 4;
+    float mine = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        bf16x8 xb = sx[2 * (16 * b + j) + (g & 1)];
+        if (g >= 2) xb = bf16x8{};
+        const float y = mlp16(F, xb);
+        if (g == b) mine = y;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return mine;
+}
+
+// Bin counts of the near queue with the MLP on the matrix cores: a wave
+// forms the standardised features of 64 entries (one per lane), runs
+// mlp_wave and bins the predictions like k_bin_count.
+__global__ __launch_bounds__(256) void k_bin_count_mfma(Segs sg, Points pts, NearQueue nq, const uint8_t* seg_per,
+                                                        double eps, const uint16_t* __restrict__ w16,
+                                                        const float* __restrict__ w, const float* __restrict__ norm,
+                                                        uint8_t* bins, uint32_t* wg_hist) {
+    __shared__ uint32_t s_hist[kBins];
+    __shared__ bf16x8 s_x[4][2 * kWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < kBins) s_hist[threadIdx.x] = 0;
+    __syncthreads();
+    MlpFrags F;
+    load_frags(w16, w, lane, F);
+    const uint64_t n = queue_len(nq);
+    const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t b0 = (uint64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+    for (uint64_t base = b0 + (uint64_t)wave * kWave; base < b1; base += 4 * kWave) {
+        const uint64_t i = base + lane;
+        const bool ok = i < b1;
+        float f[kMlpIn];
+        if (ok) {
+            uint32_t s;
+            double qx, qy;
+            queue_query(pts, nq, seg_per, i, s, qx, qy);
+            pair_features(sg, s, qx, qy, eps, f);
+            standardise(f, norm);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
+        }
+        const float y = mlp_wave(F, f, s_x[wave], lane);
+        if (ok) {
+            int bin = (int)rintf(y);
+            bin = bin < 0 ? 0 : (bin >= kBins ? kBins - 1 : bin);
+            bins[i] = (uint8_t)bin;
+            atomicAdd(&s_hist[bin], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins) wg_hist[(size_t)blockIdx.x * kBins + threadIdx.x] = s_hist[threadIdx.x];
+}
+
+// Predictions of standardised features X [n][16] on the matrix cores:
+// persistent waves, 64 rows per wave and step.
+__global__ __launch_bounds__(256) void k_predict_mfma(const uint16_t* __restrict__ w16, const float* __restrict__ w,
+                                                      const float* __restrict__ X, int64_t n, float* out) {
+    __shared__ bf16x8 s_x[4][2 * kWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    MlpFrags F;
+    load_frags(w16, w, lane, F);
+    const int64_t tiles = (n + kWave - 1) / kWave;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t i = tile * kWave + lane;
+        float f[kMlpIn];
+        if (i < n) {
+            const float4* x = reinterpret_cast<const float4*>(X + i * kMlpIn);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float4 v = x[k];
+                f[4 * k] = v.x;
+                f[4 * k + 1] = v.y;
+                f[4 * k + 2] = v.z;
+                f[4 * k + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
+        }
+        const float y = mlp_wave(F, f, s_x[wave], lane);
+        if (i < n) out[i] = y;
+    }
 }
 
 // wg_hist[g][b] -> start offset of (g, b) in bin-major order (in place).
@@ -371,23 +580,37 @@ hipError_t launch_train_step(const float* w, const float* X, const float* Y, con
 }
 
 hipError_t launch_adamw(float* master, float* m, float* v, const float* grad, float lr, float beta1, float beta2,
-                        float eps, float wd, int step, float* wbf, hipStream_t st) {
+                        float eps, float wd, int step, float* wbf, uint16_t* w16, hipStream_t st) {
     const float bc1 = 1.f - powf(beta1, (float)step), bc2 = 1.f - powf(beta2, (float)step);
     hipLaunchKernelGGL(k_adamw, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, master, m, v, grad, lr, beta1,
-                       beta2, eps, wd, bc1, bc2, wbf);
+                       beta2, eps, wd, bc1, bc2, wbf, w16);
     return hipGetLastError();
 }
 
-hipError_t launch_round_params(const float* master, float* wbf, hipStream_t st) {
-    hipLaunchKernelGGL(k_round_params, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, master, wbf);
+hipError_t launch_predict_mfma(const uint16_t* w16, const float* w, const float* X, int64_t n, float* out, int cus,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    // persistent: at most eight workgroups per compute unit
+    const int64_t want = (n + 4 * kWave - 1) / (4 * kWave);
+    const unsigned grid = (unsigned)(want < 8 * (int64_t)cus ? want : 8 * (int64_t)cus);
+    hipLaunchKernelGGL(k_predict_mfma, dim3(grid), dim3(256), 0, st, w16, w, X, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_params(const float* master, float* wbf, uint16_t* w16, hipStream_t st) {
+    hipLaunchKernelGGL(k_round_params, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, master, wbf, w16);
     return hipGetLastError();
 }
 
 hipError_t launch_binning(const Segs& sg, const Points& pts, NearQueue nq, const uint8_t* seg_per, double eps,
-                          int mode, const float* w, const float* norm, const uint8_t* measured, uint8_t* bins,
-                          uint32_t* wg_hist, int G, uint2* qs_out, double2* sh_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, sg, pts, nq, seg_per, eps, mode, w, norm, measured,
-                       bins, wg_hist);
+                          int mode, const float* w, const uint16_t* w16, const float* norm, const uint8_t* measured,
+                          uint8_t* bins, uint32_t* wg_hist, int G, uint2* qs_out, double2* sh_out, hipStream_t st) {
+    if (mode == 0 && w16)  // the MLP on the matrix cores
+        hipLaunchKernelGGL(k_bin_count_mfma, dim3(G), dim3(256), 0, st, sg, pts, nq, seg_per, eps, w16, w, norm, bins,
+                           wg_hist);
+    else
+        hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(256), 0, st, sg, pts, nq, seg_per, eps, mode, w, norm,
+                           measured, bins, wg_hist);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, wg_hist, G);
     hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(256), 0, st, nq, bins, wg_hist, qs_out, sh_out);
     return hipGetLastError();

@@ -18,7 +18,7 @@ namespace {
 
 hipError_t upload_params(wn_predictor* p, const float* params, hipStream_t st) {
     hipError_t e = hipMemcpyAsync(p->d_master, params, kMlpParams * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_round_params(p->d_master, p->d_wbf, st);
+    if (e == hipSuccess) e = launch_round_params(p->d_master, p->d_wbf, p->d_w16, st);
     return e;
 }
 
@@ -37,15 +37,17 @@ wn_status wn_predictor_create(int32_t seed, wn_predictor** out) {
     *out = nullptr;
     wn_predictor* p = new (std::nothrow) wn_predictor();
     if (!p) return WN_E_NOMEM;
-    const size_t bytes = (size_t)kMlpParams * 4 * 4 + 2 * kMlpIn * 4 + 1024;
+    const size_t bytes = (size_t)kMlpFragSlots * 2 + (size_t)kMlpParams * 4 * 4 + 2 * kMlpIn * 4 + 1024;
     hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e == hipSuccess) e = hipMalloc(&p->dmem, bytes);
     if (e != hipSuccess) {
         delete p;
         return hip_status(e);
     }
     char* b = (char*)p->dmem;
-    p->d_master = (float*)b;
+    p->d_w16 = reinterpret_cast<uint16_t*>(b);  // first: 16-byte fragment loads
+    p->d_master = reinterpret_cast<float*>(b + (size_t)kMlpFragSlots * 2);
     p->d_m = p->d_master + kMlpParams;
     p->d_v = p->d_m + kMlpParams;
     p->d_wbf = p->d_v + kMlpParams;
@@ -64,6 +66,8 @@ wn_status wn_predictor_create(int32_t seed, wn_predictor** out) {
     std::vector<float> norm(2 * kMlpIn, 0.f);
     for (int k = 0; k < kMlpIn; ++k) norm[kMlpIn + k] = 1.f;
     e = hipMemset(p->d_m, 0, kMlpParams * 4 * 2);
+    // the fragment slots no weight maps to (layer 1's K padding) stay zero
+    if (e == hipSuccess) e = hipMemset(p->d_w16, 0, (size_t)kMlpFragSlots * 2);
     if (e == hipSuccess) e = hipMemcpy(p->d_norm, norm.data(), norm.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = upload_params(p, prm.data(), nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -107,6 +111,11 @@ wn_status wn_predictor_set_params(wn_predictor* p, const float* params, const fl
 wn_status wn_predictor_predict(const wn_predictor* p, const float* X, int64_t n, float* out, void* stream) {
     if (!p || n < 0 || (n > 0 && (!X || !out))) return WN_E_INVALID;
     return hip_status(launch_predict(p->d_wbf, X, n, out, (hipStream_t)stream));
+}
+
+wn_status wn_predictor_predict_mfma(const wn_predictor* p, const float* X, int64_t n, float* out, void* stream) {
+    if (!p || n < 0 || (n > 0 && (!X || !out)) || (reinterpret_cast<uintptr_t>(X) & 15)) return WN_E_INVALID;
+    return hip_status(launch_predict_mfma(p->d_w16, p->d_wbf, X, n, out, p->cu_count, (hipStream_t)stream));
 }
 
 wn_status wn_predictor_loss_grad(const wn_predictor* p, const float* X, const float* Y, int64_t n, float delta,
@@ -315,7 +324,7 @@ wn_status wn_predictor_train(wn_predictor* pr, const wn_faces* h, const wn_point
             e = launch_train_step(pr->d_wbf, dX, dY, dIdx + s0, B, o.huber_delta, tb, st);
             if (e == hipSuccess)
                 e = launch_adamw(pr->d_master, pr->d_m, pr->d_v, tb.grad, o.lr, 0.9f, 0.999f, 1e-8f, o.weight_decay,
-                                 ++pr->step, pr->d_wbf, st);
+                                 ++pr->step, pr->d_wbf, pr->d_w16, st);
             ++steps;
         }
         float l = 0.f;

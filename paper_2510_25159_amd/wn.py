@@ -29,13 +29,13 @@ EXPORTS = [
     "wn_predictor_set_params", "wn_predictor_loss_grad", "wn_predictor_predict", "wn_pair_features",
     "wn_plan_create", "wn_plan_launch", "wn_plan_autotune", "wn_plan_destroy", "wn_nurbs_to_bezier",
     "wn_classify_grid", "wn_classify_surfaces", "wn_create_faces_nurbs", "wn_near_pairs",
-    "wn_query_noalloc", "wn_query_noalloc_scratch_bytes", "wn_torus_pairs",
+    "wn_query_noalloc", "wn_query_noalloc_scratch_bytes", "wn_torus_pairs", "wn_predictor_predict_mfma",
 ]
 FLAG_HOST_PAIRING = 1
 NOALLOC_MAX_POINTS, NOALLOC_MAX_FACES = 1 << 22, 1 << 18
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
-BIN_PREDICTOR, BIN_HEURISTIC, BIN_MEASURED, BIN_NONE = 0, 1, 2, 3
+BIN_PREDICTOR, BIN_HEURISTIC, BIN_MEASURED, BIN_NONE, BIN_PREDICTOR_VALU = 0, 1, 2, 3, 4
 BOUND_GLOBAL, BOUND_SUBDIVIDED = 0, 1
 KERNEL_ITEMS, KERNEL_FAR, KERNEL_NEAR, KERNEL_FINALIZE, KERNEL_REDO, KERNEL_FAR_PERIODIC = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4: "k_redo", 5: "k_far_periodic",
@@ -163,6 +163,8 @@ def lib():
         L.wn_predictor_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_float, _P, _P, _P]
         L.wn_predictor_predict.restype = ctypes.c_int
         L.wn_predictor_predict.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
+        L.wn_predictor_predict_mfma.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
+        L.wn_predictor_predict_mfma.restype = ctypes.c_int
         L.wn_pair_features.restype = ctypes.c_int
         L.wn_pair_features.argtypes = [_P, ctypes.POINTER(wn_points), _P, _P, ctypes.c_int64, _P, _P]
         L.wn_plan_create.restype = ctypes.c_int
@@ -565,13 +567,35 @@ class Predictor:
             raise WnError(st, "wn_predictor_loss_grad")
         return loss.value, grad
 
+    @staticmethod
+    def _features(X):
+        import torch
+
+        if X.dim() != 2 or X.shape[1] != MLP_IN or X.dtype != torch.float32:
+            raise ValueError(f"features must be float32 [n][{MLP_IN}], got {tuple(X.shape)} {X.dtype}")
+        if not X.is_cuda or not X.is_contiguous():
+            raise ValueError("features must be a contiguous device tensor")
+
     def predict(self, X, stream=None):
         import torch
 
+        self._features(X)
         out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
         st = lib().wn_predictor_predict(self._p, X.data_ptr(), X.shape[0], out.data_ptr(), _stream_ptr(stream))
         if st != WN_OK:
             raise WnError(st, "wn_predictor_predict")
+        return out
+
+    def predict_mfma(self, X, stream=None):
+        """Predictions on the matrix cores (BF16 inputs and activations)."""
+        import torch
+
+        self._features(X)
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        st = lib().wn_predictor_predict_mfma(self._p, X.data_ptr(), X.shape[0], out.data_ptr(),
+                                             _stream_ptr(stream))
+        if st != WN_OK:
+            raise WnError(st, "wn_predictor_predict_mfma")
         return out
 
 

@@ -49,6 +49,40 @@ def test_gradient_and_forward_vs_cpu_reference(torch_cuda):
     np.testing.assert_allclose(pred, mlp_ref.predict(params, X, bf16=True), rtol=0, atol=1e-4 * (1 + np.abs(pred).max()))
 
 
+def test_predict_mfma_vs_bf16_reference(torch_cuda):
+    """The matrix-core forward pass (BF16 inputs, weights and layer-1
+    activations, FP32 accumulation) against the FP64 reference with the same
+    roundings.  The two sides may round a layer-1 activation to neighbouring
+    BF16 values when its FP32 sum lies within rounding of a tie; one such
+    step moves y by at most 2^-7 |h1_k| |W2[:, k]| |w3|, so every row stays
+    within the sum of those, and nearly every row agrees to FP32 rounding.
+    4133 rows: whole waves and a ragged tail."""
+    torch = torch_cuda
+    from paper_2510_25159_amd import wn
+
+    rng = np.random.default_rng(5)
+    pr = wn.Predictor(seed=11)
+    params, _ = pr.get_params()
+    params = params + rng.normal(0, 0.05, params.shape).astype(np.float32)
+    pr.set_params(params)
+    X = rng.normal(0, 1.5, (4133, 16)).astype(np.float32)
+    y = pr.predict_mfma(_dev(torch, X, np.float32)).cpu().numpy().astype(np.float64)
+    y_ref, h1 = mlp_ref.predict(params, X, bf16=True, bf16_act=True, return_hidden=True)
+    q = mlp_ref.unpack(mlp_ref.bf16_round(params))
+    flip = 2.0 ** -7 * (np.abs(h1) @ np.abs(q["W2"]).T) @ np.abs(q["w3"])
+    h2 = np.maximum(h1 @ q["W2"].T + q["b2"], 0.0)
+    fp32 = 1e-5 * (1.0 + np.abs(h2) @ np.abs(q["w3"]) + np.abs(h1) @ np.abs(q["W2"]).T @ np.abs(q["w3"]))
+    d = np.abs(y - y_ref)
+    print(f"mfma vs reference: max |d| {d.max():.3e}, rows beyond FP32 rounding {int(np.sum(d > fp32))}", flush=True)
+    assert np.all(d <= flip + fp32)
+    assert np.sum(d > fp32) <= 0.01 * len(y)
+    # the VALU version keeps FP32 activations: the two differ by activation rounding only
+    yv = pr.predict(_dev(torch, X, np.float32)).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(yv - mlp_ref.predict(params, X, bf16=True)) <= fp32 + 1e-4 * (1 + np.abs(yv)))
+    # empty input
+    assert pr.predict_mfma(torch.zeros((0, 16), dtype=torch.float32, device="cuda:0")).numel() == 0
+
+
 def test_pair_features_vs_numpy(torch_cuda):
     torch = torch_cuda
     from paper_2510_25159_amd import wn
@@ -103,7 +137,7 @@ def test_training_beats_mean_predictor(trained):
     assert rep["holdout_mae"] < 0.8 * rep["baseline_mae"], rep
 
 
-@pytest.mark.parametrize("source", [0, 1, 2, 3])
+@pytest.mark.parametrize("source", [0, 1, 2, 3, 4])
 def test_binned_schedule_changes_nothing(torch_cuda, trained, oracle_lib, source):
     pr, _ = trained
     faces, q = W.config4("eval", near_frac=0.3)
@@ -122,7 +156,7 @@ def test_binned_periodic_and_rational(torch_cuda, trained, oracle_lib):
     pr, _ = trained
     for faces, q in (W.config2(face_ids=range(4)), W.config3(face_ids=range(8))):
         w_o, n_o = oracle_lib.query_faces(faces, q)
-        for source in (0, 1, 2):
+        for source in (0, 1, 2, 4):
             w, lab = run_wn(faces, q, schedule=2, predictor=pr, bin_source=source)
             compare(w, lab, w_o, n_o)
 
