@@ -320,6 +320,37 @@ def section_config4(args):
     return out
 
 
+def section_degree(args):
+    """Runtime against boundary degree (Sec. 5): 512 cubic star faces (64
+    segments each) elevated to degree 4 and 5 without changing the curves,
+    4096 points per face, all on the curves (the recursion's worst case) or
+    all uniform."""
+    import torch
+
+    from paper_2510_25159_amd import wn
+    from paper_2510_25159_amd import workloads as W
+
+    out = {}
+    for sampling, frac in (("on_curve", 1.0), ("uniform", 0.0)):
+        res = {}
+        for d in (3, 4, 5):
+            faces, q = W.degree_set(d, num_faces=512, points_per_face=4096, on_curve_frac=frac)
+            fs = wn.FaceSet(faces)
+            tens = _dev_queries(torch, q)
+            ms, k = _time_query(torch, fs, tens, q.face_point_offsets, 10, schedule=1)
+            st = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device="cuda:0")
+            fs.query(*tens, q.face_point_offsets, schedule=1, stats=st)
+            torch.cuda.synchronize()
+            stats = dict(zip(wn.STAT_NAMES, st.cpu().numpy().tolist()))
+            res[f"degree{d}"] = {"ms_per_step": ms, "queries_per_s": q.num_points / (ms / 1e3),
+                                 "kernel_ms": k, "splits_per_point": stats["splits"] / q.num_points,
+                                 "near_pairs_per_point": stats["near_pairs"] / q.num_points,
+                                 "max_depth": stats["max_depth"]}
+        out[sampling] = res
+    out["points"] = 512 * 4096
+    return out
+
+
 def section_config5(args):
     """Serving loop: Poisson arrivals, resident faces, graph replays."""
     from paper_2510_25159_amd import serving
@@ -329,7 +360,7 @@ def section_config5(args):
 
 SECTIONS = (("config1", section_config1), ("long_path", section_long_path), ("config3", section_config3),
             ("config4", section_config4), ("config5", section_config5), ("spheres", section_spheres),
-            ("tessellation", section_tessellation), ("multipatch", section_multipatch))
+            ("tessellation", section_tessellation), ("multipatch", section_multipatch), ("degree", section_degree))
 
 
 def main():
@@ -458,8 +489,9 @@ def main():
         kern_serial = ps_.collect()
         log(f"batched, passes in series: {ms_serial:.3f} ms/step; kernels {kern_serial}")
 
-    ms_mixed = ms_tree = ms_plain = ms_cp = float("nan")
-    kern_mixed = kern_tree = kern_cp = work_cp = {}
+    ms_mixed = ms_tree = ms_plain = ms_cp = ms_combo = float("nan")
+    kern_mixed = kern_tree = kern_cp = work_cp = kern_combo = rep_tr = {}
+    combo_same = None
     cp_diff = cp_onb = None
     mixed_same = plain_agree = None
     tree_diff = tree_onb = None
@@ -530,6 +562,35 @@ def main():
         work_cp = dict(zip(wn.STAT_NAMES, (int(x) for x in st_cp.cpu().numpy())))
         log(f"subdivided control-point bound: {ms_cp:.3f} ms/step; kernels {kern_cp}; label differences {cp_diff}, "
             f"on-boundary differences {cp_onb}; work {work_cp}")
+
+        # all three of the method's accelerations together: batched schedule,
+        # FP32 far-field admission and near pairs binned by the learned depth
+        # predictor (MLP on the matrix cores), trained on 100 faces of the same
+        # generator outside the timed set; compared with the plain FP64 kernel below
+        t_tr = time.perf_counter()
+        f_tr, q_tr = W.config2(face_ids=range(args.faces, args.faces + 100))
+        pr = wn.Predictor(seed=7)
+        rep_tr = pr.train(wn.FaceSet(f_tr), *_dev_queries(torch, q_tr), epochs=20, lr=3e-3, seed=1,
+                          max_samples=400000)
+        rep_tr["train_s"] = time.perf_counter() - t_tr
+
+        def step_combo(profile=None):
+            fs.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=wn.SCHED_BINNED, precision=1,
+                     predictor=pr, bin_source=wn.BIN_PREDICTOR, queries_per_wg=args.qpw, profile=profile,
+                     stream=stream)
+
+        step_combo()
+        torch.cuda.synchronize()
+        pcb = wn.Profile(capacity=8 * args.mixed_steps + 64)
+        tcb = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            step_combo(pcb)
+        torch.cuda.synchronize()
+        ms_combo = (time.perf_counter() - tcb) * 1e3 / max(args.mixed_steps, 1)
+        kern_combo = {k: t_ / max(n, 1) for k, (n, t_) in pcb.collect().items()}
+        combo_same = bool(np.array_equal(out_l.cpu().numpy(), lab_b))
+        log(f"batched + FP32 admission + learned binning: {ms_combo:.3f} ms/step; kernels {kern_combo}; "
+            f"labels equal to FP64 batched: {combo_same}; predictor {rep_tr}")
 
         # plain schedule beside it (one launch per face, in-line recursion)
         step(0)
@@ -680,7 +741,15 @@ def main():
                              "splits": work_cp.get("splits"), "leaves": work_cp.get("leaves"),
                              "max_depth": work_cp.get("max_depth"),
                              "note": "near pass with the smaller of B 2^-k and the node's control-point bound "
-                                     "(passes in series); compare roofline_serial's k_near and work.splits"},
+                                     "(passes in series); compare rooflines_serial's k_near and work.splits"},
+        "batched_mixed_binned": {"ms_per_step": ms_combo, "evals_per_s": pairs / (ms_combo / 1e3),
+                                 "kernel_ms": kern_combo, "labels_equal_fp64": combo_same,
+                                 "speedup_vs_plain_fp64": ms_plain / ms_combo,
+                                 "predictor": {k: v for k, v in rep_tr.items()
+                                               if k in ("samples", "holdout_mae", "baseline_mae", "train_s")},
+                                 "note": "batched schedule + FP32 far-field admission + near pairs binned by the "
+                                         "learned depth predictor (MLP on the matrix cores, trained on faces "
+                                         f"{args.faces}..{args.faces + 99} of the generator) vs the plain FP64 kernel"},
         "mismatches": mism,
         "kernels": kernels,
         "work": st,

@@ -43,6 +43,7 @@ SEED_C4_TRAIN = 40
 SEED_C4_EVAL = 41
 SEED_C5 = 5
 SEED_BREP = 6
+SEED_DEG = 8
 
 
 @dataclass
@@ -314,6 +315,46 @@ def config1_queries(seed: int = SEED_C1, n: int = 65536, half: float = 1.5) -> Q
 
 def config1(seed: int = SEED_C1):
     return config1_faces(seed), config1_queries(seed)
+
+
+# --------------------------------------------------------------------------
+# Degree set (Sec. 5, runtime against boundary degree): cubic star loops
+# elevated to higher degree without changing the curve
+# --------------------------------------------------------------------------
+def elevate_bezier(cp: np.ndarray, times: int) -> np.ndarray:
+    """Control points of the same polynomial Bezier curve at degree n + times
+    (repeated degree elevation: P'_i = i/(n+1) P_{i-1} + (1 - i/(n+1)) P_i).
+    The end points are kept bit-for-bit, so joints stay shared."""
+    cp = np.asarray(cp, dtype=np.float64)
+    for _ in range(times):
+        n = len(cp) - 1
+        a = (np.arange(1, n + 1) / (n + 1))[:, None]
+        cp = np.vstack([cp[:1], a * cp[:-1] + (1.0 - a) * cp[1:], cp[-1:]])
+    return cp
+
+
+def degree_set(degree: int, seed: int = SEED_DEG, num_faces: int = 64, nseg: int = 64,
+               points_per_face: int = 8192, on_curve_frac: float = 0.5):
+    """``num_faces`` cubic star faces (config 1's generator, one per seed) with
+    every segment elevated to ``degree`` (3..5), and the same queries for
+    every degree: per face, ``on_curve_frac`` of the points on the cubic
+    curve (random segment and parameter, evaluated in FP64: within rounding
+    of the boundary, the worst case of the recursion) and the rest uniform in
+    the face's box [-1.5, 1.5]^2."""
+    if not 3 <= degree <= 5:
+        raise ValueError("degree_set: degree must be in 3..5 (cubic curves elevated)")
+    face_loops, pts = [], []
+    for f in range(num_faces):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, f])))
+        lp = hermite_star_loop(StarCurve(rng), nseg)
+        k = int(round(on_curve_frac * points_per_face))
+        si = rng.integers(0, nseg, k)
+        t = rng.uniform(0.0, 1.0, k)
+        on = _eval_many([lp], np.zeros(k, dtype=np.int64), si, t)
+        uni = rng.uniform(-1.5, 1.5, size=(points_per_face - k, 2))
+        pts.append(np.vstack([on, uni]))
+        face_loops.append([[(elevate_bezier(c, degree - 3), None) for c in lp.cps]])
+    return faces_from_loops(face_loops), queries_for_faces(pts)
 
 
 # --------------------------------------------------------------------------
