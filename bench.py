@@ -83,6 +83,26 @@ def measured_traffic() -> dict:
     return out
 
 
+def measured_copy_rate(torch, gib: int = 2, reps: int = 10) -> float:
+    """HBM rate of a plain device copy (bytes read + written per second):
+    the measured counterpart of the published 8 TB/s."""
+    n = gib * (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    rate = 2.0 * 8 * n * reps / (a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return rate
+
+
 def host_cpu() -> dict:
     """CPU model and logical CPU count of the host (from /proc/cpuinfo)."""
     model, n = None, 0
@@ -135,6 +155,46 @@ def section_config1(args):
                      "kernel_ms": k}
     kf = out["plain"]["kernel_ms"].get("k_far", float("nan"))
     out["plain"]["far_roofline_frac"] = FLOPS_PER_PAIR * pairs / (kf / 1e3) / PEAK_FP64_VALU
+    # wall time per query without the per-kernel events, and the batched query
+    # as an autotuned plan (one graph replay per query: no host work per call)
+    reps = 200
+    for name, sched in (("plain", 0), ("batched", 1)):
+        ow, ol = fs.query(*tens, q.face_point_offsets, schedule=sched)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fs.query(*tens, q.face_point_offsets, ow, ol, schedule=sched)
+        torch.cuda.synchronize()
+        out[name]["ms_per_step_unprofiled"] = (time.perf_counter() - t) * 1e3 / reps
+    lab_plain = fs.query(*tens, q.face_point_offsets, schedule=0)[1].cpu().numpy()
+    ow = torch.empty(q.num_points, dtype=torch.float64, device="cuda:0")
+    ol = torch.empty(q.num_points, dtype=torch.uint8, device="cuda:0")
+    plan = wn.Plan(fs, *tens, ow, ol)
+    rep = plan.autotune(reps=5)
+    plan.launch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        plan.launch()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    out["batched_plan"] = {"ms_per_step": ms, "evals_per_s": pairs / (ms / 1e3), "autotune": rep,
+                           "labels_equal_plain": bool(np.array_equal(ol.cpu().numpy(), lab_plain))}
+    # where the plain kernel's time goes: the same face with the points whose
+    # pairs recurse removed (found from the kernel's own depth log) leaves the
+    # far scan alone; the difference is the tail of the in-line recursions
+    spf = fs.info().max_segments_per_face
+    dl = torch.zeros(q.num_points * spf, dtype=torch.uint8, device="cuda:0")
+    fs.query(*tens, q.face_point_offsets, schedule=0, depth_log=dl)
+    torch.cuda.synchronize()
+    deep = dl.view(q.num_points, spf).amax(dim=1).cpu().numpy()
+    keep = np.flatnonzero(deep == 0)
+    qf = W.queries_for_faces([np.column_stack([q.u[keep], q.v[keep]])])
+    msf, kff = _time_query(torch, fs, _dev_queries(torch, qf), qf.face_point_offsets, 50, schedule=0)
+    out["plain"]["recursion"] = {"points_with_near_pairs": int(q.num_points - keep.size),
+                                 "max_depth": int(deep.max()),
+                                 "far_only_points": int(keep.size), "far_only_k_far_ms": kff.get("k_far"),
+                                 "far_only_ms_per_step": msf}
     return out
 
 
@@ -657,6 +717,8 @@ def main():
         roofline = dict(rooflines_serial[dom], kernel=dom)
         roofline["note"] = ("kernel alone on the GPU (far and near passes in series); its launches in the "
                             "overlapped timed steps are under rooflines_overlapped")
+        # measured counterpart of the HBM peak (context; the fractions use the published peak)
+        roofline["measured_copy_GBps"] = measured_copy_rate(torch) / 1e9
 
     # CPU oracle on a bounded sample of the same workload; also the parity check
     cpu = None

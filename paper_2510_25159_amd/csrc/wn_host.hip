@@ -338,6 +338,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->bpc_far[m][2] = far_blocks_per_cu(false, m == 1, 256);
     }
     h->bpc_far_tree = far_tree_blocks_per_cu();
+    h->bpc_far_wtree = far_wtree_blocks_per_cu();
     for (int qpl = 2; qpl <= 4; ++qpl) h->bpc_farq[qpl] = farq_blocks_per_cu(qpl);
     h->bpc_far_per = far_periodic_blocks_per_cu(kPerQueue);
     h->bpc_redo_per = far_periodic_blocks_per_cu(kPerRedo);
@@ -362,6 +363,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         (longest >= kTreeAutoSegs ? ord_tree : ord_flat).push_back(f);
     }
     h->h_ord_flat = ord_flat;
+    h->h_ord_tree = ord_tree;
     std::stable_sort(ord_per.begin(), ord_per.end(), by_size);
     h->per_pos.assign((size_t)F, 0);
     for (size_t r = 0; r < ord_per.size(); ++r) h->per_pos[ord_per[r]] = (int32_t)r;
@@ -799,7 +801,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
         sc.out = Out{out_w, out_lab, nullptr, 0, rule};
     } else {
         e = scratch_alloc(h, N, cap, binned, binned && q.bin_source == WN_BIN_MEASURED, out_w, out_lab, rule, sc,
-                          st, true);
+                          st, true, q.path_hierarchy != 0);
         if (e != hipSuccess) return hip_status(e);
     }
 
@@ -866,7 +868,8 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     sc.near_join = nullptr;
     const int64_t* ovl =
         (!binned && !preset && !q.stats && !cp && prec == WN_PREC_FP64) ? p->face_point_offsets_host : nullptr;
-    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st, ovl);
+    e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st, ovl,
+                   p->face_point_offsets_host);
     NearQueue nq = sc.nq;
     if (e == hipSuccess && binned) {
         const wn_predictor* pr = q.predictor;
@@ -944,8 +947,9 @@ wn_status wn_query_ex(const wn_faces* h, const wn_points* p, double* out_w, uint
 namespace wn {
 
 hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned, bool depth, double* out_w,
-                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st, bool stream_ordered) {
+                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st, bool stream_ordered, bool order) {
     const bool periodic = h->num_periodic > 0;
+    const bool ordered = periodic || order;
     const int32_t F = h->num_faces;
     sc.max_items = N / 64 + F + 1;
     size_t total = 0;
@@ -960,7 +964,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
     const size_t o_w = out_w ? 0 : take((size_t)N * 8), o_l = out_lab ? 0 : take((size_t)N);
     const size_t o_q2 = take(binned ? (size_t)cap * 8 : 0), o_s2 = take(binned && periodic ? (size_t)cap * 16 : 0);
     const size_t o_bn = take(binned ? (size_t)cap : 0), o_wh = take(binned ? (size_t)G * 32 * 4 : 0);
-    const size_t o_dp = take(depth ? (size_t)cap : 0), o_pm = take(periodic ? (size_t)N * 4 : 0);
+    const size_t o_dp = take(depth ? (size_t)cap : 0), o_pm = take(ordered ? (size_t)N * 4 : 0);
     const size_t o_wt = take(depth ? (size_t)N * 8 : 0), o_lt = take(depth ? (size_t)N : 0);
     const hipError_t e = stream_ordered ? hipMallocAsync(&sc.base, total, st) : hipMalloc(&sc.base, total);
     if (e != hipSuccess) return e;
@@ -971,7 +975,7 @@ hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned,
     sc.nq = NearQueue{(uint2*)(b + o_nq), periodic ? (double2*)(b + o_sh) : nullptr,
                       (unsigned long long*)(sc.counters + 2), (uint64_t)cap};
     sc.out = Out{out_w ? out_w : (double*)(b + o_w), out_lab ? out_lab : (uint8_t*)(b + o_l), nullptr, 0, rule};
-    sc.perm = periodic ? (uint32_t*)(b + o_pm) : nullptr;
+    sc.perm = ordered ? (uint32_t*)(b + o_pm) : nullptr;
     if (binned) {
         sc.qs2 = (uint2*)(b + o_q2);
         sc.sh2 = periodic ? (double2*)(b + o_s2) : nullptr;
@@ -1076,7 +1080,7 @@ static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, cons
 }
 
 hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
-                      wn_profile* prof, hipStream_t st, const int64_t* host_offs) {
+                      wn_profile* prof, hipStream_t st, const int64_t* host_offs, const int64_t* counts_host) {
     hipError_t e = hipSuccess;
     bool zero_near = true;
     const bool persistent = policy != 2;
@@ -1112,17 +1116,49 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
         }
     }
     if (e == hipSuccess && tree != 0 && tree_ft.num_faces > 0) {
-        {
-            ProfScope ps(prof, WN_KERNEL_ITEMS, st);
-            e = launch_build_items(tree_ft, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters, zero_near,
-                                   st);
-            zero_near = false;
+        // With a spatial order of the points (the query's scratch holds one),
+        // faces of at most kOrderMaxPoints points take the walk shared by the
+        // wave's spatially neighbouring queries, and the per-lane walk takes
+        // the faces whose points keep the caller's order; it only runs when
+        // such a face may exist (always without host offsets).
+        const bool wave_walk = sc.perm != nullptr;
+        bool big = true;
+        if (wave_walk && counts_host) {
+            big = false;
+            for (const int32_t f : tree == 2 ? h->h_ord_tree : h->h_ord_plan)
+                if (counts_host[f + 1] - counts_host[f] > kOrderMaxPoints) {
+                    big = true;
+                    break;
+                }
         }
-        if (e == hipSuccess) {
-            const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_far_tree : sc.max_items;
-            ProfScope ps(prof, WN_KERNEL_FAR, st);
-            e = launch_far_tree(h->tree, tree_ft, pts, sc.item_offs, sc.item_map, persistent ? sc.counters : nullptr,
-                                grid, sc.nq, sc.out, h->eps2, st);
+        if (wave_walk) {
+            {
+                ProfScope ps(prof, WN_KERNEL_ITEMS, st);
+                e = launch_build_items(tree_ft, pts, kWave * kWtreeQPL * kWavesPerWG, sc.item_offs, sc.item_map,
+                                       sc.max_items, sc.counters, zero_near, st);
+                zero_near = false;
+                if (e == hipSuccess) e = launch_spatial_order(tree_ft, pts, sc.perm, st);
+            }
+            if (e == hipSuccess) {
+                const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_far_wtree : sc.max_items;
+                ProfScope ps(prof, WN_KERNEL_FAR, st);
+                e = launch_far_wtree(h->tree, tree_ft, pts, sc.perm, sc.item_offs, sc.item_map,
+                                     persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, st);
+            }
+        }
+        if (e == hipSuccess && (!wave_walk || big)) {
+            {
+                ProfScope ps(prof, WN_KERNEL_ITEMS, st);
+                e = launch_build_items(tree_ft, pts, 256, sc.item_offs, sc.item_map, sc.max_items, sc.counters,
+                                       zero_near, st);
+                zero_near = false;
+            }
+            if (e == hipSuccess) {
+                const int64_t grid = persistent ? (int64_t)h->cu_count * h->bpc_far_tree : sc.max_items;
+                ProfScope ps(prof, WN_KERNEL_FAR, st);
+                e = launch_far_tree(h->tree, tree_ft, pts, sc.item_offs, sc.item_map,
+                                    persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, st, wave_walk);
+            }
         }
     }
     if (e == hipSuccess && h->num_periodic > 0) {

@@ -24,13 +24,15 @@ struct wn_faces {
     int precision = WN_PREC_FP64, rule = WN_RULE_NONZERO, schedule = WN_SCHED_BATCHED;
     int cu_count = 0;
     int bpc_far[2][3] = {{1, 1, 1}, {1, 1, 1}};  // resident workgroups per CU, k_far batched: [FP64, MIXED][64/128/256 points per workgroup]
-    int bpc_farq[5] = {1, 1, 1, 1, 1}, bpc_far_tree = 1, bpc_far_per = 1, bpc_redo_per = 1, bpc_near = 1;
+    int bpc_farq[5] = {1, 1, 1, 1, 1}, bpc_far_tree = 1, bpc_far_wtree = 1, bpc_far_per = 1, bpc_redo_per = 1,
+        bpc_near = 1;
     int bpc_near_cp = 1;
     std::vector<int32_t> h_seg_begin;
     std::vector<int32_t> h_dom;
     std::vector<int32_t> per_pos;  // position of each periodic face in ft_per.order
     std::vector<int32_t> h_ord_plan;  // ft_plan.order on the host
     std::vector<int32_t> h_ord_flat;  // ft_flat.order on the host
+    std::vector<int32_t> h_ord_tree;  // ft_tree.order on the host
     std::vector<wn::PUnit> h_units;   // periodic units (torus pairs included) on the host
     std::vector<wn::PFace> h_pface;   // [F] periodic face records on the host (planar: zero)
     // side stream of the overlapped far/near passes (default priority); null
@@ -84,15 +86,22 @@ struct Scratch {
 
 // Allocate (stream-ordered) scratch for N points; outputs the caller did
 // not provide are allocated too.  binned adds the binning buffers.
+// order: also hold a spatial order of the points (always held for periodic
+// face sets; the path hierarchy's wave walk needs it for planar faces).
 hipError_t scratch_alloc(const wn_faces* h, int64_t N, int64_t cap, bool binned, bool depth, double* out_w,
-                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st, bool stream_ordered);
+                         uint8_t* out_lab, int rule, Scratch& sc, hipStream_t st, bool stream_ordered,
+                         bool order = false);
 void scratch_free(Scratch& sc, hipStream_t st);
 
 // Item build + persistent far passes (planar, periodic) filling sc.nq.  With
 // host_offs (the host copy of the points' face offsets) the planar flat pass
 // may overlap near passes on h->side and leave sc.near_lo for the final one.
+// host_offs: the host offsets when the far/near overlap may run; counts_host:
+// the host offsets whenever the caller gave them (the hierarchy reads the
+// per-face point counts from them).
 hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
-                      wn_profile* prof, hipStream_t st, const int64_t* host_offs = nullptr);
+                      wn_profile* prof, hipStream_t st, const int64_t* host_offs = nullptr,
+                      const int64_t* counts_host = nullptr);
 // Near pass over nq; entry_depth optional.
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
                      uint8_t* entry_depth, wn_profile* prof, hipStream_t st, unsigned long long* cursor,

@@ -79,6 +79,10 @@ struct PathTree {
     const int32_t* chunk_begin;  // [F+1] chunks of face f are [chunk_begin[f], chunk_begin[f+1])
 };
 constexpr int kTreeChunk = 512;  // nodes staged in LDS at a time (24 KB)
+// Faces with more points keep the caller's order in the spatial ordering (one
+// workgroup would take too long over them; large faces already fill several
+// waves per copy).
+constexpr int64_t kOrderMaxPoints = 65536;
 constexpr int kTreeAutoSegs = 512;  // automatic hierarchy: faces with a chain at least this long
 
 struct FaceTab {
@@ -199,8 +203,17 @@ int far_blocks_per_cu(bool inline_near, bool mixed, int qpw);
 // Queued FP64 far pass over the path hierarchy (items of 256 queries).
 hipError_t launch_far_tree(const PathTree& tr, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                            const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
-                           double eps2, hipStream_t st);
+                           double eps2, hipStream_t st, bool skip_ordered = false);
 int far_tree_blocks_per_cu();
+// The same hierarchy walked once per wave over spatially ordered queries
+// (perm, from launch_spatial_order), four queries per lane, items of 1024
+// queries; faces with more than kOrderMaxPoints points are skipped (they keep
+// the caller's order: launch_far_tree with skip_ordered takes them).
+hipError_t launch_far_wtree(const PathTree& tr, const FaceTab& ft, const Points& pts, const uint32_t* perm,
+                            const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
+                            NearQueue nq, Out out, double eps2, hipStream_t st);
+int far_wtree_blocks_per_cu();
+constexpr int kWtreeQPL = 4;
 // Queued FP64 far pass with qpl (2, 3 or 4) queries per lane (items of 256 qpl
 // queries), over the items of the faces of rank [rank_lo, rank_hi) of ft
 // (rank_hi < 0: all faces).

@@ -600,7 +600,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Points pts, const int32_t* item_offs,
                                                   const int2* item_map, uint32_t* item_counter, NearQueue nq,
-                                                  Out out, double eps2) {
+                                                  Out out, double eps2, int skip_ordered) {
     __shared__ TNode s_node[kTreeChunk];  // the current chunk of whole chains
     __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
     __shared__ int s_item;
@@ -625,6 +625,7 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
         int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
         qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
         qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+        if (skip_ordered && qe - qb <= kOrderMaxPoints) continue;  // k_far_wtree's face
         const int64_t qi = qb + (int64_t)tile * (kWave * kWavesPerWG) + wave * kWave + lane;
         const bool active = qi < qe;
         double qx = 0.0, qy = 0.0;
@@ -685,6 +686,174 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
         if (active) {
             out.w[qi] = turn_angle(T) + kTwoPi * (double)xc;
             out.lab[qi] = !valid ? 3 : (onb ? 2 : (lost ? kRedo : 0));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Far pass over the path hierarchy, one walk per wave.  The wave's 64 QPL
+// queries are neighbours (the face's points in spatial order, through perm),
+// and the wave visits the face's subpath trees in preorder in uniform control
+// flow, one node per trip, read once from LDS for all lanes.  A query takes
+// part in a node until it prunes an ancestor (skip_to: the node its walk
+// resumes at).  At a node it takes the node's chord when outside the node's
+// ellipse or at a leaf (the subpath and its chord bound no area around the
+// query, so they cross its ray equally often), and an inner node it is
+// outside of is pruned (skip_to = the node's skip index).  The wave goes down
+// to the first child when some query is inside an inner node, else past the
+// subtree.  Per query this is exactly k_far_tree's walk: the same chords, the
+// same end points tested against eps, the same near pairs (a leaf inside its
+// ellipse); only the reads and the control flow are shared.  Faces whose
+// points keep the caller's order (more than kOrderMaxPoints) are skipped.
+// ---------------------------------------------------------------------------
+// Coordinates given to the inactive and invalid queries of k_far_wtree (far
+// beyond kCoordLimit, so that their squared distances overflow).
+constexpr double kAway = 1e300;
+
+// flush_near for queries of arbitrary indices: bit q of lost is set when a
+// pair of query qi[q] did not fit in the queue.
+template <int QPL>
+__device__ __forceinline__ void flush_near_list(const uint2* buf, int nfill, const NearQueue& nq, int lane,
+                                                const int32_t (&qi)[QPL], int& lost) {
+    if (nfill == 0) return;
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(nq.count, (unsigned long long)nfill);
+    base = __shfl(base, 0);
+    for (int e = lane; e < nfill; e += kWave)
+        if (base + (unsigned long long)e < nq.cap) nq.qs[base + e] = buf[e];
+    if (base + (unsigned long long)nfill > nq.cap) {
+        for (int e = 0; e < nfill; ++e) {
+            if (base + (unsigned long long)e < nq.cap) continue;
+            const uint32_t x = buf[e].x;
+#pragma unroll
+            for (int q = 0; q < QPL; ++q) lost |= x == (uint32_t)qi[q] ? 1 << q : 0;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int QPL>
+__global__ __launch_bounds__(kWG) void k_far_wtree(PathTree tr, FaceTab ft, Points pts, const uint32_t* perm,
+                                                   const int32_t* item_offs, const int2* item_map,
+                                                   uint32_t* item_counter, NearQueue nq, Out out, double eps2) {
+    constexpr int kQPWG = kWave * QPL * kWavesPerWG;  // queries per work item
+    __shared__ TNode s_node[kTreeChunk];                // the current chunk of whole chains
+    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    const int total = item_offs[ft.num_faces];
+    for (int iter = 0;; ++iter) {
+        int item;
+        if (item_counter) {
+            __syncthreads();
+            if (tid == 0) s_item = (int)atomicAdd(item_counter, 1u);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(s_item);
+        } else {
+            if (iter > 0) break;
+            item = blockIdx.x;
+        }
+        if (item >= total) break;
+        const int2 mp = item_map[item];
+        const int f = mp.x, tile = mp.y;
+        int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
+        qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
+        qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
+        if (qe - qb > kOrderMaxPoints) continue;  // k_far_tree's face (the same for the whole workgroup)
+        int32_t qi[QPL];    // query index (-1: no query in this slot)
+        double qx[QPL], qy[QPL];
+        Turn T[QPL];
+        int xc[QPL], skip_to[QPL];
+        uint64_t em[QPL];   // lanes with an end point within eps
+        int lost = 0;       // bit q: a near pair of query q did not fit in the queue
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            const int64_t slot = qb + (int64_t)tile * kQPWG + (int64_t)(wave * QPL + q) * kWave + lane;
+            qi[q] = slot < qe ? (int32_t)perm[slot] : -1;
+            qx[q] = qy[q] = 0.0;
+            if (qi[q] >= 0) {
+                qx[q] = pts.u[(int64_t)qi[q] * pts.stride];
+                qy[q] = pts.v[(int64_t)qi[q] * pts.stride];
+            }
+            // an inactive or invalid query sits at (kAway, kAway): its squared
+            // distances overflow to +inf, so it is outside every ellipse, within
+            // eps of no end point and crosses no chord
+            if (!(qi[q] >= 0 && fabs(qx[q]) < kCoordLimit && fabs(qy[q]) < kCoordLimit)) qx[q] = qy[q] = kAway;
+            T[q] = Turn{1.0, 0.0, 0};
+            xc[q] = 0;
+            em[q] = 0;
+        }
+        int nfill = 0;  // entries in this wave's near-pair buffer (wave-uniform)
+        // every chain's closing angle, once per query, in uniform control flow
+        for (int r = kload(tr.begin, f), re_ = kload(tr.begin, f + 1); r < re_;) {
+            const TNode rt = kload(tr.node, r);
+#pragma unroll
+            for (int q = 0; q < QPL; ++q)
+                if (qx[q] != kAway) close_chain(T[q], xc[q], rt.sx - qx[q], rt.sy - qy[q], rt.ex - qx[q], rt.ey - qy[q]);
+            r = rt.skip & ~kTreeRoot;
+        }
+        for (int k = tr.chunk_begin[f]; k < tr.chunk_begin[f + 1]; ++k) {
+            const int2 ch = tr.chunk[k];
+            const int lo = ch.x, ne = ch.y;
+            __syncthreads();
+            for (int i = tid; i < min(ne - lo, kTreeChunk); i += kWG) s_node[i] = tr.node[lo + i];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QPL; ++q) skip_to[q] = lo;
+            int i = lo;  // wave-uniform
+            while (i < ne) {
+                const TNode nd = i - lo < kTreeChunk ? s_node[i - lo] : kload(tr.node, i);
+                const bool leaf = nd.seg >= 0;
+                const int nskip = nd.skip & ~kTreeRoot;
+                uint64_t nm[QPL];
+                uint64_t stay = 0;
+#pragma unroll
+                for (int q = 0; q < QPL; ++q) {
+                    const uint64_t am = __builtin_amdgcn_ballot_w64(skip_to[q] <= i);
+                    const double ax = nd.sx - qx[q], ay = nd.sy - qy[q];
+                    const double bx = nd.ex - qx[q], by = nd.ey - qy[q];
+                    const double ra = fma(ax, ax, ay * ay), rb = fma(bx, bx, by * by);
+                    em[q] |= (__builtin_amdgcn_fcmp(ra, eps2, kCmpOLT) | __builtin_amdgcn_fcmp(rb, eps2, kCmpOLT)) & am;
+                    const uint64_t in = near_mask(ra, rb, nd.hb2);
+                    const uint64_t take = leaf ? am : (am & ~in);
+                    ray_cross_mask(xc[q], low_mask(ay), low_mask(by), ax, ay, bx, by, take);
+                    nm[q] = leaf ? (am & in & ~em[q]) : 0ull;
+                    if (!leaf) {
+                        if (__builtin_amdgcn_inverse_ballot_w64(am & ~in)) skip_to[q] = nskip;
+                        stay |= am & in;
+                    }
+                }
+                if (leaf) {
+                    int cnt = 0;
+#pragma unroll
+                    for (int q = 0; q < QPL; ++q) cnt += __popcll(nm[q]);
+                    if (cnt > 0) {
+                        if (nfill + cnt > kNearBuf) {
+                            flush_near_list<QPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
+                            nfill = 0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < QPL; ++q) {
+                            if (__builtin_amdgcn_inverse_ballot_w64(nm[q]))
+                                s_nbuf[wave][nfill + lanes_below(nm[q])] = make_uint2((uint32_t)qi[q], (uint32_t)nd.seg);
+                            nfill += __popcll(nm[q]);
+                        }
+                    }
+                }
+                i = (!leaf && stay != 0ull) ? i + 1 : nskip;  // a leaf's skip index is i + 1
+            }
+        }
+        flush_near_list<QPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            if (qi[q] < 0) continue;
+            const bool valid = qx[q] != kAway;
+            const bool onb = valid & __builtin_amdgcn_inverse_ballot_w64(em[q]);
+            out.w[qi[q]] = turn_angle(T[q]) + kTwoPi * (double)xc[q];
+            out.lab[qi[q]] = !valid ? 3 : (onb ? 2 : (((lost >> q) & 1) ? kRedo : 0));
         }
     }
 }
@@ -1218,11 +1387,26 @@ int farq_blocks_per_cu(int qpl) {
 
 hipError_t launch_far_tree(const PathTree& tr, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                            const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
-                           double eps2, hipStream_t st) {
+                           double eps2, hipStream_t st, bool skip_ordered) {
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_far_tree, dim3((unsigned)grid), dim3(kWG), 0, st, tr, ft, pts, item_offs, item_map,
-                       item_counter, nq, out, eps2);
+                       item_counter, nq, out, eps2, skip_ordered ? 1 : 0);
     return hipGetLastError();
+}
+
+hipError_t launch_far_wtree(const PathTree& tr, const FaceTab& ft, const Points& pts, const uint32_t* perm,
+                            const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
+                            NearQueue nq, Out out, double eps2, hipStream_t st) {
+    if (grid <= 0 || !perm) return grid <= 0 ? hipSuccess : hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_far_wtree<kWtreeQPL>, dim3((unsigned)grid), dim3(kWG), 0, st, tr, ft, pts, perm, item_offs,
+                       item_map, item_counter, nq, out, eps2);
+    return hipGetLastError();
+}
+
+int far_wtree_blocks_per_cu() {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_far_wtree<kWtreeQPL>, kWG, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 int far_tree_blocks_per_cu() {

@@ -385,9 +385,6 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
 // its own window, in the same order.  One workgroup per face; faces with more
 // than kOrderMaxPoints points get the identity.
 constexpr int kOrderSide = 16, kOrderBins = kOrderSide * kOrderSide;
-// Faces with more points keep the caller's order (one workgroup would take
-// too long over them; large faces already fill several waves per copy).
-constexpr int64_t kOrderMaxPoints = 65536;
 static_assert(kOrderBins == kWG, "one bin per thread");
 
 __device__ __forceinline__ uint32_t morton8(uint32_t x, uint32_t y) {

@@ -125,6 +125,54 @@ def test_path_hierarchy_long_path(torch_cuda, oracle_lib):
         assert st["compared"] > 0.99 * q.num_points
 
 
+def test_path_hierarchy_mixed_face_sizes(torch_cuda, oracle_lib):
+    """One query over faces on both sides of the spatial-order limit (65,536
+    points): the wave walk takes the small faces, the per-lane walk the large
+    one, with host offsets (the per-lane pass only when needed) and without
+    (both passes always run).  Oracle parity and the flat pass's labels and
+    near pairs."""
+    import torch
+
+    big_face = W.config1_faces(nseg=256)
+    f2, q2 = W.config2(face_ids=range(3))
+    big_pts = W.config1_queries(n=70000)
+    loops = []
+    for F in (big_face, f2):
+        for f in range(F.num_faces):
+            fl = []
+            for l in range(F.face_loop_offsets[f], F.face_loop_offsets[f + 1]):
+                segs = []
+                for s_ in range(F.loop_seg_offsets[l], F.loop_seg_offsets[l + 1]):
+                    a, b = F.seg_cp_offsets[s_], F.seg_cp_offsets[s_ + 1]
+                    cp = np.column_stack([F.cp_u[a:b], F.cp_v[a:b]])
+                    segs.append((cp, None if F.cp_w is None else F.cp_w[a:b]))
+                fl.append(segs)
+            loops.append(fl)
+    faces = W.faces_from_loops(loops)
+    pts = [np.column_stack([big_pts.u, big_pts.v])]
+    for f in range(3):
+        a, b = q2.face_point_offsets[f], q2.face_point_offsets[f + 1]
+        pts.append(np.column_stack([q2.u[a:b], q2.v[a:b]]))
+    q = W.queries_for_faces(pts)
+    w_o, n_o = oracle_lib.query_faces(faces, q)
+    w0, lab0 = run_wn(faces, q, schedule=1)
+    s0 = torch.zeros(8, dtype=torch.int64, device="cuda")
+    run_wn(faces, q, schedule=1, stats=s0)
+    for host in (True, False):
+        for tree in (1, 2):
+            print(f"mixed face sizes: host offsets {host}, path_hierarchy {tree}", flush=True)
+            w, lab = run_wn(faces, q, schedule=1, path_hierarchy=tree, offsets_host=host)
+            st = compare(w, lab, w_o, n_o)
+            assert st["compared"] > 0.99 * q.num_points
+            far = n_o == 0
+            assert np.array_equal(lab[far], lab0[far])
+            ok = far & np.isfinite(w0)
+            assert np.max(np.abs(w[ok] - w0[ok])) <= 1e-12
+        s1 = torch.zeros(8, dtype=torch.int64, device="cuda")
+        run_wn(faces, q, schedule=1, stats=s1, path_hierarchy=1, offsets_host=host)
+        assert s0.cpu().tolist()[:6] == s1.cpu().tolist()[:6]
+
+
 def test_interleaved_points_and_device_offsets(torch_cuda, c2_small):
     f, q, w_o, n_o = c2_small
     w, lab = run_wn(f, q, schedule=0, stride=2, offsets_host=False)
