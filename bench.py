@@ -10,12 +10,12 @@ Prints one JSON line (rank 0).  `value` is point x segment pair evaluations
 per second of the batched schedule; the plain schedule (one launch per face,
 in-line recursion) is reported beside it, together with queries/s, the
 CPU oracle's throughput on a bounded sample (and single-threaded on config
-1), and per-kernel roofline positions.  `roofline` is the dominant kernel
-of the path with every kernel alone on the GPU (steps whose far and near
-passes run in series): algorithmic flops per launch over its HIP-event
+1), and per-kernel roofline positions.  The timed steps run the far and
+near passes in series (the library's default); `roofline` is the dominant
+kernel of those steps: algorithmic flops per launch over its HIP-event
 launch duration on the stream it runs on, against the FP64 VALU peak, and
-its measured HBM bytes per launch against 8 TB/s.  The same kernels'
-launches inside the overlapped timed steps are under rooflines_overlapped.
+its measured HBM bytes per launch against 8 TB/s.  The overlapped form
+(WN_FLAG_OVERLAP) is timed beside it for reference (rooflines_overlapped).
 """
 from __future__ import annotations
 
@@ -442,9 +442,10 @@ def main():
     ap.add_argument("--serial-steps", type=int, default=10,
                     help="timed steps with the far and near passes in series (each kernel alone on the GPU): "
                          "the per-kernel rooflines")
-    ap.add_argument("--overlap", type=int, default=1,
-                    help="1: the timed steps overlap near and far passes of different face runs (default); "
-                         "0: the timed steps run the passes in series (profiling the kernels alone)")
+    ap.add_argument("--overlap", type=int, default=0,
+                    help="0: the timed steps run the far and near passes in series (default, the faster form); "
+                         "1: the face set is created with WN_FLAG_OVERLAP and the timed steps overlap near and far "
+                         "passes of different face runs")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed batched steps and the work counters (profiling runs)")
     ap.add_argument("--sections", default="", help="comma list of the extra sections to run (default: all)")
@@ -490,13 +491,13 @@ def main():
     offs = torch.from_numpy(q.face_point_offsets).to(dev)
     out_w = torch.empty(N, dtype=torch.float64, device=dev)
     out_l = torch.empty(N, dtype=torch.uint8, device=dev)
-    fs = wn.FaceSet(faces)
+    fs = wn.FaceSet(faces, flags=wn.FLAG_OVERLAP if args.overlap else 0)
     stream = torch.cuda.current_stream()
     prof = wn.Profile(capacity=16 * (args.steps + args.warmup) + 64)
 
-    # host offsets let the library overlap the near passes of early face runs
-    # with the far pass of later ones; without them the passes run in series
-    offs_overlap = q.face_point_offsets if args.overlap else None
+    # host offsets: with WN_FLAG_OVERLAP they let the library overlap the near
+    # passes of early face runs with the far pass of later ones
+    offs_overlap = q.face_point_offsets
 
     def step(schedule, profile=None):
         fs.query(u, v, offs, offs_overlap, out_w, out_l, schedule=schedule, queries_per_wg=args.qpw,
@@ -529,6 +530,21 @@ def main():
     log(f"batched: {ms_step:.3f} ms/step, {value:.3e} evals/s; kernels {kern}")
     w_b = out_w.cpu().numpy()
     lab_b = out_l.cpu().numpy()
+
+    # the overlapped form for reference (a handle with WN_FLAG_OVERLAP)
+    ms_ovl_ref = None
+    if not args.overlap and not args.headline_only and args.serial_steps > 0:
+        fs_ovl = wn.FaceSet(faces, flags=wn.FLAG_OVERLAP)
+        fs_ovl.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, stream=stream)
+        torch.cuda.synchronize()
+        to1 = time.perf_counter()
+        for _ in range(args.serial_steps):
+            fs_ovl.query(u, v, offs, q.face_point_offsets, out_w, out_l, schedule=args.schedule, stream=stream)
+        torch.cuda.synchronize()
+        ms_ovl_ref = (time.perf_counter() - to1) * 1e3 / args.serial_steps
+        ovl_same = bool(np.array_equal(out_l.cpu().numpy(), lab_b))
+        del fs_ovl
+        log(f"overlapped far/near passes (reference): {ms_ovl_ref:.3f} ms/step; labels equal: {ovl_same}")
 
     # the same steps without the far/near overlap (no host offsets: the passes
     # run one after the other), for rooflines of each kernel on its own
@@ -715,8 +731,8 @@ def main():
     if rooflines_serial:
         dom = max(rooflines_serial, key=lambda k: rooflines_serial[k]["ms_per_step"])
         roofline = dict(rooflines_serial[dom], kernel=dom)
-        roofline["note"] = ("kernel alone on the GPU (far and near passes in series); its launches in the "
-                            "overlapped timed steps are under rooflines_overlapped")
+        roofline["note"] = ("kernel alone on the GPU (far and near passes in series, the default and faster "
+                            "form); the overlapped form's step time is under rooflines_overlapped")
         # measured counterpart of the HBM peak (context; the fractions use the published peak)
         roofline["measured_copy_GBps"] = measured_copy_rate(torch) / 1e9
 
@@ -817,7 +833,8 @@ def main():
         "work": st,
         "roofline": roofline,
         "rooflines_serial": {"ms_per_step": ms_serial, "kernels": rooflines_serial},
-        "rooflines_overlapped": {"ms_per_step": ms_step if args.overlap else None, "kernels": rooflines_overlapped},
+        "rooflines_overlapped": {"ms_per_step": ms_step if args.overlap else ms_ovl_ref,
+                                 "kernels": rooflines_overlapped},
         "cpu_baseline": cpu,
         "configs": sections,
     }

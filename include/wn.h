@@ -27,9 +27,10 @@
  *  - A wn_faces handle is immutable after creation: concurrent wn_query calls
  *    on different streams with the same handle are safe.  Each call allocates
  *    its own stream-ordered scratch memory.
- *  - Given host offsets (face_point_offsets_host), the batched FP64 schedule
- *    runs near passes of early face runs on a second stream that the handle
- *    owns (default priority), forked from `stream` and joined back to it
+ *  - With WN_FLAG_OVERLAP and host offsets (face_point_offsets_host), the
+ *    batched FP64 schedule runs near passes of early face runs on a second
+ *    stream that the handle owns (default priority), forked from `stream` and
+ *    joined back to it
  *    before the call's work on `stream` ends, so ordering on `stream` holds as
  *    for any other call.  Concurrent calls on one handle share that stream:
  *    their side passes then run one after another, with the same results.
@@ -134,7 +135,14 @@ enum {
      * pairing rule, App. C; kept for comparison).  By default the pairing
      * runs on the GPU, one wave per torus face (faces with more than 64
      * loops in B always pair on the host). */
-    WN_FLAG_HOST_PAIRING = 1
+    WN_FLAG_HOST_PAIRING = 1,
+    /* Let batched FP64 queries given host offsets run the near passes of
+     * early face runs on a second stream beside the far pass of later runs
+     * (see the conventions above).  Off by default: with the far pass's
+     * queue appends batched, the far and near passes take about equal time
+     * and both are instruction-bound, and the overlapped passes measured
+     * slower than the passes in series on every workload here. */
+    WN_FLAG_OVERLAP = 2
 };
 
 /* Query points, grouped by face: the points of face f are

@@ -128,7 +128,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     if (opt.precision < 0 || opt.precision > WN_PREC_MIXED) return WN_E_INVALID;
     if (opt.rule < 0 || opt.rule > WN_RULE_POSITIVE) return WN_E_INVALID;
     if (opt.schedule < 0 || opt.schedule > WN_SCHED_BINNED) return WN_E_INVALID;
-    if (opt.flags & ~(int32_t)WN_FLAG_HOST_PAIRING) return WN_E_INVALID;
+    if (opt.flags & ~(int32_t)(WN_FLAG_HOST_PAIRING | WN_FLAG_OVERLAP)) return WN_E_INVALID;
     const int32_t F = d->num_faces, L = d->num_loops, S = d->num_segments;
     if (F < 0 || L < 0 || S < 0) return WN_E_INVALID;
     if (!d->face_loop_offsets || !d->loop_seg_offsets || !d->seg_cp_offsets) return WN_E_INVALID;
@@ -632,7 +632,7 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
         h->pt.face = (const PFace*)(base + o_pface);
     }
     // side stream of the overlapped passes (none: no overlap)
-    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+    if ((opt.flags & WN_FLAG_OVERLAP) && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
         h->side = nullptr;
         (void)hipGetLastError();
     }

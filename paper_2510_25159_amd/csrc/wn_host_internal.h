@@ -36,7 +36,7 @@ struct wn_faces {
     std::vector<wn::PUnit> h_units;   // periodic units (torus pairs included) on the host
     std::vector<wn::PFace> h_pface;   // [F] periodic face records on the host (planar: zero)
     // side stream of the overlapped far/near passes (default priority); null
-    // when it could not be created
+    // without WN_FLAG_OVERLAP or when it could not be created
     hipStream_t side = nullptr;
 };
 

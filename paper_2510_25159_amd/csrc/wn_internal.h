@@ -18,7 +18,15 @@ constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kNearSlots = 4;       // LDS ring slots per lane for deferred intervals (two end points each)
 constexpr int kDepthCap = 52;       // dyadic parameters a + 2^-k stay exact in FP64
 constexpr int kSegChunk = kWG;      // segments staged in LDS per chunk
-constexpr int kNearBuf = 256;       // per-wave LDS buffer of near pairs before one queue append
+// Per-wave LDS buffers of near pairs before one queue append (one atomic on
+// the queue's count).  Appends to that single counter from every wave of the
+// GPU contend: with 256-entry buffers the far pass of the batched planar set
+// (154.5M near pairs) spent about half its time on them, so the planar far
+// passes take larger buffers as far as their LDS budgets allow.
+constexpr int kNearBuf = 256;    // periodic far pass (its entries carry a shift too)
+constexpr int kNearBufQ = 1024;  // k_farq (four queries per lane)
+constexpr int kNearBufT = 480;   // k_far (queued), k_far_tree, k_far_wtree (4 workgroups of the
+                                 // hierarchy passes, 24 KB of nodes each, fit in 160 KB of LDS)
 constexpr int kRefillMin = 16;      // near pass: idle lanes of a wave before they take new pairs
 constexpr float kMixedMargin = 0x1p-20f; // precision MIXED: relative FP32 admission margin
 // Relative inflation of the ellipse axis: the far decision is taken only when

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
     __shared__ double4 s_stack[INLINE ? kWavesPerWG * kNearSlots * kWave : 1];
     __shared__ double s_ang[kWavesPerWG][kWave];
     __shared__ int s_flag[kWavesPerWG][kWave];
-    __shared__ uint2 s_nbuf[INLINE ? 1 : kWavesPerWG][INLINE ? 1 : kNearBuf];
+    __shared__ uint2 s_nbuf[INLINE ? 1 : kWavesPerWG][INLINE ? 1 : kNearBufT];
     __shared__ int s_item;
 
     const int tid = threadIdx.x;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                         auto append = [&](uint64_t m, int j) {
                             if (m) {
                                 const int cntm = __popcll(m);
-                                if (nfill + cntm > kNearBuf) {
+                                if (nfill + cntm > kNearBufT) {
                                     lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
                                     nfill = 0;
                                 }
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
                             const uint64_t m = __builtin_amdgcn_ballot_w64(need);
                             if (m) {
                                 const int cntm = __popcll(m);
-                                if (nfill + cntm > kNearBuf) {
+                                if (nfill + cntm > kNearBufT) {
                                     lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
                                     nfill = 0;
                                 }
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
     constexpr int kQPWG2 = kWave * QPL * kWavesPerWG;  // queries per work item
     __shared__ double s_p0x[kSegChunk], s_p0y[kSegChunk], s_pnx[kSegChunk], s_pny[kSegChunk], s_hb2[kSegChunk];
     __shared__ uint8_t s_join[kSegChunk];
-    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
+    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBufQ];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
                             int cnt = 0;
 #pragma unroll
                             for (int q = 0; q < kQPL; ++q) cnt += __popcll(nm[q]);
-                            if (nfill + cnt > kNearBuf) {
+                            if (nfill + cnt > kNearBufQ) {
                                 flush_near_q<kQPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
                                 nfill = 0;
                             }
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
                                                   const int2* item_map, uint32_t* item_counter, NearQueue nq,
                                                   Out out, double eps2, int skip_ordered) {
     __shared__ TNode s_node[kTreeChunk];  // the current chunk of whole chains
-    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
+    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBufT];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -673,7 +673,7 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
             const uint64_t m = __ballot(need);
             if (m) {
                 const int cntm = __popcll(m);
-                if (nfill + cntm > kNearBuf) {
+                if (nfill + cntm > kNearBufT) {
                     lost |= flush_near(s_nbuf[wave], nfill, nq, lane, qi) ? 1 : 0;
                     nfill = 0;
                 }
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(kWG) void k_far_wtree(PathTree tr, FaceTab ft, Poin
                                                    uint32_t* item_counter, NearQueue nq, Out out, double eps2) {
     constexpr int kQPWG = kWave * QPL * kWavesPerWG;  // queries per work item
     __shared__ TNode s_node[kTreeChunk];                // the current chunk of whole chains
-    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBuf];
+    __shared__ uint2 s_nbuf[kWavesPerWG][kNearBufT];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(kWG) void k_far_wtree(PathTree tr, FaceTab ft, Poin
 #pragma unroll
                     for (int q = 0; q < QPL; ++q) cnt += __popcll(nm[q]);
                     if (cnt > 0) {
-                        if (nfill + cnt > kNearBuf) {
+                        if (nfill + cnt > kNearBufT) {
                             flush_near_list<QPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
                             nfill = 0;
                         }

@@ -31,7 +31,7 @@ EXPORTS = [
     "wn_classify_grid", "wn_classify_surfaces", "wn_create_faces_nurbs", "wn_near_pairs",
     "wn_query_noalloc", "wn_query_noalloc_scratch_bytes", "wn_torus_pairs", "wn_predictor_predict_mfma",
 ]
-FLAG_HOST_PAIRING = 1
+FLAG_HOST_PAIRING, FLAG_OVERLAP = 1, 2
 NOALLOC_MAX_POINTS, NOALLOC_MAX_FACES = 1 << 22, 1 << 18
 MLP_IN, MLP_HIDDEN = 16, 64
 MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1

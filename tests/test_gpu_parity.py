@@ -365,13 +365,16 @@ def test_nurbs_faces(torch_cuda, oracle_lib):
 
 @pytest.mark.parametrize("qpw", [512, 1024])
 def test_overlapped_far_near_match_serial(torch_cuda, c2_small, qpw):
-    """With host offsets the batched FP64 query overlaps near passes of early
-    face runs with the far pass of later ones (a side stream); without them it
-    runs the passes one after the other.  Same labels, omega within rounding
-    of the order of the near pass's additions, and both match the oracle."""
+    """With WN_FLAG_OVERLAP and host offsets the batched FP64 query overlaps
+    near passes of early face runs with the far pass of later ones (a side
+    stream); by default it runs the passes one after the other.  Same labels,
+    omega within rounding of the order of the near pass's additions, and both
+    match the oracle."""
+    from paper_2510_25159_amd import wn
+
     f, q, w_o, n_o = c2_small
-    w1, l1 = run_wn(f, q, schedule=1, queries_per_wg=qpw)  # host offsets: overlapped
-    w2, l2 = run_wn(f, q, schedule=1, queries_per_wg=qpw, offsets_host=False)  # serial
+    w1, l1 = run_wn(f, q, schedule=1, queries_per_wg=qpw, create={"flags": wn.FLAG_OVERLAP})  # overlapped
+    w2, l2 = run_wn(f, q, schedule=1, queries_per_wg=qpw)  # serial
     assert np.array_equal(l1, l2)
     ok = l1 < 2
     assert np.max(np.abs(w1[ok] - w2[ok])) <= 1e-12
@@ -392,8 +395,10 @@ def test_overlapped_with_auto_hierarchy(torch_cuda, oracle_lib):
     rng = np.random.default_rng(21)
     q = W.queries_for_faces([rng.uniform(-1.5, 1.5, (n, 2)) for n in (3000, 5000, 2500, 4000, 1500)])
     w_o, n_o = oracle_lib.query_faces(faces, q)
-    w1, l1 = run_wn(faces, q, schedule=1, queries_per_wg=1024, path_hierarchy=2)
-    w2, l2 = run_wn(faces, q, schedule=1, queries_per_wg=1024, path_hierarchy=2, offsets_host=False)
+    from paper_2510_25159_amd import wn
+
+    w1, l1 = run_wn(faces, q, schedule=1, queries_per_wg=1024, path_hierarchy=2, create={"flags": wn.FLAG_OVERLAP})
+    w2, l2 = run_wn(faces, q, schedule=1, queries_per_wg=1024, path_hierarchy=2)
     assert np.array_equal(l1, l2)
     ok = l1 < 2
     assert np.max(np.abs(w1[ok] - w2[ok])) <= 1e-12
@@ -411,7 +416,7 @@ def test_concurrent_queries_share_a_handle(torch_cuda, c2_small):
 
     torch = torch_cuda
     f, q, _, _ = c2_small
-    fs = wn.FaceSet(f)
+    fs = wn.FaceSet(f, flags=wn.FLAG_OVERLAP)
     dev = torch.device("cuda:0")
     u = torch.from_numpy(q.u).to(dev)
     v = torch.from_numpy(q.v).to(dev)
