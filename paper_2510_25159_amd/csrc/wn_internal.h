@@ -24,7 +24,7 @@ constexpr int kSegChunk = kWG;      // segments staged in LDS per chunk
 // (154.5M near pairs) spent about half its time on them, so the planar far
 // passes take larger buffers as far as their LDS budgets allow.
 constexpr int kNearBuf = 256;    // periodic far pass (its entries carry a shift too)
-constexpr int kNearBufQ = 1024;  // k_farq (four queries per lane)
+constexpr int kNearBufQ = 896;   // k_farq (four queries per lane; four workgroups fit in LDS)
 constexpr int kNearBufT = 480;   // k_far (queued), k_far_tree, k_far_wtree (4 workgroups of the
                                  // hierarchy passes, 24 KB of nodes each, fit in 160 KB of LDS)
 constexpr int kRefillMin = 16;      // near pass: idle lanes of a wave before they take new pairs

@@ -393,11 +393,25 @@ __global__ __launch_bounds__(kWG) void k_far(Segs sg, FaceTab ft, Points pts, co
 // masks (SGPRs) and the orientation of a pair is only computed when some
 // lane's chord changes side of the ray's line.
 // ---------------------------------------------------------------------------
-// flush_near for QPL queries per lane: lost[q] |= 1 when a pair of query
-// qi[q] did not fit in the queue.
+// flush_near for QPL queries per lane (query q of the lane: qi0 + q kWave):
+// bit q of lost is set when a pair of query q did not fit in the queue.
+// Coordinates given to the inactive and invalid queries of the far passes
+// that carry no validity masks (far beyond kCoordLimit, so that their
+// squared distances overflow to +inf: outside every ellipse, within eps of no
+// end point, crossing no chord).
+constexpr double kAway = 1e300;
+
+// A wave-uniform double held in scalar registers (lane 0's value).
+__device__ __forceinline__ double uniform_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <int QPL>
-__device__ __forceinline__ void flush_near_q(const uint2* buf, int nfill, const NearQueue& nq, int lane,
-                                             const int64_t (&qi)[QPL], int (&lost)[QPL]) {
+__device__ __forceinline__ void flush_near_q(const uint2* buf, int nfill, const NearQueue& nq, int lane, int64_t qi0,
+                                             int& lost) {
     if (nfill == 0) return;
     __builtin_amdgcn_wave_barrier();
     unsigned long long base = 0;
@@ -410,13 +424,15 @@ __device__ __forceinline__ void flush_near_q(const uint2* buf, int nfill, const 
             if (base + (unsigned long long)e < nq.cap) continue;
             const int64_t x = (int64_t)buf[e].x;
 #pragma unroll
-            for (int q = 0; q < QPL; ++q) lost[q] |= x == qi[q] ? 1 : 0;
+            for (int q = 0; q < QPL; ++q) lost |= x == qi0 + (int64_t)q * kWave ? 1 << q : 0;
         }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-// occupancy target of k_farq: the register budget that keeps it
+// occupancy target of k_farq: the register budget that keeps it (four
+// queries per lane: 128 VGPRs, with two spilled, for 4 waves per SIMD; the
+// near-pair buffers are sized so that four workgroups fit in LDS)
 template <int QPL>
 struct FarqWaves;
 template <>
@@ -429,7 +445,7 @@ struct FarqWaves<3> {
 };
 template <>
 struct FarqWaves<4> {
-    static constexpr int w = 3;
+    static constexpr int w = 4;
 };
 
 template <int QPL>
@@ -464,29 +480,29 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
         int64_t qb = pts.offs[f], qe = pts.offs[f + 1];
         qb = qb < 0 ? 0 : (qb > pts.n ? pts.n : qb);
         qe = qe < qb ? qb : (qe > pts.n ? pts.n : qe);
-        int64_t qi[kQPL];
-        bool active[kQPL], valid[kQPL];
+        // query q of this lane: qi0 + q kWave
+        const int64_t qi0 = qb + (int64_t)tile * kQPWG2 + (int64_t)wave * kQPL * kWave + lane;
         double qx[kQPL], qy[kQPL];
         Turn T[kQPL];
-        int xc[kQPL], lost[kQPL];
-        uint64_t vm[kQPL], em[kQPL], am[kQPL];  // valid lanes, eps hits, chain end below the ray's line
-        double csx[kQPL], csy[kQPL], pbx[kQPL], pby[kQPL], prb[kQPL];
+        int xc[kQPL];
+        int lost = 0;                    // bit q: a near pair of query q did not fit in the queue
+        uint64_t em[kQPL], am[kQPL];     // eps hits, chain end below the ray's line
+        double pbx[kQPL], pby[kQPL], prb[kQPL];
+        double chx = 0.0, chy = 0.0;     // the open chain's start point (wave-uniform)
 #pragma unroll
         for (int q = 0; q < kQPL; ++q) {
-            qi[q] = qb + (int64_t)tile * kQPWG2 + (wave * kQPL + q) * kWave + lane;
-            active[q] = qi[q] < qe;
+            const int64_t qi = qi0 + (int64_t)q * kWave;
             qx[q] = qy[q] = 0.0;
-            if (active[q]) {
-                qx[q] = pts.u[qi[q] * pts.stride];
-                qy[q] = pts.v[qi[q] * pts.stride];
+            if (qi < qe) {
+                qx[q] = pts.u[qi * pts.stride];
+                qy[q] = pts.v[qi * pts.stride];
             }
-            valid[q] = active[q] && fabs(qx[q]) < kCoordLimit && fabs(qy[q]) < kCoordLimit;
-            if (!valid[q]) qx[q] = qy[q] = 0.0;
-            vm[q] = __builtin_amdgcn_ballot_w64(valid[q]);
+            // an inactive or invalid query sits at (kAway, kAway): no mask needed
+            if (!(qi < qe && fabs(qx[q]) < kCoordLimit && fabs(qy[q]) < kCoordLimit)) qx[q] = qy[q] = kAway;
             T[q] = Turn{1.0, 0.0, 0};
-            xc[q] = lost[q] = 0;
+            xc[q] = 0;
             em[q] = am[q] = 0;
-            csx[q] = csy[q] = pbx[q] = pby[q] = prb[q] = 0.0;
+            pbx[q] = pby[q] = prb[q] = 0.0;
         }
         const int s0 = ft.seg_begin[f], s1 = ft.seg_begin[f + 1];
         int nfill = 0;      // entries in this wave's near-pair buffer (wave-uniform)
@@ -511,15 +527,17 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
                 while (jj < jn) {
                     if (!(open & ((jm >> jj) & 1ull))) {  // a chain starts at segment j0 + jj
 #pragma unroll
+                        for (int q = 0; q < kQPL; ++q)
+                            if (open) close_chain(T[q], xc[q], chx - qx[q], chy - qy[q], pbx[q], pby[q]);
+                        chx = uniform_f64(s_p0x[j0 + jj]);
+                        chy = uniform_f64(s_p0y[j0 + jj]);
+#pragma unroll
                         for (int q = 0; q < kQPL; ++q) {
-                            if (open) close_chain(T[q], xc[q], csx[q], csy[q], pbx[q], pby[q]);
-                            pbx[q] = s_p0x[j0 + jj] - qx[q];
-                            pby[q] = s_p0y[j0 + jj] - qy[q];
+                            pbx[q] = chx - qx[q];
+                            pby[q] = chy - qy[q];
                             prb[q] = pbx[q] * pbx[q] + pby[q] * pby[q];
                             em[q] |= __builtin_amdgcn_fcmp(prb[q], eps2, kCmpOLT);
                             am[q] = low_mask(pby[q]);
-                            csx[q] = pbx[q];
-                            csy[q] = pby[q];
                         }
                         open = true;
                     }
@@ -535,7 +553,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
                             em[q] |= __builtin_amdgcn_fcmp(rb, eps2, kCmpOLT);
                             const uint64_t bm = low_mask(by);
                             ray_cross_mask(xc[q], am[q], bm, pbx[q], pby[q], bx, by);
-                            nm[q] = near_mask(prb[q], rb, hb) & vm[q];
+                            nm[q] = near_mask(prb[q], rb, hb);
                             pbx[q] = bx;
                             pby[q] = by;
                             prb[q] = rb;
@@ -549,14 +567,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
 #pragma unroll
                             for (int q = 0; q < kQPL; ++q) cnt += __popcll(nm[q]);
                             if (nfill + cnt > kNearBufQ) {
-                                flush_near_q<kQPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
+                                flush_near_q<kQPL>(s_nbuf[wave], nfill, nq, lane, qi0, lost);
                                 nfill = 0;
                             }
                             const uint32_t seg = (uint32_t)(c0 + j);
 #pragma unroll
                             for (int q = 0; q < kQPL; ++q) {
                                 if (__builtin_amdgcn_inverse_ballot_w64(nm[q]))
-                                    s_nbuf[wave][nfill + lanes_below(nm[q])] = make_uint2((uint32_t)qi[q], seg);
+                                    s_nbuf[wave][nfill + lanes_below(nm[q])] =
+                                        make_uint2((uint32_t)(qi0 + (int64_t)q * kWave), seg);
                                 nfill += __popcll(nm[q]);
                             }
                         }
@@ -573,14 +592,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FarqWaves<Q
                 }
             }
         }
-        flush_near_q<kQPL>(s_nbuf[wave], nfill, nq, lane, qi, lost);
+        flush_near_q<kQPL>(s_nbuf[wave], nfill, nq, lane, qi0, lost);
 #pragma unroll
         for (int q = 0; q < kQPL; ++q) {
-            if (open) close_chain(T[q], xc[q], csx[q], csy[q], pbx[q], pby[q]);
-            const bool onb = valid[q] & __builtin_amdgcn_inverse_ballot_w64(em[q]);
-            if (active[q]) {
-                out.w[qi[q]] = turn_angle(T[q]) + kTwoPi * (double)xc[q];
-                out.lab[qi[q]] = !valid[q] ? 3 : (onb ? 2 : (lost[q] ? kRedo : 0));
+            if (open) close_chain(T[q], xc[q], chx - qx[q], chy - qy[q], pbx[q], pby[q]);
+            const int64_t qi = qi0 + (int64_t)q * kWave;
+            const bool valid = qx[q] != kAway;
+            const bool onb = valid & __builtin_amdgcn_inverse_ballot_w64(em[q]);
+            if (qi < qe) {
+                out.w[qi] = turn_angle(T[q]) + kTwoPi * (double)xc[q];
+                out.lab[qi] = !valid ? 3 : (onb ? 2 : (((lost >> q) & 1) ? kRedo : 0));
             }
         }
     }
@@ -706,10 +727,6 @@ __global__ __launch_bounds__(kWG) void k_far_tree(PathTree tr, FaceTab ft, Point
 // ellipse); only the reads and the control flow are shared.  Faces whose
 // points keep the caller's order (more than kOrderMaxPoints) are skipped.
 // ---------------------------------------------------------------------------
-// Coordinates given to the inactive and invalid queries of k_far_wtree (far
-// beyond kCoordLimit, so that their squared distances overflow).
-constexpr double kAway = 1e300;
-
 // flush_near for queries of arbitrary indices: bit q of lost is set when a
 // pair of query qi[q] did not fit in the queue.
 template <int QPL>
