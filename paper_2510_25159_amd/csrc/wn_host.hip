@@ -1119,17 +1119,19 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
         // With a spatial order of the points (the query's scratch holds one),
         // faces of at most kOrderMaxPoints points take the walk shared by the
         // wave's spatially neighbouring queries, and the per-lane walk takes
-        // the faces whose points keep the caller's order; it only runs when
-        // such a face may exist (always without host offsets).
-        const bool wave_walk = sc.perm != nullptr;
+        // the faces whose points keep the caller's order.  Each walk only runs
+        // when a face of its kind may exist (both without host offsets).
+        bool wave_walk = sc.perm != nullptr;
         bool big = true;
         if (wave_walk && counts_host) {
+            bool small = false;
             big = false;
-            for (const int32_t f : tree == 2 ? h->h_ord_tree : h->h_ord_plan)
-                if (counts_host[f + 1] - counts_host[f] > kOrderMaxPoints) {
-                    big = true;
-                    break;
-                }
+            for (const int32_t f : tree == 2 ? h->h_ord_tree : h->h_ord_plan) {
+                const int64_t nf = counts_host[f + 1] - counts_host[f];
+                big |= nf > kOrderMaxPoints;
+                small |= nf > 0 && nf <= kOrderMaxPoints;
+            }
+            wave_walk = small;
         }
         if (wave_walk) {
             {
