@@ -287,7 +287,8 @@ wn_status wn_query_ex(const wn_faces* faces, const wn_points* points, double* ou
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, hosts that forbid hipMalloc): wn_query_ex
  * with the batched schedule, whose scratch (work items, counters, near queue,
- * spatial order of periodic points) lives in a fixed device array of
+ * spatial order of the points of periodic faces and, with path_hierarchy, of
+ * planar faces) lives in a fixed device array of
  * wn_query_noalloc_scratch_bytes() bytes (64 MiB) that the library holds on
  * each device it runs on until the process ends.  No allocation of any kind
  * is made.  The near queue gets whatever the array has left; pairs that do

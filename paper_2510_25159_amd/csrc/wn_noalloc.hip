@@ -1,5 +1,6 @@
 // A batched query that allocates nothing: its scratch (work items, counters,
-// near queue, spatial order of periodic points) lives in one file-scope
+// near queue, spatial order of the points of periodic faces and of the faces
+// the path hierarchy walks) lives in one file-scope
 // device array of kNoAllocScratchBytes, laid out afresh by every call.
 //
 // The array's name is a host-side stand-in in host code, not a device
@@ -67,6 +68,7 @@ wn_status wn_query_noalloc(const wn_faces* h, const wn_points* p, double* out_w,
     if (N == 0) return WN_OK;
     const int32_t F = h->num_faces;
     const bool periodic = h->num_periodic > 0;
+    const bool ordered = periodic || q.path_hierarchy != 0;
     // layout: item offsets, item map, counters, spatial order, then the near
     // queue (entries, and their copy shifts for periodic face sets) in the rest
     Scratch sc;
@@ -75,7 +77,7 @@ wn_status wn_query_noalloc(const wn_faces* h, const wn_points* p, double* out_w,
     const size_t o_im = o_io + align256(((size_t)F + 1) * 4);
     const size_t o_ct = o_im + align256((size_t)sc.max_items * 8);
     const size_t o_pm = o_ct + 256;
-    const size_t o_nq = o_pm + (periodic ? align256((size_t)N * 4) : 0);
+    const size_t o_nq = o_pm + (ordered ? align256((size_t)N * 4) : 0);
     if (o_nq >= kNoAllocScratchBytes) return WN_E_INVALID;
     const size_t per_entry = periodic ? 8 + 16 : 8;
     int64_t cap = (int64_t)((kNoAllocScratchBytes - o_nq - 256) / per_entry);
@@ -90,7 +92,7 @@ wn_status wn_query_noalloc(const wn_faces* h, const wn_points* p, double* out_w,
     sc.item_offs = (int32_t*)(b + o_io);
     sc.item_map = (int2*)(b + o_im);
     sc.counters = (uint32_t*)(b + o_ct);
-    sc.perm = periodic ? (uint32_t*)(b + o_pm) : nullptr;
+    sc.perm = ordered ? (uint32_t*)(b + o_pm) : nullptr;
     sc.nq = NearQueue{(uint2*)(b + o_nq), periodic ? (double2*)(b + o_sh) : nullptr,
                       (unsigned long long*)(sc.counters + 2), (uint64_t)cap};
     q.near_capacity = cap;

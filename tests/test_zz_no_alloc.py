@@ -1,8 +1,9 @@
 """wn_query_noalloc (the batched query on the library's fixed device scratch)
 against wn_query_ex on the same handle and points, two calls in a row with
 the second on a smaller input: labels identical, winding within 1e-12, both
-also against the oracle.  A planar set (30 % of the points near curves) and
-a periodic set (cylinders and tori: spatial order and queue shifts in the
+also against the oracle.  A planar set (30 % of the points near curves), the
+same set under the path hierarchy (its spatial order in the scratch), a
+periodic set (cylinders and tori: spatial order and queue shifts in the
 scratch), and the limits the entry point rejects."""
 import numpy as np
 import pytest
@@ -22,7 +23,7 @@ def _sub(q, keep_every):
     return W.Queries(q.u[idx].copy(), q.v[idx].copy(), offs)
 
 
-def _run_both(fs, q):
+def _run_both(fs, q, **opts):
     import torch
 
     from paper_2510_25159_amd import wn
@@ -32,10 +33,10 @@ def _run_both(fs, q):
     v = torch.from_numpy(q.v).to(dev)
     offs = torch.from_numpy(q.face_point_offsets).to(dev)
     n = q.num_points
-    w_ref, l_ref = fs.query(u, v, offs, q.face_point_offsets, schedule=wn.SCHED_BATCHED)
+    w_ref, l_ref = fs.query(u, v, offs, q.face_point_offsets, schedule=wn.SCHED_BATCHED, **opts)
     w_na = torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
     l_na = torch.full((n,), 255, dtype=torch.uint8, device=dev)
-    fs.query_noalloc(u, v, offs, w_na, l_na)
+    fs.query_noalloc(u, v, offs, w_na, l_na, **opts)
     torch.cuda.synchronize()
     return (w_ref.cpu().numpy(), l_ref.cpu().numpy(), w_na.cpu().numpy(), l_na.cpu().numpy())
 
@@ -52,7 +53,7 @@ def _check(oracle_lib, faces, q, res):
     assert st["compared"] > 0.5 * q.num_points
 
 
-@pytest.mark.parametrize("kind", ["planar", "periodic"])
+@pytest.mark.parametrize("kind", ["planar", "planar_hierarchy", "periodic"])
 def test_noalloc_matches_query_ex_twice(oracle_lib, kind):
     import torch
 
@@ -60,7 +61,8 @@ def test_noalloc_matches_query_ex_twice(oracle_lib, kind):
         pytest.skip("no GPU")
     from paper_2510_25159_amd import wn
 
-    if kind == "planar":
+    opts = {"path_hierarchy": 1} if kind == "planar_hierarchy" else {}
+    if kind.startswith("planar"):
         faces, q = W.config2(face_ids=range(24))
     else:
         faces, q = W.config3(face_ids=range(64))
@@ -68,8 +70,8 @@ def test_noalloc_matches_query_ex_twice(oracle_lib, kind):
     q_small = _sub(q, 3)
     print(f"{kind}: {faces.num_faces} faces, calls of {q.num_points} then {q_small.num_points} points", flush=True)
     assert q.num_points <= wn.NOALLOC_MAX_POINTS
-    _check(oracle_lib, faces, q, _run_both(fs, q))
-    _check(oracle_lib, faces, q_small, _run_both(fs, q_small))
+    _check(oracle_lib, faces, q, _run_both(fs, q, **opts))
+    _check(oracle_lib, faces, q_small, _run_both(fs, q_small, **opts))
 
 
 def test_noalloc_rejects_out_of_range():
