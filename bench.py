@@ -333,6 +333,18 @@ def section_config3(args):
     for name, sched in (("plain", 0), ("batched", 1)):
         ms, k = _time_query(torch, fs, tens, q.face_point_offsets, 10 if sched else 3, schedule=sched)
         out[name] = {"ms_per_step": ms, "queries_per_s": q.num_points / (ms / 1e3), "kernel_ms": k}
+    # the (query, segment copy) pairs of the copy windows, counted by the
+    # periodic far pass itself in one more (untimed) query
+    st = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device="cuda:0")
+    fs.query(*tens, q.face_point_offsets, schedule=1, stats=st)
+    torch.cuda.synchronize()
+    pairs = int(st[wn.STAT_NAMES.index("periodic_pairs")].item())
+    b = out["batched"]
+    kp = b["kernel_ms"].get("k_far_periodic", float("nan"))
+    out["pairs"] = pairs
+    b["evals_per_s"] = pairs / (b["ms_per_step"] / 1e3)
+    out["plain"]["evals_per_s"] = pairs / (out["plain"]["ms_per_step"] / 1e3)
+    b["far_periodic_roofline_frac"] = FLOPS_PER_PAIR * pairs / (kp / 1e3) / PEAK_FP64_VALU
     return out
 
 

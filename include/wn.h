@@ -245,7 +245,9 @@ enum {
     WN_STAT_MAX_DEPTH = 5,    /* deepest level reached (max, not sum)                    */
     WN_STAT_NEAR_STEPS = 6,   /* near pass: loop trips summed over its waves             */
     WN_STAT_NEAR_LANE_STEPS = 7, /* near pass: lanes holding a pair, summed over trips    */
-    WN_STATS_COUNT = 8
+    WN_STAT_PERIODIC_PAIRS = 8,  /* periodic far pass: (query, segment copy) pairs in the
+                                    copy windows of the valid queries (Sec. 4.3-4.5)      */
+    WN_STATS_COUNT = 9
 };
 
 /* Fill `opt` with the defaults listed above.  Never fails. */

@@ -869,7 +869,7 @@ wn_status query_core(const wn_faces* h, const wn_points* p, double* out_w, uint8
     const int64_t* ovl =
         (!binned && !preset && !q.stats && !cp && prec == WN_PREC_FP64) ? p->face_point_offsets_host : nullptr;
     e = far_passes(h, pts, qpw, q.queue_policy, prec == WN_PREC_MIXED, q.path_hierarchy, sc, q.profile, st, ovl,
-                   p->face_point_offsets_host);
+                   p->face_point_offsets_host, q.stats);
     NearQueue nq = sc.nq;
     if (e == hipSuccess && binned) {
         const wn_predictor* pr = q.predictor;
@@ -1080,7 +1080,8 @@ static hipError_t far_near_overlapped(const wn_faces* h, const FaceTab& ft, cons
 }
 
 hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
-                      wn_profile* prof, hipStream_t st, const int64_t* host_offs, const int64_t* counts_host) {
+                      wn_profile* prof, hipStream_t st, const int64_t* host_offs, const int64_t* counts_host,
+                      unsigned long long* stats) {
     hipError_t e = hipSuccess;
     bool zero_near = true;
     const bool persistent = policy != 2;
@@ -1176,7 +1177,7 @@ hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy,
             ProfScope ps(prof, WN_KERNEL_FAR_PERIODIC, st);
             e = launch_far_periodic(kPerQueue, h->sg, h->ft_per, pts, sc.item_offs, sc.item_map,
                                     persistent ? sc.counters : nullptr, grid, sc.nq, sc.out, h->eps2, h->pt, sc.perm,
-                                    st);
+                                    st, stats ? stats + WN_STAT_PERIODIC_PAIRS : nullptr);
         }
     }
     return e;

@@ -98,10 +98,11 @@ void scratch_free(Scratch& sc, hipStream_t st);
 // may overlap near passes on h->side and leave sc.near_lo for the final one.
 // host_offs: the host offsets when the far/near overlap may run; counts_host:
 // the host offsets whenever the caller gave them (the hierarchy reads the
-// per-face point counts from them).
+// per-face point counts from them); stats: the query's work counters
+// (WN_STAT_PERIODIC_PAIRS), or null.
 hipError_t far_passes(const wn_faces* h, const Points& pts, int qpw, int policy, bool mixed, int tree, Scratch& sc,
                       wn_profile* prof, hipStream_t st, const int64_t* host_offs = nullptr,
-                      const int64_t* counts_host = nullptr);
+                      const int64_t* counts_host = nullptr, unsigned long long* stats = nullptr);
 // Near pass over nq; entry_depth optional.
 hipError_t near_pass(const wn_faces* h, const Points& pts, NearQueue nq, Out out, unsigned long long* stats,
                      uint8_t* entry_depth, wn_profile* prof, hipStream_t st, unsigned long long* cursor,

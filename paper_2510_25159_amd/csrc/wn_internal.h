@@ -245,10 +245,13 @@ hipError_t launch_pair_torus(const Segs& sg, const PLoop* loops, const PairJob* 
                              int2* out, double eps2, hipStream_t st);
 // Periodic far pass variants: near pairs queued (overflow -> label kRedo),
 // recursed in line, or recursed in line for the kRedo-labelled queries only.
+// stat_pairs (optional): adds the (query, segment copy) pairs of the copy
+// windows of the valid queries.
 enum : int { kPerQueue = 0, kPerInline = 1, kPerRedo = 2 };
 hipError_t launch_far_periodic(int mode, const Segs& sg, const FaceTab& ft, const Points& pts,
                                const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
-                               NearQueue nq, Out out, double eps2, PerTab pt, const uint32_t* perm, hipStream_t st);
+                               NearQueue nq, Out out, double eps2, PerTab pt, const uint32_t* perm, hipStream_t st,
+                               unsigned long long* stat_pairs = nullptr);
 // Spatial order of the points of every face of ft (one workgroup per face):
 // perm[slot] = point index; perm == nullptr in launch_far_periodic = identity.
 hipError_t launch_spatial_order(const FaceTab& ft, const Points& pts, uint32_t* perm, hipStream_t st);

@@ -147,6 +147,7 @@ struct PerLane {
     int xc;     // integer parts of near pairs recursed in line (2 pi units)
     int nfill;  // entries in the wave's near-pair buffer (wave-uniform)
     int cnt;    // pairs since the start (wave-uniform)
+    uint32_t pairs;  // (segment, copy) pairs in this query's windows (work counter)
 };
 
 // Per-wave resources: near-pair staging buffers (queue variant) or the
@@ -192,6 +193,7 @@ template <int MODE>
 __device__ __forceinline__ void loop_copy(const Segs& sg, const PLoop& L, double shx, double shy, bool act,
                                           PerLane& P, const PerWave& W) {
     const double xq = P.qx - shx, yq = P.qy - shy;
+    if (act && P.valid) P.pairs += (uint32_t)(L.s1 - L.s0);
     FarRec nx = kload(sg.frec, L.s0);
     for (int s = L.s0; s < L.s1; ++s) {
         const FarRec r = nx;  // loaded one segment ahead
@@ -274,7 +276,7 @@ template <int MODE>
 __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Points pts, const int32_t* item_offs,
                                                       const int2* item_map, uint32_t* item_counter, NearQueue nq,
                                                       Out out, double eps2, PerTab pt,
-                                                      const uint32_t* perm) {
+                                                      const uint32_t* perm, unsigned long long* stat_pairs) {
     __shared__ PerShared<MODE> sh;
     if (MODE == kPerRedo && *nq.count <= nq.cap) return;  // the queue never overflowed: nothing was lost
     const int tid = threadIdx.x;
@@ -333,6 +335,7 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
         P.xc = 0;
         P.nfill = 0;
         P.cnt = 0;
+        P.pairs = 0;
         const PFace pf = kload(pt.face, f);
         for (int u = pf.u0; u < pf.u1; ++u) {
             const PUnit U = kload(pt.unit, u);
@@ -372,6 +375,12 @@ __global__ __launch_bounds__(kWG) void k_far_periodic(Segs sg, FaceTab ft, Point
         if (active) {
             out.w[P.qi] = turn_angle(P.T) + kTwoPi * ((double)P.xc + pf.offset);
             out.lab[P.qi] = !P.valid ? 3 : (P.onb ? 2 : (P.lost ? kRedo : 0));
+        }
+        if (stat_pairs) {  // work counter: one atomic per wave and item
+            unsigned long long c = active ? (unsigned long long)P.pairs : 0ull;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+            if (lane == 0 && c) atomicAdd(stat_pairs, c);
         }
     }
 }
@@ -476,26 +485,28 @@ hipError_t launch_spatial_order(const FaceTab& ft, const Points& pts, uint32_t* 
 template <int MODE>
 static hipError_t launch_per(const Segs& sg, const FaceTab& ft, const Points& pts, const int32_t* item_offs,
                              const int2* item_map, uint32_t* item_counter, int64_t grid, NearQueue nq, Out out,
-                             double eps2, PerTab pt, const uint32_t* perm, hipStream_t st) {
+                             double eps2, PerTab pt, const uint32_t* perm, hipStream_t st,
+                             unsigned long long* stat_pairs) {
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_far_periodic<MODE>, dim3((unsigned)grid), dim3(kWG), 0, st, sg, ft, pts, item_offs, item_map,
-                       item_counter, nq, out, eps2, pt, perm);
+                       item_counter, nq, out, eps2, pt, perm, stat_pairs);
     return hipGetLastError();
 }
 
 hipError_t launch_far_periodic(int mode, const Segs& sg, const FaceTab& ft, const Points& pts,
                                const int32_t* item_offs, const int2* item_map, uint32_t* item_counter, int64_t grid,
-                               NearQueue nq, Out out, double eps2, PerTab pt, const uint32_t* perm, hipStream_t st) {
+                               NearQueue nq, Out out, double eps2, PerTab pt, const uint32_t* perm, hipStream_t st,
+                               unsigned long long* stat_pairs) {
     switch (mode) {
         case kPerQueue:
             return launch_per<kPerQueue>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, perm,
-                                   st);
+                                   st, stat_pairs);
         case kPerInline:
             return launch_per<kPerInline>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, perm,
-                                   st);
+                                   st, stat_pairs);
         case kPerRedo:
             return launch_per<kPerRedo>(sg, ft, pts, item_offs, item_map, item_counter, grid, nq, out, eps2, pt, perm,
-                                   st);
+                                   st, stat_pairs);
         default:
             return hipErrorInvalidValue;
     }

@@ -42,8 +42,8 @@ KERNEL_NAMES = {0: "k_build_items", 1: "k_far", 2: "k_near", 3: "k_finalize", 4:
                 6: "k_bin"}
 KERNEL_KINDS = 8
 STAT_NAMES = ["near_pairs", "splits", "leaves", "reevals", "near_flops", "max_depth", "near_steps",
-              "near_lane_steps"]
-STATS_COUNT = 8
+              "near_lane_steps", "periodic_pairs"]
+STATS_COUNT = 9
 
 _P = ctypes.c_void_p
 

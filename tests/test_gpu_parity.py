@@ -104,7 +104,9 @@ def test_path_hierarchy(torch_cuda, c1, c2_small, policy, cap, mode):
     if cap == 0:
         import torch
 
-        stats = [torch.zeros(8, dtype=torch.int64, device="cuda") for _ in range(2)]
+        from paper_2510_25159_amd import wn
+
+        stats = [torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device="cuda") for _ in range(2)]
         f, q = c2_small[0], c2_small[1]
         run_wn(f, q, schedule=1, queue_policy=policy, stats=stats[0])
         run_wn(f, q, schedule=1, queue_policy=policy, stats=stats[1], path_hierarchy=1)
@@ -133,6 +135,8 @@ def test_path_hierarchy_mixed_face_sizes(torch_cuda, oracle_lib):
     near pairs."""
     import torch
 
+    from paper_2510_25159_amd import wn
+
     big_face = W.config1_faces(nseg=256)
     f2, q2 = W.config2(face_ids=range(3))
     big_pts = W.config1_queries(n=70000)
@@ -156,7 +160,7 @@ def test_path_hierarchy_mixed_face_sizes(torch_cuda, oracle_lib):
     q = W.queries_for_faces(pts)
     w_o, n_o = oracle_lib.query_faces(faces, q)
     w0, lab0 = run_wn(faces, q, schedule=1)
-    s0 = torch.zeros(8, dtype=torch.int64, device="cuda")
+    s0 = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device="cuda")
     run_wn(faces, q, schedule=1, stats=s0)
     for host in (True, False):
         for tree in (1, 2):
@@ -168,7 +172,7 @@ def test_path_hierarchy_mixed_face_sizes(torch_cuda, oracle_lib):
             assert np.array_equal(lab[far], lab0[far])
             ok = far & np.isfinite(w0)
             assert np.max(np.abs(w[ok] - w0[ok])) <= 1e-12
-        s1 = torch.zeros(8, dtype=torch.int64, device="cuda")
+        s1 = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device="cuda")
         run_wn(faces, q, schedule=1, stats=s1, path_hierarchy=1, offsets_host=host)
         assert s0.cpu().tolist()[:6] == s1.cpu().tolist()[:6]
 

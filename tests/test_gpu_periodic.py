@@ -234,3 +234,41 @@ def test_large_and_small_periodic_faces(torch_cuda, oracle_lib):
     for sched, pol in ((1, 0), (1, 2), (0, 0)):
         w, lab = run_wn(f, q2, schedule=sched, queue_policy=pol)
         compare(w[idx], lab[idx], w_o, n_o)
+
+
+def test_periodic_pair_counter(torch_cuda, c3_small):
+    """The periodic far pass's work counter (WN_STAT_PERIODIC_PAIRS: the
+    (query, segment copy) pairs of the valid queries' copy windows, Sec.
+    4.3-4.5): zero on a planar set; at least one copy of every segment of a
+    query's face per query (every window holds a copy); additive over a split
+    of each face's points, since each query's windows are its own; the same
+    under the binned schedule, which shares the far pass."""
+    from paper_2510_25159_amd import wn
+
+    torch = torch_cuda
+    f, q = c3_small[0], c3_small[1]
+    fs = wn.FaceSet(f)
+    idx = wn.STAT_NAMES.index("periodic_pairs")
+
+    def count(faces, qq, faceset=None, **kw):
+        st = torch.zeros(wn.STATS_COUNT, dtype=torch.int64, device="cuda")
+        run_wn(faces, qq, faceset=faceset, stats=st, **kw)
+        return int(st[idx].item())
+
+    total = count(f, q, fs, schedule=1)
+    per_face = np.diff(q.face_point_offsets)
+    print(f"periodic pairs {total} over {q.num_points} points", flush=True)
+    assert total >= int((f.face_segment_counts() * per_face).sum())
+    # each face's points split into its first and second halves
+    fid = q.face_ids()
+    rank = np.arange(q.num_points) - q.face_point_offsets[fid]
+    first = rank < per_face[fid] // 2
+    halves = []
+    for sel in (first, ~first):
+        counts = np.bincount(fid[sel], minlength=f.num_faces)
+        halves.append(W.Queries(q.u[sel].copy(), q.v[sel].copy(),
+                                np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)))
+    assert count(f, halves[0], fs, schedule=1) + count(f, halves[1], fs, schedule=1) == total
+    assert count(f, q, fs, schedule=2, bin_source=wn.BIN_HEURISTIC) == total
+    f2, q2 = W.config2(face_ids=range(2))
+    assert count(f2, q2, schedule=1) == 0
