@@ -345,7 +345,8 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
     h->bpc_near = near_blocks_per_cu();
     h->bpc_near_cp = near_cp_blocks_per_cu();
 
-    // faces ordered by segment count (largest first) for the work queues
+    // faces ordered by segment count (largest first) for the work queues (the
+    // periodic faces are ordered again by their copies once these are known)
     std::vector<int32_t> ord_plan, ord_per;
     for (int32_t f = 0; f < F; ++f) (dom[f] == WN_DOMAIN_PLANE ? ord_plan : ord_per).push_back(f);
     auto by_size = [&](int32_t a, int32_t b) {
@@ -596,6 +597,41 @@ wn_status wn_create_faces(const wn_faces_desc* d, const wn_options* opt_in, void
             }
         }
         if (units.size() > (size_t)(2 * L + 1)) return fail(WN_E_TOPOLOGY);
+        // Work-queue order of the periodic faces: most (segment, copy) pairs
+        // per query first, so that the cheap faces' items fill the end of the
+        // persistent pass.  A unit's copy windows span its extent over the
+        // period (or family spacing) plus the windows' widening by one copy on
+        // each side; the estimate only orders the faces.
+        {
+            auto ext_pairs = [&](int32_t l) {
+                const PLoop& Lp = ploop[l];
+                const double copies = Lp.lv > 0.0 ? (Lp.xi_hi - Lp.xi_lo) / Lp.lv + 3.0 : 1.0;
+                return copies * (double)(Lp.s1 - Lp.s0);
+            };
+            std::vector<double> cost((size_t)F, 0.0);
+            for (int32_t f = 0; f < F; ++f) {
+                if (dom[f] == WN_DOMAIN_PLANE) continue;
+                const PFace& pf = pface[f];
+                for (int32_t u = pf.u0; u < pf.u1; ++u) {
+                    const PUnit& U = units[u];
+                    if (U.kind == kUnitExtended) {
+                        cost[f] += ext_pairs(U.la);
+                    } else if (U.kind == kUnitContractible) {
+                        const PLoop& Lp = ploop[U.la];
+                        double c = (Lp.bb[1] - Lp.bb[0]) / pf.Tu + 3.0;
+                        if (pf.dom == WN_DOMAIN_TORUS) c *= (Lp.bb[3] - Lp.bb[2]) / pf.Tv + 3.0;
+                        cost[f] += c * (double)(Lp.s1 - Lp.s0);
+                    } else {
+                        const double fam = pf.Delta > 0.0 ? (U.eta_hi - U.eta_lo) / pf.Delta + 3.0 : 1.0;
+                        cost[f] += fam * (ext_pairs(U.la) + ext_pairs(U.lb));
+                    }
+                }
+            }
+            std::stable_sort(ord_per.begin(), ord_per.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+            for (size_t r = 0; r < ord_per.size(); ++r) h->per_pos[ord_per[r]] = (int32_t)r;
+            e = hipMemcpyAsync(base + o_oq, ord_per.data(), ord_per.size() * 4, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) return fail(hip_status(e));
+        }
         // far-test records: the lifted end points (the lift's own additions,
         // repeated with its offsets) and the final hb2
         std::vector<FarRec> frec((size_t)S);
