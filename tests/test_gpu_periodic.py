@@ -60,7 +60,8 @@ def test_closed_noise_free_bands(torch_cuda, oracle_lib):
 
 
 def test_mixed_planar_and_periodic_faces(torch_cuda, oracle_lib):
-    """Planar and periodic faces in one handle and one query."""
+    """Planar and periodic faces in one handle and one query (also under the
+    path hierarchy)."""
     fp, qp = W.config2(face_ids=[0, 1])
     fc, qc = W.config3(face_ids=[2, 3])
     loops = []
@@ -96,6 +97,11 @@ def test_mixed_planar_and_periodic_faces(torch_cuda, oracle_lib):
         compare(w, lab, w_o, n_o)
     w, lab = run_wn(faces, q, schedule=1, near_capacity=300)  # both redo kernels
     compare(w, lab, w_o, n_o)
+    # the path hierarchy's wave walk orders the planar faces' points in the
+    # same scratch array that then orders the periodic faces' points
+    for offs_host in (True, False):
+        w, lab = run_wn(faces, q, schedule=1, path_hierarchy=1, offsets_host=offs_host)
+        compare(w, lab, w_o, n_o)
 
 
 def test_topology_error_reported(torch_cuda):
